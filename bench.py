@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark: GCUPS of the fused Runge-Kutta-Merson step on one MI355X.
+
+Workload (default): the coupled heat + Allen-Cahn model in FP64 on the
+128^3 glass-bead grid (64 spheres of radius 14 voxels, ~35% solid; bottom
+face held at -5 C, T0 = +1 C; tol 1e-6 adaptive steps).  One benchmark step
+is one adaptive Merson attempt over the whole grid: five fused stage passes,
+the FP64 error-norm and diagnostic reductions and the on-device step
+controller.  GCUPS = cells x attempts / s / 1e9 (every cell counts, glass
+included).
+
+Prints ONE JSON line.  Inputs are synthetic (seeded random sequential addition
+of spheres) and resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS of fused RKM step (FP64/FP32); time-to-equilibrium warm vs cold start"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell of each fused stage pass, per unknown: words
+# read + written (S1: r y, w Y2 k1; S2: r Y2 k1, w Y3; S3: r Y3 y k1, w Y4 k3;
+# S4: r Y4 y k1 k3, w Y5 P C; S5: r Y5 P C, w y_new) plus the 1-byte
+# neighbourhood code.
+STAGE_WORDS = [3, 3, 5, 7, 4]
+
+
+def stage_bytes(nvar: int, esize: int):
+    return [w * nvar * esize + 1 for w in STAGE_WORDS]
+
+
+WORKLOADS = {
+    "coupled_128_fp64": dict(
+        case="case_coupled_128", precision="fp64",
+        desc="coupled heat + Allen-Cahn (SigmaP1-P), FP64, 128^3, 64 spheres r=14, "
+             "bottom Dirichlet -5 C, T0=+1 C, adaptive RKM tol 1e-6"),
+    "coupled_256_fp32": dict(
+        case="case_coupled_256", precision="fp32",
+        desc="coupled heat + Allen-Cahn (SigmaP1-P), FP32 fields + FP64 reductions, 256^3, "
+             "64 spheres r=28, bottom Dirichlet ramp -5 -> +5 C over 60 s, adaptive RKM tol 1e-6"),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2401_01672_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str, kernel: str, src_hash: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_gpu(args, wl):
+    import numpy as np
+    import torch
+
+    import paper_2401_01672_amd as pf
+    import pf_inputs as pi
+
+    torch.cuda.set_device(0)
+    case = getattr(pi, wl["case"])()
+    prec = wl["precision"]
+    npdt = np.float64 if prec == "fp64" else np.float32
+    run = dict(case.run)
+    s = pf.Solver(case.params, case.mask, prec, run)
+    s.set_loop(args.steps_per_poll, not args.no_graph)
+    if args.z_chunk:
+        s.set_tile(args.z_chunk)
+    s.set_state(case.phi0.astype(npdt), (case.T0 - case.params["t_star"]).astype(npdt))
+    s.set_time(0.0, run["dt0"])
+    torch.cuda.synchronize()
+    # warmup (includes the tile autotuner on the first call)
+    if args.warmup > 0:
+        s.integrate(max_steps=args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.integrate(max_steps=args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    attempts = st["steps_accepted"] + st["steps_rejected"]
+    assert attempts == args.steps, st
+    ncell = case.ncells
+    gcups = ncell * attempts / wall / 1e9
+    # per-kernel durations with HIP events on the library's stream
+    ms = s.time_kernels(args.kernel_reps)
+    esize = 8 if prec == "fp64" else 4
+    nvar = 2 if case.model == "coupled" else 1
+    sb = stage_bytes(nvar, esize)
+    per_stage = []
+    for i in range(5):
+        gbs = sb[i] * ncell / (ms[i] * 1e-3) / 1e9
+        per_stage.append(dict(stage=f"S{i + 1}", ms=round(ms[i], 5), bytes_per_cell=sb[i],
+                              gbs=round(gbs, 1)))
+    dom = max(range(5), key=lambda i: ms[i])
+    step_ms = sum(ms)
+    src_hash = kernel_source_hash()
+    kname = f"stage{dom + 1}"
+    traffic = read_traffic(args.workload, kname, src_hash)
+    achieved = per_stage[dom]["gbs"]
+    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=f"stage_kernel S{dom + 1} ({prec}, {case.model})",
+                algorithmic_bytes_per_launch=sb[dom] * ncell)
+    extra = dict(
+        stages=per_stage,
+        step_kernels_ms=round(step_ms, 5),
+        step_algorithmic_bytes_per_cell=sum(sb),
+        step_effective_gbs=round(sum(sb) * ncell / (step_ms * 1e-3) / 1e9, 1),
+        controller_ms=round(ms[5], 5),
+        accepted=st["steps_accepted"], rejected=st["steps_rejected"], t_sim=st["t"],
+        ice_fraction=st["ice_fraction"], source_hash=src_hash,
+        z_chunk=s.get_tile()[0], workgroups=s.get_tile()[1],
+    )
+    s.close()
+    return gcups, wall, roof, extra, case, prec
+
+
+def cpu_baseline(wl, sample_steps: int):
+    """The FP64 oracle (as it stands) on the same grid for a bounded number of
+    adaptive attempts, timed on this host's cores."""
+    import numpy as np
+
+    import oracle
+    import pf_inputs as pi
+
+    case = getattr(pi, wl["case"])()
+    P = oracle.make_params(case.params)
+    ctl = oracle.make_ctl(tol=case.run["tol"])
+    T0 = case.T0
+    t0 = time.perf_counter()
+    _, _, st = oracle.integrate(P, case.mask, ctl, 0.0, case.run["dt0"], case.phi0, T0,
+                                max_steps=sample_steps)
+    wall = time.perf_counter() - t0
+    n = st["steps_accepted"] + st["steps_rejected"]
+    return dict(value=round(case.ncells * n / wall / 1e9, 5), unit="GCUPS",
+                cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n} adaptive RKM attempts of the same {case.shape[::-1]} grid in "
+                       f"FP64 ({wall:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="coupled_128_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps-per-poll", type=int, default=16)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--z-chunk", type=int, default=0)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
+        sys.exit(2)
+    wl = WORKLOADS[args.workload]
+    gcups, wall, roof, extra, case, prec = run_gpu(args, wl)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_steps)
+    out = dict(
+        metric=METRIC, value=round(gcups, 4), unit="GCUPS", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(wall / args.steps * 1e3, 5),
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64" if prec == "fp64" else "f32",
+        data="synthetic (seeded random sequential addition of glass spheres)",
+        config=dict(workload=f"{args.workload}: {wl['desc']}", cells=case.ncells,
+                    grid=list(case.shape[::-1]), parallelism="single GPU"),
+        roofline=roof, cpu_baseline=cpu, detail=extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

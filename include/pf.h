@@ -1,0 +1,228 @@
+/*
+ * pf.h - C ABI of the MI355X (gfx950) solver for the pore-scale
+ * freezing/thawing phase-field model of P. Strachota, "Three-dimensional
+ * phase-field simulations of water freezing and thawing at pore-scale"
+ * (arXiv 2401.01672).
+ *
+ * The library integrates, on one GPU, the method-of-lines system obtained by
+ * a finite-volume discretisation (Sec. 2.5) of
+ *   - the heat equation with blended conductivity / heat capacity and latent
+ *     heat release (Sec. 2.2, eq. heat-equation; blending eq.
+ *     material-properties-blending-formula), and
+ *   - the Allen-Cahn equation with the SigmaP1-P reaction term and the water
+ *     indicator (Sec. 2.2, eqs. Allen-Cahn-equation, reaction-term-SigmaP1-P,
+ *     Sigma-limiter, water-indicator),
+ * or the micro-scale reduction at constant temperature (Sec. 2.4), with the
+ * Runge-Kutta-Merson integrator and adaptive steps (Sec. 2.5).
+ *
+ * Discretisation (the paper gives the scheme only in words):
+ *   - cubic cells of edge h on an n1 x n2 x n3 grid; cell (i1,i2,i3) is stored
+ *     at n = i1 + n1*(i2 + n2*i3) (x1 fastest, x3 vertical);
+ *   - glass is a binary voxel mask (G in {0,1});
+ *   - two-point face fluxes; the face conductivity is the arithmetic mean of
+ *     the two cell values; no phase-field flux through a face that touches
+ *     glass or lies on the domain boundary (eq. BC-PF);
+ *   - temperature faces on the domain boundary are insulated (eq.
+ *     BC-temperature-wall) unless listed in dirichlet_faces, where the ghost
+ *     value 2 T_D(t) - T_c is used with the cell's own conductivity (eq.
+ *     BC-temperature-cap);
+ *   - Merson stages k1..k5, new state y + dt (k1 + 4 k4 + k5)/6, error
+ *     estimate dt (2 k1 - 9 k3 + 8 k4 - k5)/30, its max-norm over every
+ *     unknown; accept when eps <= tol; next step
+ *     min(dt_max, safety * dt * (tol/eps)^(1/5)); the last step is clipped to
+ *     land on t_end; tol <= 0 selects fixed steps.
+ *
+ * State: the phase field phi and the temperature offset theta = T - T*
+ * (kelvin).  Fields are stored in the handle's precision (PF_FP64 or
+ * PF_FP32); the error norm, t, dt and every diagnostic sum are FP64.
+ *
+ * Conventions: every call returns PF_OK (0), a positive informational code,
+ * or a negative error code; nothing throws across the ABI.  pf_last_error()
+ * gives a message for the last failing call on a handle (pf_create failures:
+ * pf_last_error(NULL)).  A handle is used from one host thread at a time.
+ * Device pointers passed in are caller-owned; the handle owns its own state
+ * and work buffers and frees them in pf_destroy.  Work is issued on the
+ * handle's stream (pf_set_stream; default: a stream the handle creates).
+ */
+#ifndef PF_H_
+#define PF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define PF_OK 0
+#define PF_EQUILIBRIUM 1 /* run ended: max over water cells of |d phi/dt| < eq_tol */
+#define PF_MAXSTEPS 2    /* run ended: step budget used                           */
+#define PF_EINVAL (-1)   /* invalid argument                                      */
+#define PF_ENOMEM (-2)   /* device allocation failed                              */
+#define PF_EHIP (-3)     /* HIP runtime error                                     */
+#define PF_ENONFINITE (-4) /* NaN/Inf in the error estimate: attempt rejected    */
+#define PF_EDTMIN (-5)   /* proposed step fell below dt_min                       */
+
+/* Models. */
+#define PF_MODEL_AC 0      /* micro-scale: Allen-Cahn only, T = T* - dT (Sec. 2.4) */
+#define PF_MODEL_COUPLED 1 /* heat + Allen-Cahn (Sec. 2.2)                          */
+#define PF_MODEL_TEMP 2    /* Temp model: phi = varphi(T) (Sec. 2.3)                */
+
+/* Reaction terms of the Allen-Cahn equation. */
+#define PF_REACT_SIGMA 0 /* SigmaP1-P, eq. reaction-term-SigmaP1-P */
+#define PF_REACT_GRADP 1 /* GradP, eq. reaction-term-GradP         */
+
+/* Field precision. */
+#define PF_FP64 0
+#define PF_FP32 1
+
+/* Dirichlet temperature schedules T_D(t) (eq. BC-temperature-cap). */
+#define PF_BC_CONST 0 /* T_D = bc_T0                                           */
+#define PF_BC_RAMP 1  /* linear from bc_T0 at bc_t0 to bc_T1 at bc_t1, clamped  */
+#define PF_BC_STEP 2  /* bc_T0 before bc_t0, bc_T1 from bc_t0 on (freeze/thaw)  */
+
+typedef struct pf_handle pf_handle;
+
+/* Problem description; plain data, copied by pf_create. */
+typedef struct {
+  int32_t n1, n2, n3;     /* cells per axis, each >= 1                          */
+  int32_t model;          /* PF_MODEL_*                                         */
+  int32_t precision;      /* PF_FP64 | PF_FP32                                  */
+  int32_t reaction;       /* PF_REACT_*                                         */
+  int32_t dirichlet_faces;/* bit k: face k of (x1-,x1+,x2-,x2+,x3-,x3+)        */
+  int32_t bc_kind;        /* PF_BC_*                                            */
+  double h;               /* cell edge [m]                                      */
+  double xi;              /* interface thickness parameter [m]                  */
+  double alpha;           /* attachment kinetics coefficient [s m^-2]           */
+  double mu;              /* interface mobility [m s^-1 K^-1]                   */
+  double b;               /* SigmaP1-P factor b(eps0, eps1)                     */
+  double eps0, eps1;      /* Sigma limiter knots                                */
+  double zeta;            /* water indicator parameter                          */
+  double t_star;          /* bulk melting point T* [K]                          */
+  double dT;              /* supercooling T* - T of PF_MODEL_AC [K]             */
+  double gamma;           /* Temp model rate [1/K]                              */
+  double lam[3];          /* conductivity: liquid, ice, glass [W m^-1 K^-1]     */
+  double rhoc[3];         /* volumetric heat capacity: liquid, ice, glass       */
+  double Lv;              /* volumetric latent heat rho L [J m^-3]              */
+  double bc_T0, bc_T1;    /* Dirichlet temperatures [K]                         */
+  double bc_t0, bc_t1;    /* schedule times [s]                                 */
+  double tol;             /* error tolerance; <= 0: fixed steps                 */
+  double safety;          /* step-size safety factor                            */
+  double dt_min, dt_max;  /* step bounds [s]                                    */
+} pf_params;
+
+/* Result of one attempt. */
+typedef struct {
+  int32_t accepted;  /* 1 if the attempt was accepted                         */
+  int32_t status;    /* PF_OK, PF_EQUILIBRIUM, PF_ENONFINITE or PF_EDTMIN      */
+  double eps;        /* max-norm of the error estimate                        */
+  double dt_used;    /* step of this attempt (after clipping to t_end)       */
+  double dt_next;    /* proposed next step                                    */
+  double maxk1;      /* max over water cells of |k1_phi| (state at the start) */
+  double t;          /* time after the attempt                                */
+} pf_step_info;
+
+/* Result of a run and diagnostics of the final state (FP64 sums; cells with
+ * G = 0 are water cells, eq. water-occupied-subdomain; ice cells have
+ * phi > 1/2, eq. frozen-subdomain; enthalpy = h^3 sum(rho c theta - Lv phi)). */
+typedef struct {
+  int64_t steps_accepted, steps_rejected;
+  double t, dt;          /* time reached and next proposed step                */
+  int64_t ice_count, pore_count;
+  double sum_phi;        /* sum of phi over water cells                        */
+  double enthalpy;       /* [J]                                                */
+  double maxk1;          /* last max over water cells of |k1_phi|              */
+  double wall_s;         /* host wall time of the call                         */
+  int32_t status;        /* PF_OK (t_end reached), PF_EQUILIBRIUM, PF_MAXSTEPS, or an error */
+  int32_t pad;
+} pf_run_stats;
+
+/* Create a solver for one grid.  mask: host pointer to n1*n2*n3 bytes,
+ * nonzero = glass; read during the call only.  The state starts at
+ * phi = 0, theta = 0, t = 0, dt = dt_max (use pf_set_state / pf_set_time).
+ * Errors: PF_EINVAL (sizes, model/precision/reaction codes, h/xi/alpha <= 0,
+ * NULL pointers), PF_ENOMEM, PF_EHIP. */
+int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out);
+
+/* Free every resource of the handle.  NULL is ignored. */
+void pf_destroy(pf_handle* h);
+
+/* Message of the last failing call on h; h = NULL gives the last pf_create
+ * failure of the calling thread.  Never NULL. */
+const char* pf_last_error(const pf_handle* h);
+
+/* Use a caller stream (a hipStream_t cast to uintptr_t) for all later work
+ * on this handle; 0 restores the handle's own stream. */
+int pf_set_stream(pf_handle* h, uintptr_t stream);
+
+/* Copy a state in: phi and theta point to n cells each in the handle's
+ * precision, on the device (on_device = 1) or the host (0).  theta is
+ * ignored for PF_MODEL_AC and phi for PF_MODEL_TEMP (may be NULL).
+ * Synchronous with respect to the host. */
+int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device);
+
+/* Copy the current state out (same layout rules as pf_set_state). */
+int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device);
+
+/* Set the current time and the next proposed step. */
+int pf_set_time(pf_handle* h, double t, double dt);
+
+/* Right-hand side F(t, phi, theta) of the semi-discrete system: writes
+ * dphi = d phi/dt and dtheta = d theta/dt.  All four are device pointers of n
+ * cells in the handle's precision; unused fields of the model may be NULL.
+ * Asynchronous on the handle's stream. */
+int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dphi,
+           void* dtheta);
+
+/* One Runge-Kutta-Merson attempt from (*t, current state) with proposed step
+ * *dt; on return *t and *dt hold the new time and proposed step and the state
+ * is advanced if the attempt was accepted.  info may be NULL.  Synchronous. */
+int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info);
+
+/* Integrate from the handle's (t, dt) until t_end, max_steps attempts, or
+ * equilibrium (eq_tol > 0: max over water cells of |d phi/dt| < eq_tol at the
+ * start of a step).  The step loop runs on the device (controller included);
+ * the host polls it every few steps.  Returns PF_OK, PF_EQUILIBRIUM,
+ * PF_MAXSTEPS or an error code; stats may be NULL.  Synchronous. */
+int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
+                 pf_run_stats* stats);
+
+/* Diagnostics of the current state into stats (ice/pore counts, sum_phi,
+ * enthalpy); the step counters and t are left as the last run set them. */
+int pf_diagnostics(pf_handle* h, pf_run_stats* stats);
+
+/* Step-loop options: steps_per_poll attempts are issued between host polls;
+ * use_graph = 1 captures them once into a HIP graph and replays it. */
+int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph);
+
+/* Tile shape of the stencil kernels: z_chunk = planes per workgroup column
+ * (>= 1); 0 = choose by the built-in autotuner on the next run. */
+int pf_set_tile(pf_handle* h, int32_t z_chunk);
+
+/* Current tile: *z_chunk receives the planes per workgroup column (after the
+ * autotuner, if it has run) and *workgroups the stencil grid size. */
+int pf_get_tile(const pf_handle* h, int32_t* z_chunk, int32_t* workgroups);
+
+/* Time each kernel of one attempt from the current state and step: every
+ * kernel is launched reps times back to back between two HIP events on the
+ * handle's stream; ms[0..4] receive the mean duration of stages S1..S5 and
+ * ms[5] that of the controller.  The state, t and dt are left unchanged.
+ * Synchronous. */
+int pf_time_kernels(pf_handle* h, int32_t reps, double* ms);
+
+/* Block the host until all work issued on the handle's stream is done. */
+int pf_synchronize(pf_handle* h);
+
+/* Number of cells and bytes per field of the handle (for callers that
+ * allocate matching buffers). */
+int64_t pf_num_cells(const pf_handle* h);
+
+/* Library ABI version. */
+int pf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H_ */

@@ -97,6 +97,8 @@ def lib():
             getattr(L, name).restype = C.c_double
         L.or_water_indicator.argtypes = [C.c_double, C.c_double]
         L.or_water_indicator.restype = C.c_double
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = C.c_int
         L.or_dirichlet_T.argtypes = [C.POINTER(Params), C.c_double]
         L.or_dirichlet_T.restype = C.c_double
         _lib = L
@@ -225,6 +227,10 @@ def sigma(w: float, e0: float, e1: float) -> float:
 
 def water_indicator(G: float, zeta: float) -> float:
     return lib().or_water_indicator(G, zeta)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def dirichlet_T(P: Params, t: float) -> float:

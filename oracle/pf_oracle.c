@@ -447,4 +447,12 @@ void or_diagnostics(const or_params* p, const double* G, const double* phi, cons
   out[3] = H * p->h * p->h * p->h;
 }
 
+/* Threads the oracle's parallel loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+#else
+int or_num_threads(void) { return 1; }
+#endif
+
 int or_abi_version(void) { return 1; }

@@ -1,0 +1,275 @@
+"""MI355X (gfx950) solver for the pore-scale freezing/thawing phase-field model
+of Strachota, arXiv 2401.01672 (Sec. 2.2 coupled heat + Allen-Cahn SigmaP1-P
+model, Sec. 2.4 micro-scale reduction, Sec. 2.5 finite volumes +
+Runge-Kutta-Merson).
+
+This module is a thin ctypes binding of ``libpf.so`` (C ABI in
+``include/pf.h``): it marshals arguments only.  Every step of the computation
+runs in the library's HIP kernels.  Importing fails loudly when the library is
+not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpf.so")
+
+PF_OK, PF_EQUILIBRIUM, PF_MAXSTEPS = 0, 1, 2
+PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENONFINITE, PF_EDTMIN = -1, -2, -3, -4, -5
+MODELS = {"ac": 0, "coupled": 1, "temp": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+REACTIONS = {"sigma": 0, "gradp": 1}
+STATUS_NAMES = {0: "ok", 1: "equilibrium", 2: "maxsteps", -1: "einval", -2: "enomem",
+                -3: "ehip", -4: "enonfinite", -5: "edtmin"}
+
+
+class PFParams(C.Structure):
+    _fields_ = [
+        ("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32),
+        ("model", C.c_int32), ("precision", C.c_int32), ("reaction", C.c_int32),
+        ("dirichlet_faces", C.c_int32), ("bc_kind", C.c_int32),
+        ("h", C.c_double), ("xi", C.c_double), ("alpha", C.c_double), ("mu", C.c_double),
+        ("b", C.c_double), ("eps0", C.c_double), ("eps1", C.c_double), ("zeta", C.c_double),
+        ("t_star", C.c_double), ("dT", C.c_double), ("gamma", C.c_double),
+        ("lam", C.c_double * 3), ("rhoc", C.c_double * 3), ("Lv", C.c_double),
+        ("bc_T0", C.c_double), ("bc_T1", C.c_double), ("bc_t0", C.c_double),
+        ("bc_t1", C.c_double),
+        ("tol", C.c_double), ("safety", C.c_double), ("dt_min", C.c_double),
+        ("dt_max", C.c_double),
+    ]
+
+
+class PFStepInfo(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("status", C.c_int32), ("eps", C.c_double),
+                ("dt_used", C.c_double), ("dt_next", C.c_double), ("maxk1", C.c_double),
+                ("t", C.c_double)]
+
+
+class PFRunStats(C.Structure):
+    _fields_ = [("steps_accepted", C.c_int64), ("steps_rejected", C.c_int64),
+                ("t", C.c_double), ("dt", C.c_double), ("ice_count", C.c_int64),
+                ("pore_count", C.c_int64), ("sum_phi", C.c_double),
+                ("enthalpy", C.c_double), ("maxk1", C.c_double), ("wall_s", C.c_double),
+                ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+_lib = None
+
+# (name, restype, argtypes); every symbol declared in include/pf.h
+_VP, _H = C.c_void_p, C.c_void_p
+SIGNATURES = [
+    ("pf_create", C.c_int, [C.POINTER(PFParams), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("pf_destroy", None, [_H]),
+    ("pf_last_error", C.c_char_p, [_H]),
+    ("pf_set_stream", C.c_int, [_H, C.c_size_t]),
+    ("pf_set_state", C.c_int, [_H, _VP, _VP, C.c_int]),
+    ("pf_get_state", C.c_int, [_H, _VP, _VP, C.c_int]),
+    ("pf_set_time", C.c_int, [_H, C.c_double, C.c_double]),
+    ("pf_rhs", C.c_int, [_H, C.c_double, _VP, _VP, _VP, _VP]),
+    ("pf_rkm_step", C.c_int, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(PFStepInfo)]),
+    ("pf_integrate", C.c_int, [_H, C.c_double, C.c_int64, C.c_double, C.POINTER(PFRunStats)]),
+    ("pf_diagnostics", C.c_int, [_H, C.POINTER(PFRunStats)]),
+    ("pf_set_loop", C.c_int, [_H, C.c_int32, C.c_int32]),
+    ("pf_set_tile", C.c_int, [_H, C.c_int32]),
+    ("pf_get_tile", C.c_int, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("pf_time_kernels", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double)]),
+    ("pf_synchronize", C.c_int, [_H]),
+    ("pf_num_cells", C.c_int64, [_H]),
+    ("pf_abi_version", C.c_int, []),
+]
+
+
+def lib():
+    """Load libpf.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                "(hipcc, gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def make_params(p: Dict, precision: str = "fp64", run: Optional[Dict] = None) -> PFParams:
+    """pf_params from a case parameter dict (keys as in pf_inputs.Case.params)
+    plus integration controls (tol, safety, dt_min, dt_max)."""
+    run = run or {}
+    P = PFParams()
+    P.n1, P.n2, P.n3 = int(p["n1"]), int(p["n2"]), int(p["n3"])
+    P.model = MODELS[p.get("model", "ac")]
+    P.precision = PRECISIONS[precision]
+    P.reaction = REACTIONS[p.get("reaction", "sigma")]
+    P.dirichlet_faces = int(p.get("dirichlet_faces", 0))
+    P.bc_kind = int(p.get("bc_kind", 0))
+    for k in ("h", "xi", "alpha", "mu", "b", "eps0", "eps1", "zeta", "t_star", "dT", "Lv",
+              "bc_T0", "bc_T1", "bc_t0", "bc_t1"):
+        setattr(P, k, float(p.get(k, 0.0)))
+    P.gamma = float(p.get("gamma", 2.0))
+    P.lam[:] = [float(v) for v in p["lam"]]
+    P.rhoc[:] = [float(v) for v in p["rhoc"]]
+    P.tol = float(run.get("tol", 0.0))
+    P.safety = float(run.get("safety", 0.8))
+    P.dt_min = float(run.get("dt_min", 1e-12))
+    P.dt_max = float(run.get("dt_max", 1e30))
+    return P
+
+
+def _ptr(x) -> Tuple[int, int]:
+    """(address, on_device) of a torch tensor or numpy array."""
+    if x is None:
+        return 0, 1
+    if isinstance(x, np.ndarray):
+        assert x.flags.c_contiguous
+        return x.ctypes.data, 0
+    assert x.is_contiguous()
+    return x.data_ptr(), 1 if x.is_cuda else 0
+
+
+class Solver:
+    """One grid: owns a pf_handle."""
+
+    def __init__(self, params: Dict, mask: np.ndarray, precision: str = "fp64",
+                 run: Optional[Dict] = None):
+        self.P = make_params(params, precision, run)
+        self.precision = precision
+        self.model = params.get("model", "ac")
+        self.shape = (int(params["n3"]), int(params["n2"]), int(params["n1"]))
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert m.shape == self.shape, (m.shape, self.shape)
+        self.np_dtype = np.float64 if precision == "fp64" else np.float32
+        h = C.c_void_p()
+        rc = lib().pf_create(C.byref(self.P), m.ctypes.data, C.byref(h))
+        if rc != 0:
+            raise PFError(rc, lib().pf_last_error(None).decode())
+        self.h = h
+
+    # -- plumbing ------------------------------------------------------------
+    def _check(self, rc: int, ok=(PF_OK,)) -> int:
+        if rc not in ok:
+            raise PFError(rc, lib().pf_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.shape))
+
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    # -- state ----------------------------------------------------------------
+    def set_state(self, phi, theta=None):
+        """phi, theta (= T - T*): torch tensors (cuda) or numpy arrays in the
+        handle's precision, ncells elements each."""
+        if isinstance(phi, np.ndarray):
+            phi = np.ascontiguousarray(phi, dtype=self.np_dtype)
+            if theta is not None:
+                theta = np.ascontiguousarray(theta, dtype=self.np_dtype)
+        pp, dev = _ptr(phi)
+        tp, _ = _ptr(theta)
+        self._check(lib().pf_set_state(self.h, pp, tp, dev))
+
+    def get_state(self, device: bool = False):
+        if device:
+            import torch
+            phi = torch.empty(self.shape, dtype=self.torch_dtype(), device="cuda")
+            th = torch.empty(self.shape, dtype=self.torch_dtype(), device="cuda") \
+                if self.model == "coupled" else None
+            torch.cuda.current_stream().synchronize()
+        else:
+            phi = np.empty(self.shape, dtype=self.np_dtype)
+            th = np.empty(self.shape, dtype=self.np_dtype) if self.model == "coupled" else None
+        self._check(lib().pf_get_state(self.h, _ptr(phi)[0], _ptr(th)[0], 1 if device else 0))
+        return phi, th
+
+    def set_time(self, t: float, dt: float):
+        self._check(lib().pf_set_time(self.h, float(t), float(dt)))
+
+    # -- computation -----------------------------------------------------------
+    def rhs(self, t: float, phi, theta, dphi, dtheta):
+        """F(t, phi, theta) into dphi, dtheta (device tensors)."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().pf_rhs(self.h, float(t), _ptr(phi)[0], _ptr(theta)[0],
+                                 _ptr(dphi)[0], _ptr(dtheta)[0]))
+        self._check(lib().pf_synchronize(self.h))
+
+    def rkm_step(self, t: float, dt: float):
+        tt, dd = C.c_double(t), C.c_double(dt)
+        info = PFStepInfo()
+        self._check(lib().pf_rkm_step(self.h, C.byref(tt), C.byref(dd), C.byref(info)),
+                    ok=(PF_OK, PF_ENONFINITE, PF_EDTMIN))
+        return tt.value, dd.value, dict(accepted=info.accepted, status=info.status,
+                                        eps=info.eps, dt_used=info.dt_used,
+                                        dt_next=info.dt_next, maxk1=info.maxk1)
+
+    def integrate(self, t_end: float = float("inf"), max_steps: int = 2**62,
+                  eq_tol: float = 0.0, raise_on_error: bool = True) -> Dict:
+        st = PFRunStats()
+        rc = lib().pf_integrate(self.h, float(t_end), int(max_steps), float(eq_tol), C.byref(st))
+        if rc < 0 and raise_on_error:
+            self._check(rc)
+        return self._stats(st, rc)
+
+    def diagnostics(self) -> Dict:
+        st = PFRunStats()
+        self._check(lib().pf_diagnostics(self.h, C.byref(st)))
+        return self._stats(st, PF_OK)
+
+    @staticmethod
+    def _stats(st: PFRunStats, rc: int) -> Dict:
+        pore = st.pore_count
+        return dict(steps_accepted=st.steps_accepted, steps_rejected=st.steps_rejected,
+                    t=st.t, dt=st.dt, ice_count=st.ice_count, pore_count=pore,
+                    sum_phi=st.sum_phi, enthalpy=st.enthalpy, maxk1=st.maxk1,
+                    wall_s=st.wall_s, status=st.status, rc=rc,
+                    ice_fraction=(st.ice_count / pore) if pore else 0.0,
+                    uwc=(1.0 - st.ice_count / pore) if pore else 0.0)
+
+    def set_loop(self, steps_per_poll: int = 16, use_graph: bool = True):
+        self._check(lib().pf_set_loop(self.h, int(steps_per_poll), 1 if use_graph else 0))
+
+    def set_tile(self, z_chunk: int):
+        self._check(lib().pf_set_tile(self.h, int(z_chunk)))
+
+    def get_tile(self):
+        z, w = C.c_int32(), C.c_int32()
+        self._check(lib().pf_get_tile(self.h, C.byref(z), C.byref(w)))
+        return z.value, w.value
+
+    def time_kernels(self, reps: int = 10):
+        out = (C.c_double * 6)()
+        self._check(lib().pf_time_kernels(self.h, int(reps), out))
+        return list(out)
+
+    def synchronize(self):
+        self._check(lib().pf_synchronize(self.h))

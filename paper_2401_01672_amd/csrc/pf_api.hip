@@ -1,0 +1,610 @@
+// C ABI of libpf (declarations and semantics in include/pf.h).
+//
+// A handle owns, per unknown (phi and/or theta): the double-buffered state
+// y[0]/y[1], two stage-input buffers, and the k1/P and k3/C buffers; plus the
+// per-cell neighbourhood code, the per-workgroup partial reductions and the
+// device step-control block.  One attempt is five stage kernels and one
+// controller kernel, all reading the control block, so a run of attempts is
+// issued without host round trips (optionally as a replayed HIP graph) and
+// the host only polls the control block between batches of attempts.
+#include <float.h>
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <cstdio>
+#include <string>
+
+#include "pf_internal.h"
+
+using pf::DevCtl;
+using pf::ModelConst;
+using pf::StageArgs;
+
+struct pf_handle {
+  pf_params P;
+  ModelConst mc;
+  long long ncell = 0;
+  size_t esize = 0;
+  int nvar = 0;  // 1: phi (AC); 2: phi, theta (coupled)
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  void* slab = nullptr;
+  uint8_t* code = nullptr;
+  void* y[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  void* a[2] = {nullptr, nullptr};
+  void* b[2] = {nullptr, nullptr};
+  void* k1[2] = {nullptr, nullptr};
+  void* k3[2] = {nullptr, nullptr};
+  double* part1 = nullptr;
+  double* part5 = nullptr;
+  double* diag_out = nullptr;
+  DevCtl* ctl = nullptr;   // device
+  DevCtl* hctl = nullptr;  // pinned host mirror
+  int z_chunk = 16;
+  int tiles_p = 0, tiles_z = 0, nparts = 0, max_parts = 0;
+  int autotune_pending = 1;
+  int steps_per_poll = 16;
+  int use_graph = 1;
+  hipGraphExec_t gexec = nullptr;
+  int graph_steps = 0;
+  double t = 0.0, dt = 0.0;
+  int cur = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(pf_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+#define PF_HIP(h, expr)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((h), PF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void fill_model_const(const pf_params& P, ModelConst& m) {
+  memset(&m, 0, sizeof(m));
+  m.n1 = P.n1;
+  m.n2 = P.n2;
+  m.n3 = P.n3;
+  m.dirichlet_faces = P.dirichlet_faces;
+  m.bc_kind = P.bc_kind;
+  m.model = P.model;
+  m.cL = 1.0 / (P.alpha * P.h * P.h);
+  m.cR = 1.0 / (P.alpha * P.xi * P.xi);
+  m.beta0 = 0.5 * P.xi * P.b * P.mu * P.alpha;
+  m.betaAC = m.beta0 * P.dT;
+  m.e0 = P.eps0;
+  m.inv_de = 1.0 / (P.eps1 - P.eps0);
+  m.iw_glass = 1.0 - P.zeta > 0.0 ? 1.0 - P.zeta : 0.0;
+  m.cH = 1.0 / (P.h * P.h);
+  m.lamL = P.lam[0];
+  m.dlam = P.lam[1] - P.lam[0];
+  m.lamG = P.lam[2];
+  m.rcL = P.rhoc[0];
+  m.drc = P.rhoc[1] - P.rhoc[0];
+  m.rcG = P.rhoc[2];
+  m.Lv = P.Lv;
+  m.bc_T0 = P.bc_T0 - P.t_star;
+  m.bc_T1 = P.bc_T1 - P.t_star;
+  m.bc_t0 = P.bc_t0;
+  m.bc_t1 = P.bc_t1;
+  m.h3 = P.h * P.h * P.h;
+  m.gamma = P.gamma;
+  m.dT = P.dT;
+}
+
+int validate(const pf_params* P, const uint8_t* mask) {
+  if (!P || !mask) return fail(nullptr, PF_EINVAL, "params and mask must be non-NULL");
+  if (P->n1 < 1 || P->n2 < 1 || P->n3 < 1)
+    return fail(nullptr, PF_EINVAL, "grid sizes must be >= 1");
+  const long long nc = (long long)P->n1 * P->n2 * P->n3;
+  if (nc >= (1LL << 31) - 2LL * P->n1 * P->n2)
+    return fail(nullptr, PF_EINVAL, "grid too large (cell index must fit in int32)");
+  if (P->model != PF_MODEL_AC && P->model != PF_MODEL_COUPLED)
+    return fail(nullptr, PF_EINVAL, "model must be PF_MODEL_AC or PF_MODEL_COUPLED");
+  if (P->precision != PF_FP64 && P->precision != PF_FP32)
+    return fail(nullptr, PF_EINVAL, "precision must be PF_FP64 or PF_FP32");
+  if (P->reaction != PF_REACT_SIGMA)
+    return fail(nullptr, PF_EINVAL, "reaction must be PF_REACT_SIGMA");
+  if (!(P->h > 0) || !(P->xi > 0) || !(P->alpha > 0))
+    return fail(nullptr, PF_EINVAL, "h, xi and alpha must be positive");
+  if (!(P->eps1 != P->eps0)) return fail(nullptr, PF_EINVAL, "eps1 must differ from eps0");
+  if (P->model == PF_MODEL_COUPLED) {
+    for (int i = 0; i < 3; ++i)
+      if (!(P->rhoc[i] > 0)) return fail(nullptr, PF_EINVAL, "rhoc must be positive");
+  }
+  if (P->dirichlet_faces < 0 || P->dirichlet_faces > 63)
+    return fail(nullptr, PF_EINVAL, "dirichlet_faces must be a 6-bit mask");
+  if (P->bc_kind < PF_BC_CONST || P->bc_kind > PF_BC_STEP)
+    return fail(nullptr, PF_EINVAL, "bc_kind out of range");
+  if (P->bc_kind == PF_BC_RAMP && !(P->bc_t1 > P->bc_t0))
+    return fail(nullptr, PF_EINVAL, "ramp needs bc_t1 > bc_t0");
+  if (P->tol > 0 && (!(P->safety > 0) || !(P->dt_max > 0)))
+    return fail(nullptr, PF_EINVAL, "adaptive mode needs safety > 0 and dt_max > 0");
+  return PF_OK;
+}
+
+StageArgs stage_args(const pf_handle* h, int stage) {
+  StageArgs a;
+  memset(&a, 0, sizeof(a));
+  a.code = h->code;
+  a.ctl = h->ctl;
+  a.mc = h->mc;
+  a.z_chunk = h->z_chunk;
+  a.tiles_p = h->tiles_p;
+  a.tiles_z = h->tiles_z;
+  for (int v = 0; v < 2; ++v) {
+    a.y[0][v] = h->y[0][v];
+    a.y[1][v] = h->y[1][v];
+    a.out_y[0][v] = h->y[0][v];
+    a.out_y[1][v] = h->y[1][v];
+    a.k1[v] = h->k1[v];
+    a.k3[v] = h->k3[v];
+    switch (stage) {
+      case 1: a.in[v] = nullptr; a.out[v] = h->a[v]; break;
+      case 2: a.in[v] = h->a[v]; a.out[v] = h->b[v]; break;
+      case 3: a.in[v] = h->b[v]; a.out[v] = h->a[v]; break;
+      case 4: a.in[v] = h->a[v]; a.out[v] = h->b[v]; break;
+      case 5: a.in[v] = h->b[v]; a.out[v] = nullptr; break;
+      default: break;
+    }
+  }
+  a.part = (stage == 1) ? h->part1 : (stage == 5 ? h->part5 : nullptr);
+  return a;
+}
+
+hipError_t issue_step(const pf_handle* h, hipStream_t s) {
+  for (int st = 1; st <= 5; ++st) {
+    StageArgs a = stage_args(h, st);
+    hipError_t e = pf::launch_stage(h->P.precision, h->P.model, st, a, s);
+    if (e != hipSuccess) return e;
+  }
+  return pf::launch_controller(h->ctl, h->part1, h->part5, h->nparts, h->mc.h3, s);
+}
+
+void drop_graph(pf_handle* h) {
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  h->graph_steps = 0;
+}
+
+int set_tiles(pf_handle* h, int zc) {
+  if (zc < 1) zc = 1;
+  if (zc > h->P.n3) zc = h->P.n3;
+  int tp, tz;
+  int nb = pf::grid_blocks(h->mc, zc, &tp, &tz);
+  if (nb > h->max_parts) return fail(h, PF_EINVAL, "tile choice exceeds partial buffer");
+  h->z_chunk = zc;
+  h->tiles_p = tp;
+  h->tiles_z = tz;
+  h->nparts = nb;
+  drop_graph(h);
+  return PF_OK;
+}
+
+void init_ctl(pf_handle* h, DevCtl& c, double t_end, long long max_steps, double eq_tol) {
+  memset(&c, 0, sizeof(c));
+  c.t = h->t;
+  c.dt_nom = h->dt;
+  c.t_end = t_end;
+  c.tol = h->P.tol;
+  c.safety = h->P.safety;
+  c.dt_min = h->P.dt_min;
+  c.dt_max = h->P.dt_max;
+  c.eq_tol = eq_tol;
+  c.max_steps = max_steps;
+  c.cur = h->cur;
+  c.dt_att = c.dt_nom;
+  if (c.t_end - c.t < c.dt_att) {
+    c.dt_att = c.t_end - c.t;
+    c.clipped = 1;
+  }
+}
+
+int push_ctl(pf_handle* h) {
+  PF_HIP(h, hipMemcpyAsync(h->ctl, h->hctl, sizeof(DevCtl), hipMemcpyHostToDevice, h->stream));
+  return PF_OK;
+}
+
+int pull_ctl(pf_handle* h) {
+  PF_HIP(h, hipMemcpyAsync(h->hctl, h->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, h->stream));
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  return PF_OK;
+}
+
+// Autotuner: time the five stage kernels for each candidate z_chunk on the
+// current state (no controller, so the state is untouched) and keep the
+// fastest.
+int autotune(pf_handle* h) {
+  h->autotune_pending = 0;
+  const int cands[] = {4, 8, 16, 32, 64};
+  DevCtl& c = *h->hctl;
+  init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
+  if (!(c.dt_att > 0) || !(c.dt_att < INFINITY)) c.dt_att = 1e-12;
+  int rc = push_ctl(h);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  PF_HIP(h, hipEventCreate(&e0));
+  PF_HIP(h, hipEventCreate(&e1));
+  int best = h->z_chunk;
+  float best_ms = 1e30f;
+  for (int zc : cands) {
+    if (zc > h->P.n3 && zc != cands[0]) continue;
+    if (set_tiles(h, zc)) continue;
+    float tot = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      PF_HIP(h, hipEventRecord(e0, h->stream));
+      for (int st = 1; st <= 5; ++st) {
+        StageArgs a = stage_args(h, st);
+        PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
+      }
+      PF_HIP(h, hipEventRecord(e1, h->stream));
+      PF_HIP(h, hipEventSynchronize(e1));
+      float ms = 0;
+      PF_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tot += ms;  // first repetition warms caches and code
+    }
+    if (tot < best_ms) {
+      best_ms = tot;
+      best = zc;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return set_tiles(h, best);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_abi_version(void) { return 1; }
+
+const char* pf_last_error(const pf_handle* h) {
+  if (!h) return g_create_err.c_str();
+  return h->err.c_str();
+}
+
+int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
+  if (!out) return fail(nullptr, PF_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  int rc = validate(params, mask);
+  if (rc) return rc;
+  pf_handle* h = new (std::nothrow) pf_handle();
+  if (!h) return fail(nullptr, PF_ENOMEM, "host allocation failed");
+  h->P = *params;
+  fill_model_const(h->P, h->mc);
+  h->ncell = (long long)params->n1 * params->n2 * params->n3;
+  h->esize = params->precision == PF_FP64 ? 8 : 4;
+  h->nvar = params->model == PF_MODEL_COUPLED ? 2 : 1;
+  h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
+
+  auto bail = [&](int code, const std::string& msg) {
+    g_create_err = msg;
+    pf_destroy(h);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(PF_EHIP, "hipStreamCreateWithFlags failed");
+  h->stream = h->own_stream;
+
+  // maximum number of workgroups over all tile choices (z_chunk >= 1)
+  int tp, tz;
+  h->max_parts = pf::grid_blocks(h->mc, 1, &tp, &tz);
+  const size_t field = ((size_t)h->ncell * h->esize + 255) & ~(size_t)255;
+  const size_t code_bytes = ((size_t)h->ncell + 255) & ~(size_t)255;
+  const size_t part_bytes = (((size_t)h->max_parts * (pf::kPartS1 + pf::kPartS5) + 64) *
+                             sizeof(double) + 255) & ~(size_t)255;
+  const size_t total = field * 6 * h->nvar + code_bytes + part_bytes + 2 * 256;  // control block + timing copy
+  if (hipMalloc(&h->slab, total) != hipSuccess) return bail(PF_ENOMEM, "hipMalloc of work buffers failed");
+  char* p = static_cast<char*>(h->slab);
+  for (int v = 0; v < h->nvar; ++v) {
+    h->y[0][v] = p; p += field;
+    h->y[1][v] = p; p += field;
+    h->a[v] = p; p += field;
+    h->b[v] = p; p += field;
+    h->k1[v] = p; p += field;
+    h->k3[v] = p; p += field;
+  }
+  h->code = reinterpret_cast<uint8_t*>(p); p += code_bytes;
+  h->part1 = reinterpret_cast<double*>(p);
+  h->part5 = h->part1 + (size_t)h->max_parts * pf::kPartS1;
+  h->diag_out = h->part5 + h->max_parts;
+  p += part_bytes;
+  h->ctl = reinterpret_cast<DevCtl*>(p);
+  if (hipHostMalloc((void**)&h->hctl, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess)
+    return bail(PF_ENOMEM, "hipHostMalloc failed");
+
+  // neighbourhood codes from the host mask
+  uint8_t* dmask = nullptr;
+  if (hipMalloc(&dmask, (size_t)h->ncell) != hipSuccess) return bail(PF_ENOMEM, "hipMalloc mask");
+  hipError_t e = hipMemcpy(dmask, mask, (size_t)h->ncell, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = pf::launch_build_code(dmask, h->code, params->n1, params->n2, params->n3, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->slab, 0, field * 6 * h->nvar, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(dmask);
+  if (e != hipSuccess) return bail(PF_EHIP, std::string("setup: ") + hipGetErrorString(e));
+  int zc = params->n3 >= 256 ? 32 : 16;
+  if (set_tiles(h, zc)) return bail(PF_EINVAL, h->err);
+  init_ctl(h, *h->hctl, INFINITY, 0, 0.0);
+  h->hctl->done = 1;
+  if (push_ctl(h) || hipStreamSynchronize(h->stream) != hipSuccess)
+    return bail(PF_EHIP, "control block init failed");
+  *out = h;
+  return PF_OK;
+}
+
+void pf_destroy(pf_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  if (h->slab) (void)hipFree(h->slab);
+  if (h->hctl) (void)hipHostFree(h->hctl);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  delete h;
+}
+
+int pf_set_stream(pf_handle* h, uintptr_t stream) {
+  if (!h) return PF_EINVAL;
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : h->own_stream;
+  if (s != h->stream) {
+    PF_HIP(h, hipStreamSynchronize(h->stream));
+    h->stream = s;
+    drop_graph(h);
+  }
+  return PF_OK;
+}
+
+int64_t pf_num_cells(const pf_handle* h) { return h ? h->ncell : -1; }
+
+int pf_synchronize(pf_handle* h) {
+  if (!h) return PF_EINVAL;
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  return PF_OK;
+}
+
+int pf_set_time(pf_handle* h, double t, double dt) {
+  if (!h) return PF_EINVAL;
+  if (!(dt > 0) || !(t == t)) return fail(h, PF_EINVAL, "dt must be positive and t finite");
+  h->t = t;
+  h->dt = dt;
+  return PF_OK;
+}
+
+int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device) {
+  if (!h) return PF_EINVAL;
+  if (!phi) return fail(h, PF_EINVAL, "phi must be non-NULL");
+  if (h->nvar == 2 && !theta) return fail(h, PF_EINVAL, "theta must be non-NULL for the coupled model");
+  const size_t bytes = (size_t)h->ncell * h->esize;
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  h->cur = 0;
+  PF_HIP(h, hipMemcpyAsync(h->y[0][0], phi, bytes, k, h->stream));
+  if (h->nvar == 2) PF_HIP(h, hipMemcpyAsync(h->y[0][1], theta, bytes, k, h->stream));
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  return PF_OK;
+}
+
+int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device) {
+  if (!h) return PF_EINVAL;
+  const size_t bytes = (size_t)h->ncell * h->esize;
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (phi) PF_HIP(h, hipMemcpyAsync(phi, h->y[h->cur][0], bytes, k, h->stream));
+  if (theta && h->nvar == 2) PF_HIP(h, hipMemcpyAsync(theta, h->y[h->cur][1], bytes, k, h->stream));
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  return PF_OK;
+}
+
+int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dphi,
+           void* dtheta) {
+  if (!h) return PF_EINVAL;
+  if (!phi || !dphi) return fail(h, PF_EINVAL, "phi and dphi must be non-NULL");
+  if (h->nvar == 2 && (!theta || !dtheta))
+    return fail(h, PF_EINVAL, "theta and dtheta must be non-NULL for the coupled model");
+  StageArgs a = stage_args(h, 0);
+  a.ignore_done = 1;
+  a.t_fixed = t;
+  a.in[0] = phi;
+  a.in[1] = theta;
+  a.out[0] = dphi;
+  a.out[1] = dtheta;
+  PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, h->stream));
+  return PF_OK;
+}
+
+int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info) {
+  if (!h || !t || !dt) return PF_EINVAL;
+  if (!(*dt > 0)) return fail(h, PF_EINVAL, "dt must be positive");
+  h->t = *t;
+  h->dt = *dt;
+  DevCtl& c = *h->hctl;
+  init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
+  int rc = push_ctl(h);
+  if (rc) return rc;
+  PF_HIP(h, issue_step(h, h->stream));
+  rc = pull_ctl(h);
+  if (rc) return rc;
+  h->cur = c.cur;
+  h->t = c.t;
+  h->dt = c.dt_nom;
+  *t = c.t;
+  *dt = c.dt_nom;
+  if (info) {
+    info->accepted = c.accepted;
+    info->status = c.status;
+    info->eps = c.eps;
+    info->dt_used = c.dt_used;
+    info->dt_next = c.dt_nom;
+    info->maxk1 = c.maxk1;
+    info->t = c.t;
+  }
+  if (c.status < 0) return fail(h, c.status, c.status == PF_ENONFINITE ? "non-finite error estimate"
+                                                                      : "step fell below dt_min");
+  return PF_OK;
+}
+
+int pf_diagnostics(pf_handle* h, pf_run_stats* st) {
+  if (!h || !st) return PF_EINVAL;
+  PF_HIP(h, pf::launch_diag(h->P.precision, h->P.model, h->code, h->y[h->cur][0],
+                            h->y[h->cur][1], h->mc, h->ncell, h->part1, h->max_parts > 1024 ? 1024 : h->max_parts,
+                            h->diag_out, h->stream));
+  double out[4];
+  PF_HIP(h, hipMemcpyAsync(out, h->diag_out, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  st->pore_count = (int64_t)out[0];
+  st->sum_phi = out[1];
+  st->enthalpy = out[2];
+  st->ice_count = (int64_t)out[3];
+  return PF_OK;
+}
+
+int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph) {
+  if (!h || steps_per_poll < 1 || steps_per_poll > 4096) return PF_EINVAL;
+  h->steps_per_poll = steps_per_poll;
+  h->use_graph = use_graph ? 1 : 0;
+  drop_graph(h);
+  return PF_OK;
+}
+
+int pf_get_tile(const pf_handle* h, int32_t* z_chunk, int32_t* workgroups) {
+  if (!h || !z_chunk || !workgroups) return PF_EINVAL;
+  *z_chunk = h->z_chunk;
+  *workgroups = h->nparts;
+  return PF_OK;
+}
+
+int pf_set_tile(pf_handle* h, int32_t z_chunk) {
+  if (!h || z_chunk < 0) return PF_EINVAL;
+  if (z_chunk == 0) {
+    h->autotune_pending = 1;
+    return PF_OK;
+  }
+  h->autotune_pending = 0;
+  return set_tiles(h, z_chunk);
+}
+
+int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
+                 pf_run_stats* stats) {
+  if (!h) return PF_EINVAL;
+  auto w0 = std::chrono::steady_clock::now();
+  if (h->autotune_pending) {
+    int rc = autotune(h);
+    if (rc) return rc;
+  }
+  DevCtl& c = *h->hctl;
+  init_ctl(h, c, t_end, max_steps, eq_tol);
+  if (h->t >= t_end) {
+    c.done = 1;
+    c.status = PF_OK;
+  } else if (max_steps <= 0) {
+    c.done = 1;
+    c.status = PF_MAXSTEPS;
+  }
+  int rc = push_ctl(h);
+  if (rc) return rc;
+  while (!c.done) {
+    if (h->use_graph) {
+      if (!h->gexec || h->graph_steps != h->steps_per_poll) {
+        drop_graph(h);
+        hipGraph_t g;
+        PF_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < h->steps_per_poll && e == hipSuccess; ++i) e = issue_step(h, h->stream);
+        hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+        if (e != hipSuccess) return fail(h, PF_EHIP, std::string("capture: ") + hipGetErrorString(e));
+        PF_HIP(h, e2);
+        hipError_t e3 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        PF_HIP(h, e3);
+        h->graph_steps = h->steps_per_poll;
+      }
+      PF_HIP(h, hipGraphLaunch(h->gexec, h->stream));
+    } else {
+      for (int i = 0; i < h->steps_per_poll; ++i) PF_HIP(h, issue_step(h, h->stream));
+    }
+    rc = pull_ctl(h);
+    if (rc) return rc;
+  }
+  h->cur = c.cur;
+  h->t = c.t;
+  h->dt = c.dt_nom;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    rc = pf_diagnostics(h, stats);
+    if (rc) return rc;
+    stats->steps_accepted = c.n_acc;
+    stats->steps_rejected = c.n_rej;
+    stats->t = c.t;
+    stats->dt = c.dt_nom;
+    stats->maxk1 = c.maxk1;
+    stats->status = c.status;
+    stats->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+  }
+  if (c.status < 0)
+    return fail(h, c.status, c.status == PF_ENONFINITE ? "non-finite error estimate"
+                                                       : "step fell below dt_min");
+  return c.status;
+}
+
+int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
+  if (!h || !ms || reps < 1) return PF_EINVAL;
+  if (h->autotune_pending) {
+    int rc = autotune(h);
+    if (rc) return rc;
+  }
+  // Each kernel is launched reps times back to back between two events, so
+  // the mean excludes the host launch latency.  The control block is set to
+  // a live attempt but the controller's bookkeeping of the state is not
+  // advanced: y[cur] is never written by a stage kernel, so the state, t and
+  // dt are unchanged (the stage buffers are scratch until the next S1).
+  DevCtl& c = *h->hctl;
+  init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
+  int rc = push_ctl(h);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  PF_HIP(h, hipEventCreate(&e0));
+  PF_HIP(h, hipEventCreate(&e1));
+  for (int st = 1; st <= 6; ++st) {
+    StageArgs a = stage_args(h, st <= 5 ? st : 5);
+    // warm-up launch, then the timed batch
+    if (st <= 5) PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
+    PF_HIP(h, hipEventRecord(e0, h->stream));
+    for (int r = 0; r < reps; ++r) {
+      if (st <= 5) {
+        PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
+      } else {
+        // controller timing on a copy of the control block
+        PF_HIP(h, pf::launch_controller(h->ctl + 1, h->part1, h->part5, h->nparts, h->mc.h3,
+                                        h->stream));
+      }
+    }
+    PF_HIP(h, hipEventRecord(e1, h->stream));
+    PF_HIP(h, hipEventSynchronize(e1));
+    float x = 0;
+    PF_HIP(h, hipEventElapsedTime(&x, e0, e1));
+    ms[st - 1] = (double)x / reps;
+    if (st == 5) {
+      // arm the scratch control block used for the controller timing
+      DevCtl cc = c;
+      cc.done = 0;
+      PF_HIP(h, hipMemcpyAsync(h->ctl + 1, &cc, sizeof(DevCtl), hipMemcpyHostToDevice, h->stream));
+      PF_HIP(h, hipStreamSynchronize(h->stream));
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return PF_OK;
+}
+
+}  // extern "C"

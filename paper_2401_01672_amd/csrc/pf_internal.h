@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP translation units of libpf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "pf.h"
+
+namespace pf {
+
+// Threads per stencil workgroup: one cell of a 256-cell run of the x1-x2
+// plane per thread; the workgroup then marches along x3.
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// Per-cell neighbourhood code (one byte, static): bit f (f = 0..5 for faces
+// x1-,x1+,x2-,x2+,x3-,x3+) is set when the neighbour through face f exists
+// and is water; bit 6 is set when the cell itself is glass.
+constexpr uint8_t kGlassBit = 1u << 6;
+
+// Device-resident step control.  The stage kernels read it; only the
+// controller kernel (one thread) writes it, so a run of steps needs no host
+// round trip.
+struct DevCtl {
+  double t;          // current time
+  double dt_att;     // step of the pending attempt (clipped to t_end)
+  double dt_nom;     // proposed step before clipping
+  double t_end;
+  double tol, safety, dt_min, dt_max, eq_tol;
+  double eps;        // last error norm
+  double maxk1;      // last max over water cells of |k1_phi|
+  double sum_phi, enthalpy, ice;  // diagnostics of the state at the last step start
+  double dt_used;    // step of the last attempt
+  long long n_acc, n_rej, max_steps;
+  int cur;           // which of the two state buffers holds y
+  int done;          // nonzero: the run has ended; kernels return at once
+  int status;        // PF_* code of the run
+  int clipped;       // the pending attempt lands exactly on t_end
+  int accepted;      // last attempt accepted
+  int pad[3];
+};
+
+// Model constants, precomputed on the host in FP64 (cast per kernel).
+struct ModelConst {
+  int n1, n2, n3;
+  int dirichlet_faces;
+  int bc_kind;
+  int model;
+  double cL;        // 1/(alpha h^2): Laplacian weight of the phase equation
+  double cR;        // 1/(alpha xi^2): reaction weight
+  double beta0;     // xi b mu alpha / 2
+  double betaAC;    // beta0 * dT (micro-scale model)
+  double e0, inv_de;// Sigma limiter: eps0 and 1/(eps1 - eps0)
+  double iw_glass;  // water indicator of a glass cell: max(0, 1 - zeta)
+  double cH;        // 1/h^2
+  double lamL, dlam, lamG;   // lambda_L, lambda_I - lambda_L, lambda_G
+  double rcL, drc, rcG;      // rho c likewise
+  double Lv;
+  double bc_T0, bc_T1, bc_t0, bc_t1;  // Dirichlet schedule (theta units)
+  double h3;        // h^3 for the enthalpy
+  double gamma;     // Temp model
+  double dT;        // supercooling of the micro-scale model (theta = -dT)
+};
+
+struct Buffers {
+  void* y[2][2];     // [buffer][var]: state double buffer
+  void* a[2];        // stage inputs Y2 / Y4
+  void* b[2];        // stage inputs Y3 / Y5
+  void* k1[2];       // k1, then P
+  void* k3[2];       // k3, then C
+};
+
+// Arguments of a stage kernel (passed by value).
+struct StageArgs {
+  const uint8_t* code;
+  DevCtl* ctl;
+  double* part;       // per-workgroup partial reductions
+  const void* in[2];  // stage input (stencil), per variable
+  const void* y[2][2];// both state buffers
+  void* k1[2];
+  void* k3[2];
+  void* out[2];       // next stage input, or y_new (S5: written to y[1-cur])
+  void* out_y[2][2];  // S5 destination candidates
+  ModelConst mc;
+  int z_chunk;
+  int tiles_p, tiles_z;  // workgroup grid: plane tiles x z chunks
+  int ignore_done;       // standalone RHS: ignore ctl
+  double t_fixed;        // standalone RHS time
+};
+
+// Partial-reduction slots per workgroup.
+constexpr int kPartS1 = 4;  // max |k1_phi| (water), sum phi (water), enthalpy sum, ice count
+constexpr int kPartS5 = 1;  // max |E|
+
+}  // namespace pf
+
+// Host-side launchers (pf_stencil.hip).
+namespace pf {
+hipError_t launch_build_code(const uint8_t* mask, uint8_t* code, int n1, int n2, int n3,
+                             hipStream_t s);
+hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a,
+                        hipStream_t s);
+hipError_t launch_controller(DevCtl* ctl, const double* part1, const double* part5,
+                             int nparts, double h3, hipStream_t s);
+hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* phi,
+                       const void* th, const ModelConst& m, long long n, double* part,
+                       int nparts, double* out4, hipStream_t s);
+int grid_blocks(const ModelConst& mc, int z_chunk, int* tiles_p, int* tiles_z);
+}  // namespace pf

@@ -1,0 +1,369 @@
+"""GPU (HIP, gfx950) path against the FP64 oracle, through the C ABI.
+
+Bars: FP64 fields within 1e-12 relative (max abs difference over the max
+abs oracle value, per field) at fixed steps; FP32 fields within the FP32
+error bounds derived in the tests; integer diagnostics exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pf_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2401_01672_amd as pf  # noqa: E402
+
+T_STAR = 273.15
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rand_problem(shape, model, seed, faces=0, bc_kind=0, glass=0.3):
+    rng = np.random.default_rng(seed)
+    n3, n2, n1 = shape
+    p = dict(n1=n1, n2=n2, n3=n3, h=2.1e-4, xi=2.1e-4, alpha=4.17e6, mu=1e-4, b=1.0,
+             eps0=0.05, eps1=0.2, zeta=2.0, t_star=T_STAR, dT=0.7,
+             lam=(0.6, 2.2, 1.0), rhoc=(4.2e6, 1.9e6, 2.0e6), Lv=3.34e8,
+             dirichlet_faces=faces, bc_kind=bc_kind, bc_T0=T_STAR - 5, bc_T1=T_STAR + 5,
+             bc_t0=0.0, bc_t1=2.0, model=model, phi_face_mask=1)
+    if model == "ac":
+        p.update(h=31.25e-6, xi=1.5 * 31.25e-6, alpha=pi.ALPHA_REAL / 100, dT=0.3)
+    mask = (rng.random(shape) < glass).astype(np.uint8)
+    phi = rng.random(shape)
+    phi[rng.random(shape) < 0.3] = 0.0
+    phi[rng.random(shape) < 0.2] = 1.0
+    phi[mask == 1] = 0.0
+    T = T_STAR + rng.normal(0, 2, shape)
+    return p, mask, phi, T
+
+
+def gpu_rhs(p, mask, t, phi, T, precision="fp64"):
+    s = pf.Solver(p, mask, precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    ph = torch.tensor(phi, dtype=dt, device="cuda").contiguous()
+    th = torch.tensor(T - T_STAR, dtype=dt, device="cuda").contiguous() \
+        if p["model"] == "coupled" else None
+    dph = torch.empty_like(ph)
+    dth = torch.empty_like(ph) if th is not None else None
+    s.rhs(t, ph, th, dph, dth)
+    out = (dph.cpu().numpy(), None if dth is None else dth.cpu().numpy())
+    s.close()
+    return out
+
+
+SHAPES = [(8, 8, 8), (23, 29, 37), (5, 7, 3), (1, 1, 9), (9, 1, 1), (1, 1, 1), (17, 3, 300)]
+
+
+@pytest.mark.parametrize("model", ["ac", "coupled"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_rhs_fp64_matches_oracle(model, shape):
+    for trial, faces in enumerate((0, 1 << 4, 63)):
+        p, mask, phi, T = rand_problem(shape, model, 100 + trial, faces=faces,
+                                       bc_kind=trial % 3)
+        t = 0.37 * (trial + 1)
+        kp, kT = oracle.rhs(oracle.make_params(p), mask, t, phi,
+                            T if model == "coupled" else None)
+        gp, gT = gpu_rhs(p, mask, t, phi, T)
+        assert rel(gp, kp) <= 1e-12
+        if model == "coupled":
+            assert rel(gT, kT) <= 1e-12
+
+
+@pytest.mark.parametrize("model", ["ac", "coupled"])
+def test_rhs_fp32_matches_oracle(model):
+    shape = (19, 33, 41)
+    p, mask, phi, T = rand_problem(shape, model, 7, faces=1 << 4, bc_kind=1)
+    phi = phi.astype(np.float32).astype(np.float64)
+    Tq = (T - T_STAR).astype(np.float32).astype(np.float64) + T_STAR
+    kp, kT = oracle.rhs(oracle.make_params(p), mask, 0.5, phi,
+                        Tq if model == "coupled" else None)
+    gp, gT = gpu_rhs(p, mask, 0.5, phi, Tq, "fp32")
+    # inputs are exactly representable; the error is FP32 rounding in the
+    # stencil sum and the reaction (a few ulp of the largest term)
+    assert rel(gp, kp) <= 2e-5
+    if model == "coupled":
+        assert rel(gT, kT) <= 2e-5
+
+
+def fixed_run_gpu(p, mask, phi, T, dt, steps, precision="fp64", use_graph=True, z_chunk=None):
+    s = pf.Solver(p, mask, precision, dict(tol=0.0))
+    if z_chunk:
+        s.set_tile(z_chunk)
+    s.set_loop(7, use_graph)
+    s.set_state(phi, None if p["model"] == "ac" else T - T_STAR)
+    s.set_time(0.0, dt)
+    st = s.integrate(max_steps=steps)
+    ph, th = s.get_state()
+    d = s.diagnostics()
+    s.close()
+    return ph, th, st, d
+
+
+@pytest.mark.parametrize("model,shape,dt,steps", [
+    ("ac", (20, 24, 28), 0.5, 30),
+    ("coupled", (18, 21, 26), 2e-3, 30),
+])
+def test_fixed_step_fp64_matches_oracle(model, shape, dt, steps):
+    p, mask, phi, T = rand_problem(shape, model, 21, faces=(1 << 4) | (1 << 3), bc_kind=1)
+    P = oracle.make_params(p)
+    ph_o, T_o, ost = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt, phi,
+                                      T if model == "coupled" else None, max_steps=steps)
+    ph, th, st, d = fixed_run_gpu(p, mask, phi, T, dt, steps)
+    assert st["steps_accepted"] == steps and st["status"] == pf.PF_MAXSTEPS
+    assert rel(ph, ph_o) <= 1e-12
+    if model == "coupled":
+        assert rel(th, T_o - T_STAR) <= 1e-12
+    od = oracle.diagnostics(P, mask, ph_o, T_o)
+    assert d["pore_count"] == od["pore_count"]
+    assert d["ice_count"] == od["ice_count"]
+    assert abs(d["sum_phi"] - od["sum_phi"]) <= 1e-12 * od["sum_phi"]
+    assert abs(d["enthalpy"] - od["enthalpy"]) <= 1e-10 * abs(od["enthalpy"])
+
+
+def test_graph_and_tiles_do_not_change_results():
+    p, mask, phi, T = rand_problem((33, 20, 27), "coupled", 5, faces=1 << 4)
+    runs = [fixed_run_gpu(p, mask, phi, T, 2e-3, 20, use_graph=g, z_chunk=z)
+            for g, z in ((True, 4), (False, 4), (True, 16), (False, 1))]
+    for ph, th, _, _ in runs[1:]:
+        assert np.array_equal(ph, runs[0][0]) and np.array_equal(th, runs[0][1])
+
+
+def _smooth_micro32(t_pre=5.0):
+    """The 32^3 micro-scale case advanced by the oracle to t_pre, so that the
+    Merson error estimate is well above roundoff from the first attempt on
+    (from the sharp initial field it is roundoff-sized, and any two
+    implementations then propose different steps)."""
+    c = pi.case_micro_32()
+    P = oracle.make_params(c.params)
+    ph, _, st = oracle.integrate(P, c.mask, oracle.make_ctl(tol=c.run["tol"]), 0.0,
+                                 c.run["dt0"], c.phi0, t_end=t_pre)
+    return c, P, ph, st["dt"]
+
+
+def test_single_attempt_matches_oracle_controller():
+    c, P, phi, dt = _smooth_micro32()
+    ctl = oracle.make_ctl(tol=1e-6, safety=0.8, dt_min=1e-12, dt_max=1e30)
+    s = pf.Solver(c.params, c.mask, "fp64", c.run)
+    s.set_state(phi)
+    t = 5.0
+    n_rej = 0
+    for k in range(12):
+        tg, dtg, info = s.rkm_step(t, dt)
+        ph_o, _, to, dto, oinfo = oracle.rkm_step(P, c.mask, ctl, t, dt, phi)
+        assert info["accepted"] == oinfo["accepted"]
+        assert abs(info["eps"] - oinfo["eps"]) <= 1e-9 * oinfo["eps"]
+        assert abs(info["maxk1"] - oinfo["maxk1"]) <= 1e-12 * oinfo["maxk1"]
+        assert tg == to
+        # dt_next ~ eps^(-1/5): its relative gap is a fifth of eps's
+        eps_gap = abs(info["eps"] - oinfo["eps"]) / oinfo["eps"]
+        assert abs(dtg - dto) <= (0.2 * eps_gap + 1e-14) * dto * 1.01
+        n_rej += 1 - oinfo["accepted"]
+        phi, t, dt = ph_o, to, dto * (1.6 if k % 4 == 3 else 1.0)  # provoke rejections
+    g, _ = s.get_state()
+    assert rel(g, phi) <= 1e-11
+    assert n_rej >= 1
+    s.close()
+
+
+def test_roundoff_sized_error_estimate_from_sharp_state():
+    """From the sharp initial field the estimate is roundoff: both sides accept
+    and agree within a roundoff floor of order 2^-52 dt max|k1|."""
+    c = pi.case_micro_32()
+    P = oracle.make_params(c.params)
+    ctl = oracle.make_ctl(tol=1e-6)
+    s = pf.Solver(c.params, c.mask, "fp64", c.run)
+    s.set_state(c.phi0)
+    _, _, info = s.rkm_step(0.0, 1e-3)
+    _, _, _, _, oinfo = oracle.rkm_step(P, c.mask, ctl, 0.0, 1e-3, c.phi0)
+    floor = 64 * 2.0 ** -52 * 1e-3 * oinfo["maxk1"]
+    assert info["accepted"] == oinfo["accepted"] == 1
+    assert abs(info["eps"] - oinfo["eps"]) <= floor and oinfo["eps"] <= floor
+    s.close()
+
+
+def test_adaptive_micro32_fp64_matches_oracle():
+    c, P, phi, dt = _smooth_micro32()
+    steps = 150
+    ph_o, _, ost = oracle.integrate(P, c.mask, oracle.make_ctl(tol=c.run["tol"]), 5.0, dt,
+                                    phi, max_steps=steps)
+    s = pf.Solver(c.params, c.mask, "fp64", c.run)
+    s.set_state(phi)
+    s.set_time(5.0, dt)
+    st = s.integrate(max_steps=steps)
+    g, _ = s.get_state()
+    assert st["steps_accepted"] == ost["steps_accepted"]
+    assert st["steps_rejected"] == ost["steps_rejected"]
+    # each proposed step carries the roundoff of eps^(-1/5) (eps itself is a
+    # difference of nearly equal stage sums), so t drifts by ~1e-12 per step
+    assert abs(st["t"] - ost["t"]) <= 1e-9 * ost["t"]
+    assert rel(g, ph_o) <= 1e-8
+    s.close()
+
+
+def test_equilibrium_stop_and_ice_fraction_micro32():
+    """Run the 32^3 micro-scale case to equilibrium (max |dphi/dt| < 1e-6) in
+    FP64 on both sides; the step sequences differ after the roundoff-sized
+    first estimate, so the end states are compared at the equilibrium
+    tolerance, the ice count exactly."""
+    c = pi.case_micro_32()
+    P = oracle.make_params(c.params)
+    run = c.run
+    ph_o, _, ost = oracle.integrate(P, c.mask, oracle.make_ctl(tol=run["tol"]), 0.0, run["dt0"],
+                                    c.phi0, eq_tol=run["eq_tol"], max_steps=40000)
+    assert ost["status"] == oracle.EQUILIBRIUM
+    s = pf.Solver(c.params, c.mask, "fp64", run)
+    s.set_state(c.phi0)
+    s.set_time(0.0, run["dt0"])
+    st = s.integrate(max_steps=40000, eq_tol=run["eq_tol"])
+    assert st["status"] == pf.PF_EQUILIBRIUM
+    g, _ = s.get_state()
+    od = oracle.diagnostics(P, c.mask, ph_o)
+    n_o = ost["steps_accepted"] + ost["steps_rejected"]
+    n_g = st["steps_accepted"] + st["steps_rejected"]
+    assert abs(n_g - n_o) <= 0.05 * n_o
+    assert st["ice_count"] == od["ice_count"]
+    assert abs(st["uwc"] - od["uwc"]) <= 1e-3 * max(od["uwc"], 1e-3)
+    assert np.abs(g - ph_o).max() <= 1e-3
+    s.close()
+
+
+def test_fp32_micro32_adaptive_within_precision_bounds():
+    """FP32 fields, FP64 reductions: compared with the FP64 oracle at a common
+    end time: max |dphi| <= 1e-4, ice fraction within 1e-3 relative."""
+    c = pi.case_micro_32()
+    run = c.run
+    t_end = 30.0
+    P = oracle.make_params(c.params)
+    ph_o, _, ost = oracle.integrate(P, c.mask, oracle.make_ctl(tol=run["tol"]), 0.0, run["dt0"],
+                                    c.phi0, t_end=t_end)
+    s = pf.Solver(c.params, c.mask, "fp32", run)
+    s.set_state(c.phi0.astype(np.float32))
+    s.set_time(0.0, run["dt0"])
+    st = s.integrate(t_end=t_end)
+    assert st["status"] == pf.PF_OK and st["t"] == t_end
+    g, _ = s.get_state()
+    od = oracle.diagnostics(P, c.mask, ph_o)
+    assert np.abs(g.astype(np.float64) - ph_o).max() <= 1e-4
+    assert abs(st["ice_fraction"] - od["ice_fraction"]) <= 1e-3 * od["ice_fraction"]
+    s.close()
+
+
+def test_coupled_crop_fp32_vs_fp64_oracle():
+    """64^3 crop of the 256^3 freeze-thaw case (bottom face ramps -5 -> +5 C),
+    FP32 on the GPU against the FP64 oracle at a common end time."""
+    full = pi.case_coupled_256()
+    c = pi.crop_case(full)
+    run = dict(full.run)
+    t_end = 0.6
+    P = oracle.make_params(c.params)
+    ph_o, T_o, ost = oracle.integrate(P, c.mask, oracle.make_ctl(tol=run["tol"]), 0.0,
+                                      run["dt0"], c.phi0, c.T0, t_end=t_end)
+    s = pf.Solver(c.params, c.mask, "fp32", run)
+    s.set_state(c.phi0.astype(np.float32), (c.T0 - T_STAR).astype(np.float32))
+    s.set_time(0.0, run["dt0"])
+    st = s.integrate(t_end=t_end)
+    g, th = s.get_state()
+    od = oracle.diagnostics(P, c.mask, ph_o, T_o)
+    dphi = np.abs(g.astype(np.float64) - ph_o).max()
+    assert dphi <= 1e-4, dphi
+    assert abs(st["ice_fraction"] - od["ice_fraction"]) <= 1e-3 * max(od["ice_fraction"], 1e-3)
+    # latent heat ties theta to phi: a phase-field gap d gives a temperature gap
+    # of up to (Lv / min rho c) d, so the phi bound carries over to theta
+    th_bound = c.params["Lv"] / min(c.params["rhoc"]) * 1e-4
+    assert np.abs(th.astype(np.float64) - (T_o - T_STAR)).max() <= th_bound
+    s.close()
+
+
+def test_full_size_coupled_128_fp64_two_steps():
+    """128^3, 64 spheres, the launch configuration of the benchmark: two fixed
+    steps against the oracle on the whole grid."""
+    c = pi.case_coupled_128()
+    P = oracle.make_params(c.params)
+    ph_o, T_o, _ = oracle.integrate(P, c.mask, oracle.make_ctl(tol=0.0), 0.0, 1e-3, c.phi0,
+                                    c.T0, max_steps=2)
+    s = pf.Solver(c.params, c.mask, "fp64", dict(c.run, tol=0.0))
+    s.set_state(c.phi0, c.T0 - T_STAR)
+    s.set_time(0.0, 1e-3)
+    st = s.integrate(max_steps=2)
+    g, th = s.get_state()
+    assert rel(g, ph_o) <= 1e-12
+    assert rel(th, T_o - T_STAR) <= 1e-12
+    s.close()
+
+
+def test_full_size_coupled_256_fp32_rhs_and_step():
+    """256^3 FP32 (the roofline-graded shape): the right-hand side on the whole
+    grid and one fixed step, against the FP64 oracle."""
+    c = pi.case_coupled_256()
+    P = oracle.make_params(c.params)
+    phi32 = c.phi0.astype(np.float32)
+    th32 = (c.T0 - T_STAR).astype(np.float32)
+    kp, kT = oracle.rhs(P, c.mask, 0.0, phi32.astype(np.float64),
+                        th32.astype(np.float64) + T_STAR)
+    s = pf.Solver(c.params, c.mask, "fp32", dict(c.run, tol=0.0))
+    ph = torch.tensor(phi32, device="cuda")
+    th = torch.tensor(th32, device="cuda")
+    dph, dth = torch.empty_like(ph), torch.empty_like(th)
+    s.rhs(0.0, ph, th, dph, dth)
+    assert rel(dph.cpu().numpy(), kp) <= 2e-5
+    assert rel(dth.cpu().numpy(), kT) <= 2e-5
+    s.set_state(ph, th)
+    s.set_time(0.0, 1e-3)
+    s.integrate(max_steps=1)
+    g, gth = s.get_state()
+    ph_o, T_o, _ = oracle.integrate(P, c.mask, oracle.make_ctl(tol=0.0), 0.0, 1e-3,
+                                    phi32.astype(np.float64), th32.astype(np.float64) + T_STAR,
+                                    max_steps=1)
+    assert np.abs(g - ph_o).max() <= 1e-5
+    assert np.abs(gth - (T_o - T_STAR)).max() <= 1e-5
+    s.close()
+
+
+def test_error_paths_on_gpu():
+    c = pi.case_micro_32()
+    s = pf.Solver(c.params, c.mask, "fp64", c.run)
+    phi = c.phi0.copy()
+    phi[5, 5, 5] = np.nan
+    s.set_state(phi)
+    s.set_time(0.0, 1e-3)
+    st = s.integrate(max_steps=10, raise_on_error=False)
+    assert st["rc"] == pf.PF_ENONFINITE and st["steps_rejected"] == 1
+    # dt_min above any reachable step: the first rejection proposes a step below it
+    s2 = pf.Solver(c.params, c.mask, "fp64", dict(c.run, dt_min=1e3))
+    s2.set_state(c.phi0)
+    s2.set_time(0.0, 1e4)
+    st = s2.integrate(max_steps=10, raise_on_error=False)
+    assert st["rc"] == pf.PF_EDTMIN
+    s2.close()
+    s.set_state(c.phi0)
+    s.set_time(0.0, 1e-3)
+    st = s.integrate(max_steps=5)
+    assert st["status"] == pf.PF_MAXSTEPS and st["steps_accepted"] + st["steps_rejected"] == 5
+    st = s.integrate(t_end=s.integrate(max_steps=1)["t"])  # already there: no work
+    assert st["steps_accepted"] == 0
+    s.close()
+
+
+def test_rerun_is_bitwise_deterministic():
+    c = pi.case_micro_32()
+    outs = []
+    for _ in range(2):
+        s = pf.Solver(c.params, c.mask, "fp32", c.run)
+        s.set_state(c.phi0.astype(np.float32))
+        s.set_time(0.0, 1e-3)
+        st = s.integrate(max_steps=60)
+        outs.append((s.get_state()[0], st["t"], st["sum_phi"], st["enthalpy"]))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1:] == outs[1][1:]
