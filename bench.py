@@ -27,15 +27,22 @@ sys.path.insert(0, ROOT)
 METRIC = "GCUPS of fused RKM step (FP64/FP32); time-to-equilibrium warm vs cold start"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per cell of each fused stage pass, per unknown: words
-# read + written (S1: r y, w Y2 k1; S2: r Y2 k1, w Y3; S3: r Y3 y k1, w Y4 k3;
-# S4: r Y4 y k1 k3, w Y5 P C; S5: r Y5 P C, w y_new) plus the 1-byte
-# neighbourhood code.
-STAGE_WORDS = [3, 3, 5, 7, 4]
+# Algorithmic bytes per cell of each pass, per unknown: words read + written,
+# plus the 1-byte neighbourhood code.
+#  five-pass schedule: S1 r y, w Y2 k1 | S2 r Y2 k1, w Y3 | S3 r Y3 y k1, w Y4 k3
+#                      | S4 r Y4 y k1 k3, w Y5 P C | S5 r Y5 P C, w y_new
+#  paired schedule:    S1+S2 r y, w k1 Y3 | S3+S4 r Y3 y k1, w Y5 P C
+#                      | S5 r Y5 P C, w y_new
+PASS_WORDS = {"five": [3, 3, 5, 7, 4], "paired": [3, 6, 4]}
+PASS_NAMES = {"five": ["S1", "S2", "S3", "S4", "S5"], "paired": ["S1+S2", "S3+S4", "S5"]}
+PASS_KERNELS = {"five": ["stage_kernel<..,1>", "stage_kernel<..,2>", "stage_kernel<..,3>",
+                         "stage_kernel<..,4>", "stage_kernel<..,5>"],
+                "paired": ["pair_kernel<..,1,..>", "pair_kernel<..,3,..>",
+                           "stage_kernel<..,5>"]}
 
 
-def stage_bytes(nvar: int, esize: int):
-    return [w * nvar * esize + 1 for w in STAGE_WORDS]
+def pass_bytes(schedule: str, nvar: int, esize: int):
+    return [w * nvar * esize + 1 for w in PASS_WORDS[schedule]]
 
 
 WORKLOADS = {
@@ -51,12 +58,8 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2401_01672_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_2401_01672_amd.profiling import source_hash
+    return source_hash()
 
 
 def read_traffic(workload: str, kernel: str, src_hash: str):
@@ -88,6 +91,7 @@ def run_gpu(args, wl):
     run = dict(case.run)
     s = pf.Solver(case.params, case.mask, prec, run)
     s.set_loop(args.steps_per_poll, not args.no_graph)
+    s.set_schedule(args.schedule)
     if args.z_chunk:
         s.set_tile(args.z_chunk)
     s.set_state(case.phi0.astype(npdt), (case.T0 - case.params["t_star"]).astype(npdt))
@@ -107,33 +111,36 @@ def run_gpu(args, wl):
     gcups = ncell * attempts / wall / 1e9
     # per-kernel durations with HIP events on the library's stream
     ms = s.time_kernels(args.kernel_reps)
+    cfg = s.get_config()
+    sched = cfg["schedule"]
     esize = 8 if prec == "fp64" else 4
     nvar = 2 if case.model == "coupled" else 1
-    sb = stage_bytes(nvar, esize)
-    per_stage = []
-    for i in range(5):
+    sb = pass_bytes(sched, nvar, esize)
+    npass = len(sb)
+    per_pass = []
+    for i in range(npass):
         gbs = sb[i] * ncell / (ms[i] * 1e-3) / 1e9
-        per_stage.append(dict(stage=f"S{i + 1}", ms=round(ms[i], 5), bytes_per_cell=sb[i],
-                              gbs=round(gbs, 1)))
-    dom = max(range(5), key=lambda i: ms[i])
-    step_ms = sum(ms)
+        per_pass.append(dict(pass_=PASS_NAMES[sched][i], kernel=PASS_KERNELS[sched][i],
+                             ms=round(ms[i], 5), bytes_per_cell=sb[i], gbs=round(gbs, 1)))
+    dom = max(range(npass), key=lambda i: ms[i])
+    step_ms = sum(ms[:npass]) + ms[5]
     src_hash = kernel_source_hash()
-    kname = f"stage{dom + 1}"
+    kname = f"{sched}_pass{dom + 1}"
     traffic = read_traffic(args.workload, kname, src_hash)
-    achieved = per_stage[dom]["gbs"]
+    achieved = per_pass[dom]["gbs"]
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=f"stage_kernel S{dom + 1} ({prec}, {case.model})",
+                kernel=f"{PASS_KERNELS[sched][dom]} = {PASS_NAMES[sched][dom]} "
+                       f"({prec}, {case.model})",
                 algorithmic_bytes_per_launch=sb[dom] * ncell)
     extra = dict(
-        stages=per_stage,
+        passes=per_pass,
         step_kernels_ms=round(step_ms, 5),
         step_algorithmic_bytes_per_cell=sum(sb),
         step_effective_gbs=round(sum(sb) * ncell / (step_ms * 1e-3) / 1e9, 1),
         controller_ms=round(ms[5], 5),
         accepted=st["steps_accepted"], rejected=st["steps_rejected"], t_sim=st["t"],
-        ice_fraction=st["ice_fraction"], source_hash=src_hash,
-        z_chunk=s.get_tile()[0], workgroups=s.get_tile()[1],
+        ice_fraction=st["ice_fraction"], source_hash=src_hash, config=cfg,
     )
     s.close()
     return gcups, wall, roof, extra, case, prec
@@ -171,6 +178,7 @@ def main():
     ap.add_argument("--steps-per-poll", type=int, default=16)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--z-chunk", type=int, default=0)
+    ap.add_argument("--schedule", default="five", choices=["paired", "five"])
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")

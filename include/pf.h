@@ -200,9 +200,28 @@ int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph);
  * (>= 1); 0 = choose by the built-in autotuner on the next run. */
 int pf_set_tile(pf_handle* h, int32_t z_chunk);
 
-/* Current tile: *z_chunk receives the planes per workgroup column (after the
- * autotuner, if it has run) and *workgroups the stencil grid size. */
-int pf_get_tile(const pf_handle* h, int32_t* z_chunk, int32_t* workgroups);
+/* Stencil schedule of one attempt:
+ *   0 (default): five passes, one per Merson stage (each fused with its
+ *      combinations);
+ *   1: three passes -- S1+S2 and S3+S4 each in one pass (the first
+ *      stage of a pair is evaluated on the tile plus a one-cell ring and its
+ *      output stays in LDS), then S5.
+ * Both give the same arithmetic per cell.  Re-runs the tile autotuner. */
+int pf_set_schedule(pf_handle* h, int32_t schedule);
+
+/* Single-stage passes with four consecutive x1-cells per thread (default when
+ * n1 % 4 == 0; PF_EINVAL otherwise) or one cell per thread.  Same results. */
+int pf_set_vector(pf_handle* h, int32_t enable);
+
+/* Tile of the paired passes: tile_index 0: 64x4, 1: 64x8, 2: 32x8 cells of
+ * the x1-x2 plane per workgroup; z_chunk (>= 4) planes per column.  Turns the
+ * autotuner off. */
+int pf_set_pair_tile(pf_handle* h, int32_t tile_index, int32_t z_chunk);
+
+/* Current configuration, out[0..7] = {schedule, passes per attempt,
+ * single-stage z_chunk, single-stage workgroups, pair tile x, pair tile y,
+ * pair z_chunk, pair workgroups} (after the autotuner, if it has run). */
+int pf_get_config(const pf_handle* h, int32_t* out);
 
 /* Time each kernel of one attempt from the current state and step: every
  * kernel is launched reps times back to back between two HIP events on the

@@ -77,7 +77,10 @@ SIGNATURES = [
     ("pf_diagnostics", C.c_int, [_H, C.POINTER(PFRunStats)]),
     ("pf_set_loop", C.c_int, [_H, C.c_int32, C.c_int32]),
     ("pf_set_tile", C.c_int, [_H, C.c_int32]),
-    ("pf_get_tile", C.c_int, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("pf_set_schedule", C.c_int, [_H, C.c_int32]),
+    ("pf_set_pair_tile", C.c_int, [_H, C.c_int32, C.c_int32]),
+    ("pf_set_vector", C.c_int, [_H, C.c_int32]),
+    ("pf_get_config", C.c_int, [_H, C.POINTER(C.c_int32)]),
     ("pf_time_kernels", C.c_int, [_H, C.c_int32, C.POINTER(C.c_double)]),
     ("pf_synchronize", C.c_int, [_H]),
     ("pf_num_cells", C.c_int64, [_H]),
@@ -261,10 +264,23 @@ class Solver:
     def set_tile(self, z_chunk: int):
         self._check(lib().pf_set_tile(self.h, int(z_chunk)))
 
-    def get_tile(self):
-        z, w = C.c_int32(), C.c_int32()
-        self._check(lib().pf_get_tile(self.h, C.byref(z), C.byref(w)))
-        return z.value, w.value
+    def set_schedule(self, schedule: str):
+        """'five' (one pass per stage) or 'paired' (S1+S2, S3+S4, S5)."""
+        self._check(lib().pf_set_schedule(self.h, {"five": 0, "paired": 1}[schedule]))
+
+    def set_vector(self, enable: bool):
+        self._check(lib().pf_set_vector(self.h, 1 if enable else 0))
+
+    def set_pair_tile(self, tile_index: int, z_chunk: int):
+        self._check(lib().pf_set_pair_tile(self.h, int(tile_index), int(z_chunk)))
+
+    def get_config(self) -> Dict:
+        out = (C.c_int32 * 8)()
+        self._check(lib().pf_get_config(self.h, out))
+        v = list(out)
+        return dict(schedule={0: "five", 1: "paired"}[v[0]], passes=v[1], z_chunk=v[2],
+                    workgroups=v[3], pair_tile=(v[4], v[5]), pair_z_chunk=v[6],
+                    pair_workgroups=v[7])
 
     def time_kernels(self, reps: int = 10):
         out = (C.c_double * 6)()

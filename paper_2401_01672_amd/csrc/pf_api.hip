@@ -41,8 +41,12 @@ struct pf_handle {
   double* diag_out = nullptr;
   DevCtl* ctl = nullptr;   // device
   DevCtl* hctl = nullptr;  // pinned host mirror
-  int z_chunk = 16;
+  int sched = pf::kSchedFive;
+  int vec = 0;  // four-cells-per-thread stage kernels (n1 % 4 == 0)
+  int z_chunk = 16;  // single-stage passes
   int tiles_p = 0, tiles_z = 0, nparts = 0, max_parts = 0;
+  int pair_ts = 1, pair_zc = 16;  // paired passes: tile shape index, planes per column
+  int ptx = 0, pty = 0, ptz = 0, npair = 0;
   int autotune_pending = 1;
   int steps_per_poll = 16;
   int use_graph = 1;
@@ -142,6 +146,7 @@ StageArgs stage_args(const pf_handle* h, int stage) {
   a.z_chunk = h->z_chunk;
   a.tiles_p = h->tiles_p;
   a.tiles_z = h->tiles_z;
+  a.vec = h->vec;
   for (int v = 0; v < 2; ++v) {
     a.y[0][v] = h->y[0][v];
     a.y[1][v] = h->y[1][v];
@@ -162,13 +167,72 @@ StageArgs stage_args(const pf_handle* h, int stage) {
   return a;
 }
 
+pf::PairArgs pair_args(const pf_handle* h, int first) {
+  pf::PairArgs a;
+  memset(&a, 0, sizeof(a));
+  a.code = h->code;
+  a.ctl = h->ctl;
+  a.mc = h->mc;
+  a.z_chunk = h->pair_zc;
+  a.tiles_x = h->ptx;
+  a.tiles_y = h->pty;
+  a.tiles_z = h->ptz;
+  for (int v = 0; v < 2; ++v) {
+    a.y[0][v] = h->y[0][v];
+    a.y[1][v] = h->y[1][v];
+    a.k1[v] = h->k1[v];
+    if (first == 1) {
+      a.out_a[v] = h->b[v];  // Y3
+    } else {
+      a.in[v] = h->b[v];     // Y3
+      a.out_a[v] = h->a[v];  // Y5
+      a.out_p[v] = h->k3[v]; // P
+    }
+  }
+  a.part = first == 1 ? h->part1 : nullptr;
+  return a;
+}
+
+// S5 of the paired schedule: input Y5 in A, P in K3, C in the y_new slot.
+StageArgs s5_paired_args(const pf_handle* h) {
+  StageArgs a = stage_args(h, 5);
+  for (int v = 0; v < 2; ++v) a.in[v] = h->a[v];
+  a.c_from_out = 1;
+  return a;
+}
+
+// Launch pass i (0-based) of one attempt under the handle's schedule;
+// returns hipErrorInvalidValue past the last pass.
+hipError_t issue_pass(const pf_handle* h, int i, hipStream_t s) {
+  if (h->sched == pf::kSchedFive) {
+    if (i >= 5) return hipErrorInvalidValue;
+    StageArgs a = stage_args(h, i + 1);
+    return pf::launch_stage(h->P.precision, h->P.model, i + 1, a, s);
+  }
+  if (i == 0 || i == 1) {
+    pf::PairArgs a = pair_args(h, i == 0 ? 1 : 3);
+    return pf::launch_pair(h->P.precision, h->P.model, i == 0 ? 1 : 3, h->pair_ts, a, s);
+  }
+  if (i == 2) {
+    StageArgs a = s5_paired_args(h);
+    return pf::launch_stage(h->P.precision, h->P.model, 5, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int num_passes(const pf_handle* h) { return h->sched == pf::kSchedFive ? 5 : 3; }
+
+hipError_t launch_ctl(const pf_handle* h, DevCtl* ctl, hipStream_t s) {
+  const int np1 = h->sched == pf::kSchedFive ? h->nparts : h->npair;
+  return pf::launch_controller(ctl, h->part1, np1, h->part5, h->nparts, h->mc.h3, s);
+}
+
 hipError_t issue_step(const pf_handle* h, hipStream_t s) {
-  for (int st = 1; st <= 5; ++st) {
-    StageArgs a = stage_args(h, st);
-    hipError_t e = pf::launch_stage(h->P.precision, h->P.model, st, a, s);
+  for (int i = 0; i < num_passes(h); ++i) {
+    hipError_t e = issue_pass(h, i, s);
     if (e != hipSuccess) return e;
   }
-  return pf::launch_controller(h->ctl, h->part1, h->part5, h->nparts, h->mc.h3, s);
+  return launch_ctl(h, h->ctl, s);
 }
 
 void drop_graph(pf_handle* h) {
@@ -183,12 +247,29 @@ int set_tiles(pf_handle* h, int zc) {
   if (zc < 1) zc = 1;
   if (zc > h->P.n3) zc = h->P.n3;
   int tp, tz;
-  int nb = pf::grid_blocks(h->mc, zc, &tp, &tz);
+  int nb = pf::grid_blocks(h->mc, zc, h->vec, &tp, &tz);
   if (nb > h->max_parts) return fail(h, PF_EINVAL, "tile choice exceeds partial buffer");
   h->z_chunk = zc;
   h->tiles_p = tp;
   h->tiles_z = tz;
   h->nparts = nb;
+  drop_graph(h);
+  return PF_OK;
+}
+
+int set_pair_tiles(pf_handle* h, int ts, int zc) {
+  if (ts < 0 || ts > 2) return fail(h, PF_EINVAL, "pair tile index out of range");
+  if (zc < 4) zc = 4;
+  if (zc > h->P.n3) zc = h->P.n3;
+  int tx, ty, tz;
+  int nb = pf::pair_blocks(h->mc, ts, zc, &tx, &ty, &tz);
+  if (nb > h->max_parts) return fail(h, PF_EINVAL, "pair tile choice exceeds partial buffer");
+  h->pair_ts = ts;
+  h->pair_zc = zc;
+  h->ptx = tx;
+  h->pty = ty;
+  h->ptz = tz;
+  h->npair = nb;
   drop_graph(h);
   return PF_OK;
 }
@@ -228,7 +309,6 @@ int pull_ctl(pf_handle* h) {
 // fastest.
 int autotune(pf_handle* h) {
   h->autotune_pending = 0;
-  const int cands[] = {4, 8, 16, 32, 64};
   DevCtl& c = *h->hctl;
   init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
   if (!(c.dt_att > 0) || !(c.dt_att < INFINITY)) c.dt_att = 1e-12;
@@ -237,32 +317,76 @@ int autotune(pf_handle* h) {
   hipEvent_t e0, e1;
   PF_HIP(h, hipEventCreate(&e0));
   PF_HIP(h, hipEventCreate(&e1));
-  int best = h->z_chunk;
-  float best_ms = 1e30f;
-  for (int zc : cands) {
-    if (zc > h->P.n3 && zc != cands[0]) continue;
-    if (set_tiles(h, zc)) continue;
+  // mean of two timed repetitions after one warm-up
+  auto timed = [&](auto&& launch, float* out) -> int {
     float tot = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
       PF_HIP(h, hipEventRecord(e0, h->stream));
-      for (int st = 1; st <= 5; ++st) {
-        StageArgs a = stage_args(h, st);
-        PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
-      }
+      PF_HIP(h, launch());
       PF_HIP(h, hipEventRecord(e1, h->stream));
       PF_HIP(h, hipEventSynchronize(e1));
       float ms = 0;
       PF_HIP(h, hipEventElapsedTime(&ms, e0, e1));
-      if (rep > 0) tot += ms;  // first repetition warms caches and code
+      if (rep > 0) tot += ms;
     }
-    if (tot < best_ms) {
-      best_ms = tot;
+    *out = tot;
+    return PF_OK;
+  };
+  // (1) planes per column of the single-stage passes
+  const int zcands[] = {1, 2, 4, 8, 16, 32};
+  int best = h->z_chunk;
+  float best_ms = 1e30f;
+  for (int zc : zcands) {
+    if (zc > h->P.n3 && zc != zcands[0]) continue;
+    if (set_tiles(h, zc)) continue;
+    float ms;
+    rc = timed([&]() -> hipError_t {
+      for (int st = 1; st <= 5; ++st) {
+        StageArgs a = stage_args(h, st);
+        hipError_t e = pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }, &ms);
+    if (rc) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
       best = zc;
     }
   }
+  rc = set_tiles(h, best);
+  if (rc) return rc;
+  // (2) tile shape and planes per column of the paired passes
+  if (h->sched == pf::kSchedPaired) {
+    const int pz[] = {8, 16, 32, 64};
+    int bts = h->pair_ts, bzc = h->pair_zc;
+    best_ms = 1e30f;
+    for (int ts = 0; ts < 3; ++ts) {
+      for (int zc : pz) {
+        if (zc > h->P.n3 && zc != pz[0]) continue;
+        if (set_pair_tiles(h, ts, zc)) continue;
+        float ms;
+        rc = timed([&]() -> hipError_t {
+          for (int i = 0; i < 2; ++i) {
+            hipError_t e = issue_pass(h, i, h->stream);
+            if (e != hipSuccess) return e;
+          }
+          return hipSuccess;
+        }, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+          best_ms = ms;
+          bts = ts;
+          bzc = zc;
+        }
+      }
+    }
+    rc = set_pair_tiles(h, bts, bzc);
+    if (rc) return rc;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return set_tiles(h, best);
+  return PF_OK;
 }
 
 }  // namespace
@@ -288,6 +412,7 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
   h->ncell = (long long)params->n1 * params->n2 * params->n3;
   h->esize = params->precision == PF_FP64 ? 8 : 4;
   h->nvar = params->model == PF_MODEL_COUPLED ? 2 : 1;
+  h->vec = params->n1 % 4 == 0 ? 1 : 0;
   h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
 
   auto bail = [&](int code, const std::string& msg) {
@@ -301,7 +426,12 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
 
   // maximum number of workgroups over all tile choices (z_chunk >= 1)
   int tp, tz;
-  h->max_parts = pf::grid_blocks(h->mc, 1, &tp, &tz);
+  h->max_parts = pf::grid_blocks(h->mc, 1, 0, &tp, &tz);  // scalar grid bounds the vector one
+  for (int ts = 0; ts < 3; ++ts) {
+    int tx, ty, tzz;
+    const int nb = pf::pair_blocks(h->mc, ts, 4, &tx, &ty, &tzz);
+    if (nb > h->max_parts) h->max_parts = nb;
+  }
   const size_t field = ((size_t)h->ncell * h->esize + 255) & ~(size_t)255;
   const size_t code_bytes = ((size_t)h->ncell + 255) & ~(size_t)255;
   const size_t part_bytes = (((size_t)h->max_parts * (pf::kPartS1 + pf::kPartS5) + 64) *
@@ -338,6 +468,7 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
   if (e != hipSuccess) return bail(PF_EHIP, std::string("setup: ") + hipGetErrorString(e));
   int zc = params->n3 >= 256 ? 32 : 16;
   if (set_tiles(h, zc)) return bail(PF_EINVAL, h->err);
+  if (set_pair_tiles(h, params->n1 >= 64 ? 1 : 2, 16)) return bail(PF_EINVAL, h->err);
   init_ctl(h, *h->hctl, INFINITY, 0, 0.0);
   h->hctl->done = 1;
   if (push_ctl(h) || hipStreamSynchronize(h->stream) != hipSuccess)
@@ -419,8 +550,23 @@ int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dph
   a.in[1] = theta;
   a.out[0] = dphi;
   a.out[1] = dtheta;
+  // caller buffers: the four-cell kernel needs 16-byte aligned fields
+  auto aligned = [](const void* q) { return ((uintptr_t)q & 15u) == 0; };
+  if (a.vec && !(aligned(phi) && aligned(dphi) && (h->nvar == 1 || (aligned(theta) &&
+                                                                    aligned(dtheta))))) {
+    a.vec = 0;
+    pf::grid_blocks(h->mc, h->z_chunk, 0, &a.tiles_p, &a.tiles_z);
+  }
   PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, h->stream));
   return PF_OK;
+}
+
+int pf_set_vector(pf_handle* h, int32_t enable) {
+  if (!h) return PF_EINVAL;
+  if (enable && h->P.n1 % 4 != 0)
+    return fail(h, PF_EINVAL, "four-cell kernels need n1 divisible by 4");
+  h->vec = enable ? 1 : 0;
+  return set_tiles(h, h->z_chunk);
 }
 
 int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info) {
@@ -474,13 +620,6 @@ int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph) {
   h->steps_per_poll = steps_per_poll;
   h->use_graph = use_graph ? 1 : 0;
   drop_graph(h);
-  return PF_OK;
-}
-
-int pf_get_tile(const pf_handle* h, int32_t* z_chunk, int32_t* workgroups) {
-  if (!h || !z_chunk || !workgroups) return PF_EINVAL;
-  *z_chunk = h->z_chunk;
-  *workgroups = h->nparts;
   return PF_OK;
 }
 
@@ -575,35 +714,61 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
   hipEvent_t e0, e1;
   PF_HIP(h, hipEventCreate(&e0));
   PF_HIP(h, hipEventCreate(&e1));
-  for (int st = 1; st <= 6; ++st) {
-    StageArgs a = stage_args(h, st <= 5 ? st : 5);
-    // warm-up launch, then the timed batch
-    if (st <= 5) PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
+  for (int i = 0; i < 6; ++i) ms[i] = 0.0;
+  const int np = num_passes(h);
+  for (int i = 0; i < np; ++i) {
+    // passes run in schedule order, so each one reads its predecessor's output
+    PF_HIP(h, issue_pass(h, i, h->stream));  // warm-up
     PF_HIP(h, hipEventRecord(e0, h->stream));
-    for (int r = 0; r < reps; ++r) {
-      if (st <= 5) {
-        PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
-      } else {
-        // controller timing on a copy of the control block
-        PF_HIP(h, pf::launch_controller(h->ctl + 1, h->part1, h->part5, h->nparts, h->mc.h3,
-                                        h->stream));
-      }
-    }
+    for (int r = 0; r < reps; ++r) PF_HIP(h, issue_pass(h, i, h->stream));
     PF_HIP(h, hipEventRecord(e1, h->stream));
     PF_HIP(h, hipEventSynchronize(e1));
     float x = 0;
     PF_HIP(h, hipEventElapsedTime(&x, e0, e1));
-    ms[st - 1] = (double)x / reps;
-    if (st == 5) {
-      // arm the scratch control block used for the controller timing
-      DevCtl cc = c;
-      cc.done = 0;
-      PF_HIP(h, hipMemcpyAsync(h->ctl + 1, &cc, sizeof(DevCtl), hipMemcpyHostToDevice, h->stream));
-      PF_HIP(h, hipStreamSynchronize(h->stream));
-    }
+    ms[i] = (double)x / reps;
   }
+  // controller, on a scratch copy of the control block
+  DevCtl cc = c;
+  cc.done = 0;
+  PF_HIP(h, hipMemcpyAsync(h->ctl + 1, &cc, sizeof(DevCtl), hipMemcpyHostToDevice, h->stream));
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  PF_HIP(h, hipEventRecord(e0, h->stream));
+  for (int r = 0; r < reps; ++r) PF_HIP(h, launch_ctl(h, h->ctl + 1, h->stream));
+  PF_HIP(h, hipEventRecord(e1, h->stream));
+  PF_HIP(h, hipEventSynchronize(e1));
+  float x = 0;
+  PF_HIP(h, hipEventElapsedTime(&x, e0, e1));
+  ms[5] = (double)x / reps;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return PF_OK;
+}
+
+int pf_set_schedule(pf_handle* h, int32_t schedule) {
+  if (!h || (schedule != pf::kSchedFive && schedule != pf::kSchedPaired)) return PF_EINVAL;
+  h->sched = schedule;
+  h->autotune_pending = 1;
+  drop_graph(h);
+  return PF_OK;
+}
+
+int pf_set_pair_tile(pf_handle* h, int32_t tile_index, int32_t z_chunk) {
+  if (!h || tile_index < 0 || tile_index > 2 || z_chunk < 1) return PF_EINVAL;
+  h->autotune_pending = 0;
+  return set_pair_tiles(h, tile_index, z_chunk);
+}
+
+int pf_get_config(const pf_handle* h, int32_t* out) {
+  if (!h || !out) return PF_EINVAL;
+  const int tsi = h->pair_ts;
+  out[0] = h->sched;
+  out[1] = num_passes(h);
+  out[2] = h->z_chunk;
+  out[3] = h->nparts;
+  out[4] = pf::kPairTiles[tsi][0];
+  out[5] = pf::kPairTiles[tsi][1];
+  out[6] = h->pair_zc;
+  out[7] = h->npair;
   return PF_OK;
 }
 

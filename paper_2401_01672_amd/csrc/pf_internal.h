@@ -87,8 +87,30 @@ struct StageArgs {
   int z_chunk;
   int tiles_p, tiles_z;  // workgroup grid: plane tiles x z chunks
   int ignore_done;       // standalone RHS: ignore ctl
+  int c_from_out;        // S5: C is read from the y_new slot (paired schedule)
+  int vec;               // 1: four x1-cells per thread (needs n1 % 4 == 0)
   double t_fixed;        // standalone RHS time
 };
+
+// Arguments of a paired-stage kernel (S1+S2 or S3+S4 in one pass; see
+// pf_stencil.hip).  Buffers per variable v.
+struct PairArgs {
+  const uint8_t* code;
+  DevCtl* ctl;
+  double* part;          // S1 partial reductions (first pair only)
+  const void* y[2][2];   // both state buffers
+  const void* in[2];     // second pair: Y3 (stencil input of S3)
+  void* k1[2];           // first pair writes k1, second pair reads it
+  void* out_a[2];        // first pair: Y3; second pair: Y5
+  void* out_p[2];        // second pair: P
+  ModelConst mc;
+  int z_chunk;
+  int tiles_x, tiles_y, tiles_z;
+};
+
+// Stencil schedules of one attempt.
+constexpr int kSchedFive = 0;    // S1..S5, one pass each
+constexpr int kSchedPaired = 1;  // (S1+S2), (S3+S4), S5
 
 // Partial-reduction slots per workgroup.
 constexpr int kPartS1 = 4;  // max |k1_phi| (water), sum phi (water), enthalpy sum, ice count
@@ -102,10 +124,15 @@ hipError_t launch_build_code(const uint8_t* mask, uint8_t* code, int n1, int n2,
                              hipStream_t s);
 hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a,
                         hipStream_t s);
-hipError_t launch_controller(DevCtl* ctl, const double* part1, const double* part5,
-                             int nparts, double h3, hipStream_t s);
+hipError_t launch_controller(DevCtl* ctl, const double* part1, int np1, const double* part5,
+                             int np5, double h3, hipStream_t s);
 hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* phi,
                        const void* th, const ModelConst& m, long long n, double* part,
                        int nparts, double* out4, hipStream_t s);
-int grid_blocks(const ModelConst& mc, int z_chunk, int* tiles_p, int* tiles_z);
+int grid_blocks(const ModelConst& mc, int z_chunk, int vec, int* tiles_p, int* tiles_z);
+// paired kernels: tile shape index ts selects (TX, TY) from kPairTiles
+constexpr int kPairTiles[3][2] = {{64, 4}, {64, 8}, {32, 8}};
+int pair_blocks(const ModelConst& mc, int ts, int z_chunk, int* tx, int* ty, int* tz);
+hipError_t launch_pair(int precision, int model, int first, int ts, const PairArgs& a,
+                       hipStream_t s);
 }  // namespace pf

@@ -107,10 +107,41 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&ops)[N
 // ---------------------------------------------------------------------------
 // Right-hand side of one cell.
 
+// x if bit f of code is set, else +0: a sign-extended bit field used as an
+// and-mask (two VALU operations, no compare/select).
+__device__ __forceinline__ float keep_if_bit(unsigned code, int f, float x) {
+  const int msk = ((int)(code << (31 - f))) >> 31;
+  return __int_as_float(__float_as_int(x) & msk);
+}
+__device__ __forceinline__ double keep_if_bit(unsigned code, int f, double x) {
+  const long long msk = (long long)(((int)(code << (31 - f))) >> 31);
+  return __longlong_as_double(__double_as_longlong(x) & msk);
+}
+
+// Sigma limiter with the clamp as one med3 (FP32); s = w inv - e0 inv.
+__device__ __forceinline__ float limiter_fast(float w, float inv, float e0inv) {
+  const float s = __builtin_amdgcn_fmed3f(fmaf(w, inv, -e0inv), 0.0f, 1.0f);
+  return s * s * fmaf(-2.0f, s, 3.0f);
+}
+__device__ __forceinline__ double limiter_fast(double w, double inv, double e0inv) {
+  double s = w * inv - e0inv;
+  s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+  return s * s * (3.0 - 2.0 * s);
+}
+
+__device__ __forceinline__ float div_fast(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);  // ~1 ulp: far inside the FP32 error budget
+}
+__device__ __forceinline__ double div_fast(double a, double b) { return a / b; }  // IEEE
+
 template <typename R, int MODEL>
 struct CellRHS {
-  // phn/thn: neighbour values through faces 0..5 (clamped to the cell itself
-  // when the face is on the boundary).  inb: bit f = face f has a neighbour.
+  // phn/thn: neighbour values through faces 0..5.  Precondition: for a face
+  // on the domain boundary thn[f] == thc (the caller passes the cell's own
+  // value), so an insulated face contributes exactly zero with no select;
+  // the Dirichlet faces (dirf) among the boundary faces (bits of ~inb) add
+  // 2 lambda_c (2 theta_D - theta_c - theta_c) each.  Bit f of code: the
+  // neighbour through face f exists and is water.
   __device__ __forceinline__ static void eval(const ModelConst& m, R phic, R thc,
                                               const R (&phn)[6], const R (&thn)[6],
                                               unsigned code, unsigned inb, unsigned dirf,
@@ -118,28 +149,25 @@ struct CellRHS {
     const bool glass = code & kGlassBit;
     R lap = R(0);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) lap += ((code >> f) & 1u) ? (phn[f] - phic) : R(0);
-    if (glass) lap = R(0);
-    const R sa = limiter<R>(phic, R(m.e0), R(m.inv_de));
-    const R sb = limiter<R>(R(1) - phic, R(m.e0), R(m.inv_de));
+    for (int f = 0; f < 6; ++f) lap += keep_if_bit(code, f, phn[f] - phic);
+    const R sa = limiter_fast(phic, R(m.inv_de), R(m.e0 * m.inv_de));
+    const R sb = limiter_fast(R(1) - phic, R(m.inv_de), R(m.e0 * m.inv_de));
     const R drive = (MODEL == PF_MODEL_AC) ? R(m.betaAC) : R(m.beta0) * (-thc);
     const R f = R(2) * phic * (R(1) - phic) * (phic - R(0.5) + drive * sa * sb);
-    const R iw = glass ? R(m.iw_glass) : R(1);
-    kphi = iw * (R(m.cL) * lap + R(m.cR) * f);
+    // glass: no phase-field flux and the water indicator of glass
+    kphi = glass ? R(m.iw_glass) * (R(m.cR) * f) : R(m.cL) * lap + R(m.cR) * f;
     if (MODEL == PF_MODEL_COUPLED) {
       const R lamc = glass ? R(m.lamG) : R(m.lamL) + phic * R(m.dlam);
       R qq = R(0);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
-        const bool in = (inb >> f) & 1u;
-        const bool nbw = (code >> f) & 1u;
-        const R lamn = nbw ? R(m.lamL) + phn[f] * R(m.dlam) : R(m.lamG);
-        const R w = in ? (lamc + lamn) : (((dirf >> f) & 1u) ? R(4) * lamc : R(0));
-        const R tgt = in ? thn[f] : thD;
-        qq += w * (tgt - thc);
+        const R lamn = ((code >> f) & 1u) ? R(m.lamL) + phn[f] * R(m.dlam) : R(m.lamG);
+        qq += (lamc + lamn) * (thn[f] - thc);
       }
+      const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
+      if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
       const R rc = glass ? R(m.rcG) : R(m.rcL) + phic * R(m.drc);
-      kth = (R(0.5) * R(m.cH) * qq + R(m.Lv) * kphi) / rc;
+      kth = div_fast(R(0.5) * R(m.cH) * qq + R(m.Lv) * kphi, rc);
     } else {
       kth = R(0);
     }
@@ -189,6 +217,14 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
   if (STAGE == 1) {  // S1's stencil input is the state itself
     inP = yP;
     inT = yT;
+  }
+  if (STAGE == 5 && a.c_from_out) {
+    // paired schedule: P lives in K3 and C in the y_new slot, which the pass
+    // overwrites in place (each cell reads its C before writing y_new)
+    k1P = k3P;
+    k1T = k3T;
+    k3P = oP;
+    k3T = oT;
   }
   const R rdt = R(dt);
 
@@ -336,18 +372,18 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
 // the device step control (Sec. 2.5; semantics in pf.h).
 
 __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const double* p1,
-                                                         const double* p5, int np,
+                                                         int np1, const double* p5, int np5,
                                                          double h3) {
   __shared__ double smem[8 * kWaves];
   if (ctl->done) return;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+  for (int i = threadIdx.x; i < np1; i += blockDim.x) {
     v[0] = dmax_nf(v[0], p1[(size_t)i * kPartS1 + 0]);
     v[1] += p1[(size_t)i * kPartS1 + 1];
     v[2] += p1[(size_t)i * kPartS1 + 2];
     v[3] += p1[(size_t)i * kPartS1 + 3];
-    v[4] = dmax_nf(v[4], p5[i]);
   }
+  for (int i = threadIdx.x; i < np5; i += blockDim.x) v[4] = dmax_nf(v[4], p5[i]);
   const int ops[5] = {1, 0, 0, 0, 1};
   block_reduce<5>(v, ops, smem);
   if (threadIdx.x != 0) return;
@@ -483,11 +519,559 @@ __global__ void build_code_kernel(const uint8_t* mask, uint8_t* code, int n1, in
 }
 
 // ---------------------------------------------------------------------------
+// Vectorised stage kernel: each thread owns four consecutive x1-cells (one
+// 16-byte FP32 load per field and plane, two for FP64), so address
+// arithmetic and load issue are shared by four cells.  The x1 neighbours of
+// the four cells come from the thread's own registers and from the adjacent
+// lanes (shuffles); only a lane whose neighbour sits in another wavefront
+// loads it.  Needs n1 % 4 == 0 (each quad lies in one x1 row).  Same
+// arithmetic per cell as stage_kernel.
+
+template <typename R>
+struct Quad {
+  R v[4];
+};
+
+template <typename R>
+__device__ __forceinline__ Quad<R> ldq(const R* base, uint32_t idx) {
+  Quad<R> q;
+  if constexpr (sizeof(R) == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(base + idx);
+    q.v[0] = t.x;
+    q.v[1] = t.y;
+    q.v[2] = t.z;
+    q.v[3] = t.w;
+  } else {
+    const double2 t0 = *reinterpret_cast<const double2*>(base + idx);
+    const double2 t1 = *reinterpret_cast<const double2*>(base + idx + 2);
+    q.v[0] = t0.x;
+    q.v[1] = t0.y;
+    q.v[2] = t1.x;
+    q.v[3] = t1.y;
+  }
+  return q;
+}
+
+template <typename R>
+__device__ __forceinline__ void stq(R* base, uint32_t idx, const Quad<R>& q) {
+  if constexpr (sizeof(R) == 4) {
+    *reinterpret_cast<float4*>(base + idx) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+  } else {
+    *reinterpret_cast<double2*>(base + idx) = make_double2(q.v[0], q.v[1]);
+    *reinterpret_cast<double2*>(base + idx + 2) = make_double2(q.v[2], q.v[3]);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R shfl_up1(R v) {
+  return __shfl_up(v, 1, 64);
+}
+template <typename R>
+__device__ __forceinline__ R shfl_down1(R v) {
+  return __shfl_down(v, 1, 64);
+}
+
+template <typename R, int MODEL, int STAGE>
+__global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
+  __shared__ double smem[8 * kWaves];
+  const ModelConst& m = a.mc;
+  double t0 = a.t_fixed, dt = 0.0;
+  int cur = 0;
+  if (!a.ignore_done) {
+    if (a.ctl->done) return;
+    t0 = a.ctl->t;
+    dt = a.ctl->dt_att;
+    cur = a.ctl->cur;
+  }
+  constexpr double cs = STAGE == 2 ? 1.0 / 3.0 : STAGE == 3 ? 1.0 / 3.0 : STAGE == 4 ? 0.5
+                        : STAGE == 5 ? 1.0 : 0.0;
+  const R thD = R(dirichlet_theta(m, t0 + cs * dt));
+  constexpr bool kCoupled = MODEL == PF_MODEL_COUPLED;
+  constexpr int NV = kCoupled ? 2 : 1;
+
+  const int nblk = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x, nblk);
+  const int tp = tile % a.tiles_p, tz = tile / a.tiles_p;
+  const uint32_t plane = (uint32_t)m.n1 * (uint32_t)m.n2;
+  const uint32_t p = ((uint32_t)tp * kBlock + threadIdx.x) * 4u;
+  const bool active = p < plane;
+  const int z0 = tz * a.z_chunk;
+  const int z1 = min(z0 + a.z_chunk, m.n3);
+  const int lane = threadIdx.x & 63;
+
+  const R* in[2] = {static_cast<const R*>(a.in[0]), static_cast<const R*>(a.in[1])};
+  const R* yv[2] = {static_cast<const R*>(a.y[cur][0]), static_cast<const R*>(a.y[cur][1])};
+  R* k1[2] = {static_cast<R*>(a.k1[0]), static_cast<R*>(a.k1[1])};
+  R* k3[2] = {static_cast<R*>(a.k3[0]), static_cast<R*>(a.k3[1])};
+  R* out[2] = {static_cast<R*>(STAGE == 5 ? a.out_y[1 - cur][0] : a.out[0]),
+               static_cast<R*>(STAGE == 5 ? a.out_y[1 - cur][1] : a.out[1])};
+  if (STAGE == 1) {
+    in[0] = yv[0];
+    in[1] = yv[1];
+  }
+  if (STAGE == 5 && a.c_from_out) {  // paired schedule: P in K3, C in the y_new slot
+    k1[0] = k3[0];
+    k1[1] = k3[1];
+    k3[0] = out[0];
+    k3[1] = out[1];
+  }
+  const R rdt = R(dt);
+
+  double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
+  // the quad's position (n1 % 4 == 0: all four cells share i2)
+  const uint32_t i1 = active ? p % (uint32_t)m.n1 : 0u;
+  const uint32_t i2 = active ? p / (uint32_t)m.n1 : 0u;
+  const bool xm_in = i1 > 0, xp_in = i1 + 4 < (uint32_t)m.n1;
+  const bool ym_in = i2 > 0, yp_in = i2 + 1 < (uint32_t)m.n2;
+  // lanes whose x-neighbour quad lives in another wavefront (or is inactive)
+  const bool xm_remote = xm_in && (lane == 0);
+  const bool xp_remote = xp_in && (lane == 63 || p + 4 >= plane);
+  const unsigned dirf = (unsigned)m.dirichlet_faces;
+
+  Quad<R> cm[2], cc[2], cp[2];
+  uint32_t n = p + plane * (uint32_t)z0;
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      cc[v] = ldq(in[v], n);
+      cm[v] = z0 > 0 ? ldq(in[v], n - plane) : cc[v];
+    }
+  }
+  for (int z = z0; z < z1; ++z, n += plane) {
+    const bool zp_in = z < m.n3 - 1;
+    Quad<R> ym[2], yp[2];
+    R xl[2], xr[2];
+    uint32_t codes = 0;
+    if (active) {
+      codes = *reinterpret_cast<const uint32_t*>(a.code + n);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        cp[v] = zp_in ? ldq(in[v], n + plane) : cc[v];
+        ym[v] = ym_in ? ldq(in[v], n - (uint32_t)m.n1) : cc[v];
+        yp[v] = yp_in ? ldq(in[v], n + (uint32_t)m.n1) : cc[v];
+      }
+    }
+    // x neighbours of the end cells: adjacent lanes, or memory across waves
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xl[v] = shfl_up1(cc[v].v[3]);
+      xr[v] = shfl_down1(cc[v].v[0]);
+      if (active && xm_remote) xl[v] = in[v][n - 1];
+      if (active && xp_remote) xr[v] = in[v][n + 4];
+      // a boundary face carries the cell's own value
+      if (!xm_in) xl[v] = cc[v].v[0];
+      if (!xp_in) xr[v] = cc[v].v[3];
+    }
+    if (active) {
+      const unsigned inb_c = (ym_in ? 4u : 0u) | (yp_in ? 8u : 0u) | (z > 0 ? 16u : 0u) |
+                             (zp_in ? 32u : 0u);
+      Quad<R> kq[2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const unsigned inb = inb_c | ((k > 0 || xm_in) ? 1u : 0u) | ((k < 3 || xp_in) ? 2u : 0u);
+        const unsigned code = (codes >> (8 * k)) & 0xffu;
+        R phn[6], thn[6];
+        phn[0] = k > 0 ? cc[0].v[k - 1] : xl[0];
+        phn[1] = k < 3 ? cc[0].v[k + 1] : xr[0];
+        phn[2] = ym[0].v[k];
+        phn[3] = yp[0].v[k];
+        phn[4] = cm[0].v[k];
+        phn[5] = cp[0].v[k];
+        if (kCoupled) {
+          thn[0] = k > 0 ? cc[1].v[k - 1] : xl[1];
+          thn[1] = k < 3 ? cc[1].v[k + 1] : xr[1];
+          thn[2] = ym[1].v[k];
+          thn[3] = yp[1].v[k];
+          thn[4] = cm[1].v[k];
+          thn[5] = cp[1].v[k];
+        } else {
+#pragma unroll
+          for (int f = 0; f < 6; ++f) thn[f] = R(0);
+        }
+        R kp, kt;
+        CellRHS<R, MODEL>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn, thn, code,
+                                inb, dirf, thD, kp, kt);
+        kq[0].v[k] = kp;
+        kq[1].v[k] = kt;
+        if (STAGE == 1) {
+          const bool water = !(code & kGlassBit);
+          const double dpc = (double)cc[0].v[k];
+          const double thc_d = kCoupled ? (double)cc[1].v[k] : -m.dT;
+          const double rc = (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
+          if (water) {
+            red0 = dmax_nf(red0, fabs((double)kp));
+            red1 += dpc;
+            red3 += (dpc > 0.5) ? 1.0 : 0.0;
+          }
+          red2 += rc * thc_d - m.Lv * dpc;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const Quad<R>& kk = kq[v];
+        Quad<R> o;
+        if (STAGE == 0) {
+          stq(out[v], n, kk);
+        } else if (STAGE == 1) {
+          stq(k1[v], n, kk);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 3.0) * kk.v[k]);
+          stq(out[v], n, o);
+        } else if (STAGE == 2) {
+          const Quad<R> q1 = ldq(k1[v], n);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 6.0) * (kk.v[k] - q1.v[k]));
+          stq(out[v], n, o);
+        } else if (STAGE == 3) {
+          const Quad<R> q1 = ldq(k1[v], n), y0 = ldq(yv[v], n);
+          stq(k3[v], n, kk);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            o.v[k] = y0.v[k] + rdt * (R(0.125) * (q1.v[k] + R(3) * kk.v[k]));
+          stq(out[v], n, o);
+        } else if (STAGE == 4) {
+          const Quad<R> q1 = ldq(k1[v], n), q3 = ldq(k3[v], n), y0 = ldq(yv[v], n);
+          Quad<R> P, Cc;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            o.v[k] = y0.v[k] + rdt * (R(0.5) * q1.v[k] - R(1.5) * q3.v[k] + R(2) * kk.v[k]);
+            P.v[k] = y0.v[k] + rdt * (R(1.0 / 6.0) * (q1.v[k] + R(4) * kk.v[k]));
+            Cc.v[k] = rdt * (R(1.0 / 30.0) * (R(2) * q1.v[k] - R(9) * q3.v[k] + R(8) * kk.v[k]));
+          }
+          stq(out[v], n, o);
+          stq(k1[v], n, P);
+          stq(k3[v], n, Cc);
+        } else if (STAGE == 5) {
+          const Quad<R> P = ldq(k1[v], n), Cc = ldq(k3[v], n);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            o.v[k] = P.v[k] + rdt * (R(1.0 / 6.0) * kk.v[k]);
+            const double e = (double)Cc.v[k] - dt * ((1.0 / 30.0) * (double)kk.v[k]);
+            red0 = dmax_nf(red0, fabs(e));
+          }
+          stq(out[v], n, o);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        cm[v] = cc[v];
+        cc[v] = cp[v];
+      }
+    }
+  }
+  if (STAGE == 1) {
+    double v[4] = {red0, red1, red2, red3};
+    const int ops[4] = {1, 0, 0, 0};
+    block_reduce<4>(v, ops, smem);
+    if (threadIdx.x == 0)
+      for (int i = 0; i < 4; ++i) a.part[(size_t)blockIdx.x * kPartS1 + i] = v[i];
+  } else if (STAGE == 5) {
+    double v[1] = {red0};
+    const int ops[1] = {1};
+    block_reduce<1>(v, ops, smem);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = v[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Paired-stage kernel: two consecutive Merson stages in one pass.
+//
+//   FIRST = 1: S1 on the tile plus a one-cell ring (y -> k1, Y2), then S2 on
+//              the tile (Y2 -> k2, Y3 = Y2 + dt (k2 - k1)/6).  Y2 never leaves
+//              LDS; k1 and Y3 go to HBM.
+//   FIRST = 3: S3 on tile + ring (Y3 -> k3, Y4), then S4 on the tile
+//              (Y4 -> k4; Y5, P, C).  Y4 and k3 never leave the workgroup.
+//
+// A workgroup owns a TX x TY tile of the x1-x2 plane and marches z_chunk
+// planes along x3.  Plane j of the first stage's stencil input is staged in
+// LDS over the tile plus a two-cell ring (three planes rotate); the first
+// stage is evaluated on the tile plus a one-cell ring of plane j and its
+// output (the second stage's input) is kept in LDS (three planes rotate); the
+// second stage then runs on plane j-1.  The ring is recomputed by the
+// neighbouring tiles: (TX+2)(TY+2)/(TX TY) first-stage evaluations per cell.
+// Per unknown and cell the pass moves: first pair r y, w k1, Y3 (3 words);
+// second pair r Y3, y, k1, w Y5, P, C (6 words) -- 9 words against 15 for the
+// same four stages one pass each.
+//
+// Buffers that a pass writes are never read by the same pass (neighbouring
+// workgroups read rings of the inputs concurrently): Y3 -> B, Y5 -> A,
+// P -> K3, C -> the free state slot y[1-cur], which S5 then overwrites in
+// place with y_new.
+
+template <int TX, int TY>
+__device__ __forceinline__ void ring_cell(int k, int& lx, int& ly) {
+  // k-th cell of the one-cell ring around the tile, in ring-local
+  // coordinates (0..TX+1, 0..TY+1)
+  if (k < TX + 2) {
+    lx = k;
+    ly = 0;
+  } else if (k < 2 * (TX + 2)) {
+    lx = k - (TX + 2);
+    ly = TY + 1;
+  } else {
+    const int r = k - 2 * (TX + 2);
+    lx = (r < TY) ? 0 : TX + 1;
+    ly = 1 + (r < TY ? r : r - TY);
+  }
+}
+
+template <typename R, int MODEL, int FIRST, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void pair_kernel(PairArgs a) {
+  constexpr int NT = TX * TY;
+  constexpr bool kCoupled = MODEL == PF_MODEL_COUPLED;
+  constexpr int NV = kCoupled ? 2 : 1;
+  constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;  // staged input region
+  constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;  // first-stage region
+  constexpr int NRING = N1 - NT;
+  __shared__ R inS[3][NV][N2];
+  __shared__ R midS[3][NV][N1];
+  __shared__ double smem[8 * (NT / 64)];
+
+  const ModelConst& m = a.mc;
+  if (a.ctl->done) return;
+  const double t0 = a.ctl->t;
+  const double dt = a.ctl->dt_att;
+  const int cur = a.ctl->cur;
+  const double tA = t0 + (FIRST == 1 ? 0.0 : dt / 3.0);
+  const double tB = t0 + (FIRST == 1 ? dt / 3.0 : 0.5 * dt);
+  const R thDA = R(dirichlet_theta(m, tA));
+  const R thDB = R(dirichlet_theta(m, tB));
+  const R rdt = R(dt);
+
+  const int nblk = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x, nblk);
+  const int tx = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int ty = rest % a.tiles_y;
+  const int tz = rest / a.tiles_y;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int z0 = tz * a.z_chunk;
+  const int z1 = min(z0 + a.z_chunk, m.n3);
+  const int n1 = m.n1, n2 = m.n2, n3 = m.n3;
+  const int plane = n1 * n2;
+  const unsigned dirf = (unsigned)m.dirichlet_faces;
+
+  const R* src[2];
+  if (FIRST == 1) {
+    src[0] = static_cast<const R*>(a.y[cur][0]);
+    src[1] = static_cast<const R*>(a.y[cur][1]);
+  } else {
+    src[0] = static_cast<const R*>(a.in[0]);
+    src[1] = static_cast<const R*>(a.in[1]);
+  }
+  const R* yv[2] = {static_cast<const R*>(a.y[cur][0]), static_cast<const R*>(a.y[cur][1])};
+  R* k1g[2] = {static_cast<R*>(a.k1[0]), static_cast<R*>(a.k1[1])};
+  R* oa[2] = {static_cast<R*>(a.out_a[0]), static_cast<R*>(a.out_a[1])};
+  R* op[2] = {static_cast<R*>(a.out_p[0]), static_cast<R*>(a.out_p[1])};
+  // C goes to the free state slot (FIRST == 3)
+  R* oc[2] = {static_cast<R*>(const_cast<void*>(a.y[1 - cur][0])),
+              static_cast<R*>(const_cast<void*>(a.y[1 - cur][1]))};
+
+  // this thread's tile cell
+  const int tid = threadIdx.x;
+  const int cx = tid % TX, cy = tid / TX;
+  const int gx = x0 + cx, gy = y0 + cy;
+  const bool own = gx < n1 && gy < n2;
+  const int cidx1 = (cy + 1) * W1 + (cx + 1);  // in the first-stage region
+
+  // values of the own cell carried from the first stage (plane j) to the
+  // second (plane j, one iteration later)
+  R c_k[NV], c_y[NV], c_k1[NV];   // plane being produced
+  R p_k[NV], p_y[NV], p_k1[NV];   // plane consumed by the second stage
+  unsigned c_code = 0, p_code = 0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c_k[v] = c_y[v] = c_k1[v] = p_k[v] = p_y[v] = p_k1[v] = R(0);
+
+  double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
+
+  auto load_plane = [&](int p) {
+    const int s = ((p % 3) + 3) % 3;
+    for (int i = tid; i < N2; i += NT) {
+      const int lx = i % W2, ly = i / W2;
+      const int qx = x0 + lx - 2, qy = y0 + ly - 2;
+      const bool ok = qx >= 0 && qx < n1 && qy >= 0 && qy < n2;
+      const int n = ok ? qx + n1 * qy + plane * p : 0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) inS[s][v][i] = ok ? src[v][n] : R(0);
+    }
+  };
+
+  if (z0 - 2 >= 0) load_plane(z0 - 2);
+  if (z0 - 1 >= 0) load_plane(z0 - 1);
+
+  for (int j = z0 - 1; j <= z1; ++j) {
+    if (j + 1 < n3 && j + 1 >= 0) load_plane(j + 1);
+    __syncthreads();
+    // ---- first stage at plane j over tile + ring
+    if (j >= 0 && j < n3) {
+      const int sm = (((j - 1) % 3) + 3) % 3, s0 = j % 3, sp = (j + 1) % 3;
+      const bool zin_m = j > 0, zin_p = j < n3 - 1;
+      for (int item = tid; item < N1; item += NT) {
+        int lx, ly;
+        if (item < NT) {
+          lx = 1 + item % TX;
+          ly = 1 + item / TX;
+        } else {
+          ring_cell<TX, TY>(item - NT, lx, ly);
+        }
+        const int qx = x0 + lx - 1, qy = y0 + ly - 1;
+        const int i1 = ly * W1 + lx;
+        const bool ok = qx >= 0 && qx < n1 && qy >= 0 && qy < n2;
+        if (!ok) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) midS[s0][v][i1] = R(0);
+          continue;
+        }
+        const int i2 = (ly + 1) * W2 + (lx + 1);
+        const int n = qx + n1 * qy + plane * j;
+        const unsigned code = a.code[n];
+        const unsigned inb = (qx > 0 ? 1u : 0u) | (qx < n1 - 1 ? 2u : 0u) |
+                             (qy > 0 ? 4u : 0u) | (qy < n2 - 1 ? 8u : 0u) |
+                             (zin_m ? 16u : 0u) | (zin_p ? 32u : 0u);
+        R ctr[2], nb[2][6];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          // a boundary face carries the cell's own value
+          ctr[v] = inS[s0][v][i2];
+          nb[v][0] = (inb & 1u) ? inS[s0][v][i2 - 1] : ctr[v];
+          nb[v][1] = (inb & 2u) ? inS[s0][v][i2 + 1] : ctr[v];
+          nb[v][2] = (inb & 4u) ? inS[s0][v][i2 - W2] : ctr[v];
+          nb[v][3] = (inb & 8u) ? inS[s0][v][i2 + W2] : ctr[v];
+          nb[v][4] = zin_m ? inS[sm][v][i2] : ctr[v];
+          nb[v][5] = zin_p ? inS[sp][v][i2] : ctr[v];
+        }
+        if (!kCoupled) {
+          ctr[1] = R(0);
+#pragma unroll
+          for (int f = 0; f < 6; ++f) nb[1][f] = R(0);
+        }
+        R kp, kt;
+        CellRHS<R, MODEL>::eval(m, ctr[0], ctr[1], nb[0], nb[1], code, inb, dirf, thDA, kp, kt);
+        const R kk[2] = {kp, kt};
+        const bool mine = item < NT;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (FIRST == 1) {
+            midS[s0][v][i1] = ctr[v] + rdt * (R(1.0 / 3.0) * kk[v]);
+            if (mine) {
+              c_k[v] = kk[v];
+              c_y[v] = ctr[v];
+            }
+          } else {
+            const R y0v = yv[v][n], k1v = k1g[v][n];
+            midS[s0][v][i1] = y0v + rdt * (R(0.125) * (k1v + R(3) * kk[v]));
+            if (mine) {
+              c_k[v] = kk[v];
+              c_y[v] = y0v;
+              c_k1[v] = k1v;
+            }
+          }
+        }
+        if (mine) {
+          c_code = code;
+          if (FIRST == 1 && j >= z0 && j < z1) {
+            // k1 to HBM and the diagnostics of the state (own planes only)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) k1g[v][n] = kk[v];
+            const bool water = !(code & kGlassBit);
+            const double dpc = (double)ctr[0];
+            const double thc_d = kCoupled ? (double)ctr[1] : -m.dT;
+            const double rc = (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
+            if (water) {
+              red0 = dmax_nf(red0, fabs((double)kp));
+              red1 += dpc;
+              red3 += (dpc > 0.5) ? 1.0 : 0.0;
+            }
+            red2 += rc * thc_d - m.Lv * dpc;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- second stage at plane q = j - 1 over the tile
+    const int q = j - 1;
+    if (q >= z0 && q < z1 && own) {
+      const int sm = (((q - 1) % 3) + 3) % 3, s0 = ((q % 3) + 3) % 3, sp = (q + 1) % 3;
+      const bool zin_m = q > 0, zin_p = q < n3 - 1;
+      const unsigned inb = (gx > 0 ? 1u : 0u) | (gx < n1 - 1 ? 2u : 0u) |
+                           (gy > 0 ? 4u : 0u) | (gy < n2 - 1 ? 8u : 0u) |
+                           (zin_m ? 16u : 0u) | (zin_p ? 32u : 0u);
+      R ctr[2], nb[2][6];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        ctr[v] = midS[s0][v][cidx1];
+        nb[v][0] = (inb & 1u) ? midS[s0][v][cidx1 - 1] : ctr[v];
+        nb[v][1] = (inb & 2u) ? midS[s0][v][cidx1 + 1] : ctr[v];
+        nb[v][2] = (inb & 4u) ? midS[s0][v][cidx1 - W1] : ctr[v];
+        nb[v][3] = (inb & 8u) ? midS[s0][v][cidx1 + W1] : ctr[v];
+        nb[v][4] = zin_m ? midS[sm][v][cidx1] : ctr[v];
+        nb[v][5] = zin_p ? midS[sp][v][cidx1] : ctr[v];
+      }
+      if (!kCoupled) {
+        ctr[1] = R(0);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) nb[1][f] = R(0);
+      }
+      R kp, kt;
+      CellRHS<R, MODEL>::eval(m, ctr[0], ctr[1], nb[0], nb[1], p_code, inb, dirf, thDB, kp, kt);
+      const R kk[2] = {kp, kt};
+      const int n = gx + n1 * gy + plane * q;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (FIRST == 1) {
+          oa[v][n] = ctr[v] + rdt * (R(1.0 / 6.0) * (kk[v] - p_k[v]));
+        } else {
+          const R k1v = p_k1[v], k3v = p_k[v], y0v = p_y[v];
+          oa[v][n] = y0v + rdt * (R(0.5) * k1v - R(1.5) * k3v + R(2) * kk[v]);
+          op[v][n] = y0v + rdt * (R(1.0 / 6.0) * (k1v + R(4) * kk[v]));
+          oc[v][n] = rdt * (R(1.0 / 30.0) * (R(2) * k1v - R(9) * k3v + R(8) * kk[v]));
+        }
+      }
+    }
+    // rotate the own-cell carry
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      p_k[v] = c_k[v];
+      p_y[v] = c_y[v];
+      p_k1[v] = c_k1[v];
+    }
+    p_code = c_code;
+  }
+
+  if (FIRST == 1) {
+    // wavefront xor trees, then the waves in order (fixed order: bitwise
+    // reproducible)
+    constexpr int NW = NT / 64;
+    double v[4] = {red0, red1, red2, red3};
+    const int ops[4] = {1, 0, 0, 0};
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      v[jj] = ops[jj] ? wave_reduce<1>(v[jj]) : wave_reduce<0>(v[jj]);
+      if (lane == 0) smem[jj * NW + wave] = v[jj];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int jj = 0; jj < 4; ++jj) {
+        double acc = smem[jj * NW];
+        for (int w = 1; w < NW; ++w) {
+          const double o = smem[jj * NW + w];
+          acc = ops[jj] ? (o > acc ? o : acc) : acc + o;
+        }
+        a.part[(size_t)blockIdx.x * kPartS1 + jj] = acc;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 
-int grid_blocks(const ModelConst& mc, int z_chunk, int* tiles_p, int* tiles_z) {
+int grid_blocks(const ModelConst& mc, int z_chunk, int vec, int* tiles_p, int* tiles_z) {
   const long long plane = (long long)mc.n1 * mc.n2;
-  *tiles_p = (int)((plane + kBlock - 1) / kBlock);
+  const long long per = vec ? 4LL * kBlock : kBlock;
+  *tiles_p = (int)((plane + per - 1) / per);
   *tiles_z = (mc.n3 + z_chunk - 1) / z_chunk;
   return (*tiles_p) * (*tiles_z);
 }
@@ -505,6 +1089,18 @@ hipError_t launch_build_code(const uint8_t* mask, uint8_t* code, int n1, int n2,
 template <typename R, int MODEL>
 static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
+  if (a.vec) {
+    switch (stage) {
+      case 0: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 0>), grid, block, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 1>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 2>), grid, block, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 3>), grid, block, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 4>), grid, block, 0, s, a); break;
+      case 5: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 5>), grid, block, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (stage) {
     case 0: hipLaunchKernelGGL((stage_kernel<R, MODEL, 0>), grid, block, 0, s, a); break;
     case 1: hipLaunchKernelGGL((stage_kernel<R, MODEL, 1>), grid, block, 0, s, a); break;
@@ -515,6 +1111,46 @@ static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+int pair_blocks(const ModelConst& mc, int ts, int z_chunk, int* tx, int* ty, int* tz) {
+  const int TX = kPairTiles[ts][0], TY = kPairTiles[ts][1];
+  *tx = (mc.n1 + TX - 1) / TX;
+  *ty = (mc.n2 + TY - 1) / TY;
+  *tz = (mc.n3 + z_chunk - 1) / z_chunk;
+  return (*tx) * (*ty) * (*tz);
+}
+
+template <typename R, int MODEL, int TX, int TY>
+static hipError_t launch_pair_t(int first, const PairArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.tiles_z)), block(TX * TY);
+  if (first == 1)
+    hipLaunchKernelGGL((pair_kernel<R, MODEL, 1, TX, TY>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((pair_kernel<R, MODEL, 3, TX, TY>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R, int MODEL>
+static hipError_t launch_pair_m(int first, int ts, const PairArgs& a, hipStream_t s) {
+  switch (ts) {
+    case 0: return launch_pair_t<R, MODEL, 64, 4>(first, a, s);
+    case 1: return launch_pair_t<R, MODEL, 64, 8>(first, a, s);
+    case 2: return launch_pair_t<R, MODEL, 32, 8>(first, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pair(int precision, int model, int first, int ts, const PairArgs& a,
+                       hipStream_t s) {
+  if (precision == PF_FP64) {
+    if (model == PF_MODEL_AC) return launch_pair_m<double, PF_MODEL_AC>(first, ts, a, s);
+    if (model == PF_MODEL_COUPLED) return launch_pair_m<double, PF_MODEL_COUPLED>(first, ts, a, s);
+  } else {
+    if (model == PF_MODEL_AC) return launch_pair_m<float, PF_MODEL_AC>(first, ts, a, s);
+    if (model == PF_MODEL_COUPLED) return launch_pair_m<float, PF_MODEL_COUPLED>(first, ts, a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a, hipStream_t s) {
@@ -528,9 +1164,10 @@ hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_controller(DevCtl* ctl, const double* part1, const double* part5, int nparts,
-                             double h3, hipStream_t s) {
-  hipLaunchKernelGGL(controller_kernel, dim3(1), dim3(256), 0, s, ctl, part1, part5, nparts, h3);
+hipError_t launch_controller(DevCtl* ctl, const double* part1, int np1, const double* part5,
+                             int np5, double h3, hipStream_t s) {
+  hipLaunchKernelGGL(controller_kernel, dim3(1), dim3(256), 0, s, ctl, part1, np1, part5, np5,
+                     h3);
   return hipGetLastError();
 }
 

@@ -1,18 +1,19 @@
-"""HBM-traffic measurement helpers for the stage kernels.
+"""HBM-traffic measurement helpers for the stencil passes.
 
 Two modes, used around rocprofv3 counter runs:
 
-  python -m paper_2401_01672_amd.profiling run --workload W --steps K
-      runs K adaptive steps of workload W and then a device copy of a known
-      size (the calibration kernel), so one ``rocprofv3 --pmc FETCH_SIZE``
-      (or WRITE_SIZE) run sees both;
+  python -m paper_2401_01672_amd.profiling run --workload W --schedule S
+      runs adaptive steps of workload W under stencil schedule S, then two
+      calibration kernels of known size (a 1 GiB fill, which writes 1 GiB, and
+      a 1 GiB float32 -> float64 conversion, which reads 1 GiB), so that one
+      ``rocprofv3 --pmc FETCH_SIZE`` (or ``WRITE_SIZE``) run sees both;
 
-  python -m paper_2401_01672_amd.profiling summarize --workload W \
-         --fetch DIR_FETCH --write DIR_WRITE --out profiles/
-      reads the two counter CSVs, scales each counter by the reading of the
-      calibration copy (bytes moved / counter value), and writes
-      ``traffic_stage<N>_<W>.json`` with the HBM bytes per launch of every
-      stage kernel and the hash of the kernel sources it was taken on.
+  python -m paper_2401_01672_amd.profiling summarize --workload W --schedule S \
+         --fetch DIR_FETCH --write DIR_WRITE --out DIR
+      reads the two counter CSVs, scales each counter by its reading for the
+      calibration kernel (bytes moved / counter value), and writes
+      ``traffic_<S>_pass<N>_<W>.json``: HBM bytes per launch of every pass,
+      with the hash of the kernel sources it was taken on.
 """
 from __future__ import annotations
 
@@ -22,22 +23,23 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
+CAL_BYTES = 1 << 30
 
 
 def source_hash() -> str:
+    """Hash of the stencil kernel sources (the traffic depends only on them)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2401_01672_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("pf_internal.h", "pf_stencil.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def run(workload: str, steps: int):
+def run(workload: str, schedule: str, steps: int):
     sys.path.insert(0, ROOT)
     import numpy as np
     import torch
@@ -51,71 +53,81 @@ def run(workload: str, steps: int):
     prec = wl["precision"]
     npdt = np.float64 if prec == "fp64" else np.float32
     s = pf.Solver(case.params, case.mask, prec, case.run)
-    # same loop and tile autotuning as the benchmark; with enough steps the
-    # per-stage median comes from the stepping dispatches, not the tuner's
     s.set_loop(16, False)
+    s.set_schedule(schedule)  # and the same tile autotuner as the benchmark
     th = None if case.T0 is None else (case.T0 - case.params["t_star"]).astype(npdt)
     s.set_state(case.phi0.astype(npdt), th)
     s.set_time(0.0, case.run["dt0"])
     st = s.integrate(max_steps=steps)
-    print(json.dumps(dict(steps=steps, accepted=st["steps_accepted"])), flush=True)
+    print(json.dumps(dict(steps=steps, accepted=st["steps_accepted"], config=s.get_config())),
+          flush=True)
     s.close()
-    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-    b = torch.empty_like(a)
+    a = torch.empty(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)             # calibration: writes CAL_BYTES
     torch.cuda.synchronize()
-    b.copy_(a)
+    b = a.to(torch.float64)  # calibration: reads CAL_BYTES
     torch.cuda.synchronize()
-    print(json.dumps(dict(copy_bytes=COPY_BYTES)), flush=True)
+    print(json.dumps(dict(calibration_bytes=CAL_BYTES, check=float(b[0]))), flush=True)
 
 
 def _read_counter(d: str, counter: str):
-    """{kernel name: [values per dispatch]} from a rocprofv3 counter CSV."""
+    """[(kernel name, value)] per dispatch from a rocprofv3 counter CSV."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise FileNotFoundError(f"no counter_collection.csv under {d}")
-    out = {}
+    out = []
     for f in files:
         for row in csv.DictReader(open(f)):
             if row.get("Counter_Name", counter) != counter:
                 continue
-            name = row.get("Kernel_Name", "")
-            out.setdefault(name, []).append(float(row["Counter_Value"]))
+            out.append((row.get("Kernel_Name", ""), float(row["Counter_Value"])))
     return out
 
 
-def summarize(workload: str, fetch_dir: str, write_dir: str, out_dir: str):
+def _template_args(name: str):
+    m = re.search(r"<([^<>]*)>", name)
+    return [x.strip() for x in m.group(1).split(",")] if m else []
+
+
+def pass_of(name: str, schedule: str):
+    """1-based pass index of a kernel dispatch under the schedule, or None."""
+    args = _template_args(name)
+    if "pair_kernel<" in name and schedule == "paired" and len(args) >= 3:
+        return 1 if args[2] == "1" else 2
+    if "stage_kernel<" in name and len(args) >= 3:
+        st = int(args[2])
+        if schedule == "five":
+            return st if st >= 1 else None
+        return 3 if st == 5 else None
+    return None
+
+
+def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_dir: str):
     fetch = _read_counter(fetch_dir, "FETCH_SIZE")
     write = _read_counter(write_dir, "WRITE_SIZE")
-
-    def calib(tab):
-        vals = [v for k, vs in tab.items() if "copy" in k.lower() or "elementwise" in k.lower()
-                for v in vs]
-        big = max(vals) if vals else None
-        return (COPY_BYTES / 1024.0) / big if big else None
-
-    fr, wr = calib(fetch), calib(write)
+    # calibration: the conversion kernel reads CAL_BYTES (largest FETCH among
+    # torch elementwise kernels); the fill kernel writes CAL_BYTES
+    f_cal = max(v for k, v in fetch if "elementwise" in k or "copy" in k.lower())
+    w_cal = max(v for k, v in write if "FillFunctor" in k)
+    fr = (CAL_BYTES / 1024.0) / f_cal
+    wr = (CAL_BYTES / 1024.0) / w_cal
     sh = source_hash()
+    npass = 3 if schedule == "paired" else 5
     written = []
-    for st in range(1, 6):
-        key = f"stage_kernel<"
-        fk = [v for k, vs in fetch.items() if key in k and k.rstrip(")").split(",")[-1].strip()
-              .startswith(f"{st}>") for v in vs]
-        wk = [v for k, vs in write.items() if key in k and k.rstrip(")").split(",")[-1].strip()
-              .startswith(f"{st}>") for v in vs]
+    for p in range(1, npass + 1):
+        fk = sorted(v for k, v in fetch if pass_of(k, schedule) == p)
+        wk = sorted(v for k, v in write if pass_of(k, schedule) == p)
         if not fk or not wk:
             continue
-        # KiB per dispatch (median of the dispatches) scaled by the calibration
-        fk.sort()
-        wk.sort()
-        f_kib = fk[len(fk) // 2]
-        w_kib = wk[len(wk) // 2]
-        rec = dict(workload=workload, kernel=f"stage{st}", source_hash=sh,
+        f_kib, w_kib = fk[len(fk) // 2], wk[len(wk) // 2]  # median dispatch
+        rec = dict(workload=workload, schedule=schedule, kernel=f"{schedule}_pass{p}",
+                   source_hash=sh, dispatches=len(fk),
                    fetch_kib_per_dispatch=f_kib, write_kib_per_dispatch=w_kib,
                    fetch_scale=fr, write_scale=wr,
-                   bytes_per_launch=(f_kib * 1024 * (fr or 1.0) + w_kib * 1024 * (wr or 1.0)),
-                   calibration=f"torch copy of {COPY_BYTES} bytes: "
-                               f"FETCH x{fr and round(fr, 4)}, WRITE x{wr and round(wr, 4)}")
-        path = os.path.join(out_dir, f"traffic_stage{st}_{workload}.json")
+                   bytes_per_launch=f_kib * 1024 * fr + w_kib * 1024 * wr,
+                   calibration=f"{CAL_BYTES}-byte fill (WRITE_SIZE x{wr:.4f}) and "
+                               f"{CAL_BYTES}-byte-read conversion (FETCH_SIZE x{fr:.4f})")
+        path = os.path.join(out_dir, f"traffic_{schedule}_pass{p}_{workload}.json")
         json.dump(rec, open(path, "w"), indent=1)
         written.append(path)
     print("\n".join(written))
@@ -126,17 +138,19 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("--workload", default="coupled_256_fp32")
+    r.add_argument("--schedule", default="five", choices=["paired", "five"])
     r.add_argument("--steps", type=int, default=64)
     s = sub.add_parser("summarize")
     s.add_argument("--workload", default="coupled_256_fp32")
+    s.add_argument("--schedule", default="five", choices=["paired", "five"])
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
     s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.workload, a.steps)
+        run(a.workload, a.schedule, a.steps)
     else:
-        summarize(a.workload, a.fetch, a.write, a.out)
+        summarize(a.workload, a.schedule, a.fetch, a.write, a.out)
 
 
 if __name__ == "__main__":
