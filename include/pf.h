@@ -188,6 +188,19 @@ int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info);
 int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
                  pf_run_stats* stats);
 
+/* Batched sweep: integrate n independent instances (same model and
+ * precision, each with n1 divisible by 4, each with its own geometry,
+ * constants, state, t and dt) with ONE persistent cooperative kernel per
+ * batch of attempts: every stage pass processes the tiles of all unfinished
+ * instances together, then each instance's own controller runs (per-instance
+ * adaptive dt, equilibrium test and status).  Stops each instance at t_end,
+ * max_steps attempts, or equilibrium (eq_tol > 0), like pf_integrate.
+ * out[i] receives instance i's statistics (wall_s: the whole batch).  stream:
+ * a hipStream_t cast to uintptr_t, 0 = the first instance's stream.
+ * Returns PF_OK or the first instance error code; synchronous. */
+int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t max_steps,
+                       double eq_tol, pf_run_stats* out, uintptr_t stream);
+
 /* Diagnostics of the current state into stats (ice/pore counts, sum_phi,
  * enthalpy); the step counters and t are left as the last run set them. */
 int pf_diagnostics(pf_handle* h, pf_run_stats* stats);

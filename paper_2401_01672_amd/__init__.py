@@ -75,6 +75,8 @@ SIGNATURES = [
                               C.POINTER(PFStepInfo)]),
     ("pf_integrate", C.c_int, [_H, C.c_double, C.c_int64, C.c_double, C.POINTER(PFRunStats)]),
     ("pf_diagnostics", C.c_int, [_H, C.POINTER(PFRunStats)]),
+    ("pf_batch_integrate", C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_int64,
+                                     C.c_double, C.POINTER(PFRunStats), C.c_size_t]),
     ("pf_set_loop", C.c_int, [_H, C.c_int32, C.c_int32]),
     ("pf_set_tile", C.c_int, [_H, C.c_int32]),
     ("pf_set_schedule", C.c_int, [_H, C.c_int32]),
@@ -289,3 +291,17 @@ class Solver:
 
     def synchronize(self):
         self._check(lib().pf_synchronize(self.h))
+
+
+def batch_integrate(solvers, t_end: float = float("inf"), max_steps: int = 2**62,
+                    eq_tol: float = 0.0, raise_on_error: bool = True):
+    """pf_batch_integrate over Solver objects (one persistent kernel for all).
+    Returns one stats dict per solver."""
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.h for s in solvers])
+    out = (PFRunStats * n)()
+    rc = lib().pf_batch_integrate(hs, n, float(t_end), int(max_steps), float(eq_tol), out, 0)
+    if rc < 0 and raise_on_error:
+        raise PFError(rc, lib().pf_last_error(solvers[0].h).decode() or
+                      lib().pf_last_error(None).decode())
+    return [Solver._stats(out[i], rc) for i in range(n)]

@@ -24,6 +24,9 @@ FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",
+    # contract a*b+c only within one source expression, so every kernel that
+    # inlines the cell update (single stage, vector, batched) rounds alike
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "pf_internal.h"
 
@@ -742,6 +743,135 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return PF_OK;
+}
+
+int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t max_steps,
+                       double eq_tol, pf_run_stats* out, uintptr_t stream) {
+  if (!inst || n < 1 || !out) return fail(nullptr, PF_EINVAL, "batch: inst, n >= 1 and out required");
+  auto w0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < n; ++i) {
+    if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
+    if (inst[i]->P.precision != inst[0]->P.precision || inst[i]->P.model != inst[0]->P.model)
+      return fail(nullptr, PF_EINVAL, "batch: all instances need the same model and precision");
+    if (inst[i]->P.n1 % 4 != 0)
+      return fail(nullptr, PF_EINVAL, "batch: every instance needs n1 divisible by 4");
+  }
+  pf_handle* h0 = inst[0];
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : h0->own_stream;
+  const int kBatchZ = 4;        // planes per work item: fine-grained load balance
+  const int kStepsPerLaunch = 32;
+  std::vector<pf::BatchDesc> desc(n);
+  std::vector<int> item_inst;
+  int item0 = 0;
+  for (int i = 0; i < n; ++i) {
+    pf_handle* h = inst[i];
+    PF_HIP(h, hipStreamSynchronize(h->stream));
+    h->vec = 1;
+    int rc = set_tiles(h, kBatchZ);
+    if (rc) return rc;
+    DevCtl& c = *h->hctl;
+    init_ctl(h, c, t_end, max_steps, eq_tol);
+    if (h->t >= t_end) {
+      c.done = 1;
+      c.status = PF_OK;
+    } else if (max_steps <= 0) {
+      c.done = 1;
+      c.status = PF_MAXSTEPS;
+    }
+    PF_HIP(h, hipMemcpyAsync(h->ctl, h->hctl, sizeof(DevCtl), hipMemcpyHostToDevice, s));
+    pf::BatchDesc& d = desc[i];
+    memset(&d, 0, sizeof(d));
+    for (int st = 1; st <= 5; ++st) d.st[st - 1] = stage_args(h, st);
+    d.p1 = h->part1;
+    d.p5 = h->part5;
+    d.ntiles = h->nparts;
+    d.item0 = item0;
+    d.h3 = h->mc.h3;
+    for (int k = 0; k < h->nparts; ++k) item_inst.push_back(i);
+    item0 += h->nparts;
+  }
+  const int nitems = item0;
+  pf::BatchDesc* ddesc = nullptr;
+  int* ditem = nullptr;
+  unsigned* dbar = nullptr;  // [0] arrivals, [1] generation, [2] barrier-overrun flag
+  if (hipMalloc(&ddesc, sizeof(pf::BatchDesc) * n) != hipSuccess ||
+      hipMalloc(&ditem, sizeof(int) * nitems) != hipSuccess ||
+      hipMalloc(&dbar, 4 * sizeof(unsigned)) != hipSuccess) {
+    (void)hipFree(ddesc);
+    (void)hipFree(ditem);
+    return fail(h0, PF_ENOMEM, "batch: descriptor allocation failed");
+  }
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(ddesc);
+    (void)hipFree(ditem);
+    (void)hipFree(dbar);
+  };
+  unsigned hbar[4] = {0, 0, 0, 0};
+  if (hipMemcpyAsync(ddesc, desc.data(), sizeof(pf::BatchDesc) * n, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(ditem, item_inst.data(), sizeof(int) * nitems, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(dbar, hbar, sizeof(hbar), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    cleanup();
+    return fail(h0, PF_EHIP, "batch: descriptor upload failed");
+  }
+  int grid = pf::batch_max_blocks(h0->P.precision, h0->P.model);
+  if (grid < 1) {
+    cleanup();
+    return fail(h0, PF_EHIP, "batch: occupancy query failed");
+  }
+  if (grid > nitems) grid = nitems;
+  for (;;) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) any |= !inst[i]->hctl->done;
+    if (!any) break;
+    hipError_t e = pf::launch_batch(h0->P.precision, h0->P.model, ddesc, ditem, nitems, n,
+                                    kStepsPerLaunch, grid, dbar, dbar + 2, s);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(h0, PF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < n; ++i)
+      if (hipMemcpyAsync(inst[i]->hctl, inst[i]->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s) !=
+          hipSuccess) {
+        cleanup();
+        return fail(h0, PF_EHIP, "batch: control readback failed");
+      }
+    if (hipMemcpyAsync(hbar, dbar, sizeof(hbar), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      cleanup();
+      return fail(h0, PF_EHIP, "batch: synchronize failed");
+    }
+    if (hbar[2]) {
+      cleanup();
+      return fail(h0, PF_EHIP, "batch: a grid barrier wait overran its bound");
+    }
+  }
+  cleanup();
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+  int ret = PF_OK;
+  for (int i = 0; i < n; ++i) {
+    pf_handle* h = inst[i];
+    const DevCtl& c = *h->hctl;
+    h->cur = c.cur;
+    h->t = c.t;
+    h->dt = c.dt_nom;
+    pf_run_stats& st = out[i];
+    memset(&st, 0, sizeof(st));
+    int rc = pf_diagnostics(h, &st);
+    if (rc) return rc;
+    st.steps_accepted = c.n_acc;
+    st.steps_rejected = c.n_rej;
+    st.t = c.t;
+    st.dt = c.dt_nom;
+    st.maxk1 = c.maxk1;
+    st.status = c.status;
+    st.wall_s = wall;
+    if (c.status < 0 && ret == PF_OK) ret = c.status;
+  }
+  return ret;
 }
 
 int pf_set_schedule(pf_handle* h, int32_t schedule) {

@@ -108,6 +108,16 @@ struct PairArgs {
   int tiles_x, tiles_y, tiles_z;
 };
 
+// One instance of a batched sweep (device-resident table, one per instance).
+struct BatchDesc {
+  StageArgs st[5];      // per stage; part points at the instance's slots
+  const double* p1;     // S1 partials of the instance (ntiles x kPartS1)
+  const double* p5;     // S5 partials (ntiles)
+  int ntiles;           // work items (stage-pass tiles) of the instance
+  int item0;            // first global item index of the instance
+  double h3;
+};
+
 // Stencil schedules of one attempt.
 constexpr int kSchedFive = 0;    // S1..S5, one pass each
 constexpr int kSchedPaired = 1;  // (S1+S2), (S3+S4), S5
@@ -135,4 +145,11 @@ constexpr int kPairTiles[3][2] = {{64, 4}, {64, 8}, {32, 8}};
 int pair_blocks(const ModelConst& mc, int ts, int z_chunk, int* tx, int* ty, int* tz);
 hipError_t launch_pair(int precision, int model, int first, int ts, const PairArgs& a,
                        hipStream_t s);
+// batched sweep: cooperative persistent launch; grid_blocks <= batch_max_blocks()
+// bar: two zeroed unsigned counters (grid barrier); err: set to 1 when a
+// barrier wait overran its bound
+hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int* item_inst,
+                        int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
+                        unsigned* err, hipStream_t s);
+int batch_max_blocks(int precision, int model);
 }  // namespace pf

@@ -30,6 +30,7 @@
 //   S5: k5 = F(t + dt, Y5);      y_new = P + dt k5/6,        E = C - dt k5/30
 // S1 also reduces the diagnostics of y; S5 reduces max |E| in FP64.
 #include <float.h>
+#include <hip/hip_cooperative_groups.h>
 #include <math.h>
 
 #include "pf_internal.h"
@@ -371,10 +372,11 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
 // Controller: reduces the partials of S1 and S5 in a fixed order and updates
 // the device step control (Sec. 2.5; semantics in pf.h).
 
-__global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const double* p1,
-                                                         int np1, const double* p5, int np5,
-                                                         double h3) {
-  __shared__ double smem[8 * kWaves];
+// One block (256 threads) runs the controller of one control block; smem
+// holds 8 * kWaves doubles.  Safe to call repeatedly from a persistent block.
+__device__ void controller_body(DevCtl* ctl, const double* p1, int np1, const double* p5,
+                                int np5, double h3, double* smem) {
+  __syncthreads();  // smem reuse across consecutive calls
   if (ctl->done) return;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < np1; i += blockDim.x) {
@@ -451,6 +453,144 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
     c.clipped = 1;
   }
   *ctl = c;
+}
+
+__global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const double* p1,
+                                                         int np1, const double* p5, int np5,
+                                                         double h3) {
+  __shared__ double smem[8 * kWaves];
+  controller_body(ctl, p1, np1, p5, np5, h3, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweep: many independent grids (instances) advanced by one
+// persistent cooperative kernel.  Work items are (instance, tile) pairs of
+// the four-cell stage passes; all items of one stage are processed (strided
+// over the workgroups), then a grid-wide barrier, then the next stage; after
+// S5 one workgroup per instance runs that instance's controller on its own
+// control block (own t, dt, status), then a barrier.  Instances whose
+// control block says done are skipped, so finished instances cost nothing
+// and the remaining ones share the whole GPU.  A launch performs at most
+// steps_per_launch attempts and returns; every workgroup leaves the loop at
+// the same point (the exit test reads the control blocks after a barrier).
+
+template <typename R, int MODEL, int STAGE>
+__device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile, const int slot,
+                                            double* smem);
+
+// Grid-wide barrier: bar[0] counts arrivals, bar[1] is the generation.  The
+// last workgroup to arrive resets the count and advances the generation
+// (release); the others wait for the generation to change (acquire).  The
+// agent-scope fences make every workgroup's global writes before the barrier
+// visible to every workgroup after it (L2 write-back / invalidate across
+// XCDs).  The wait is bounded: on overrun *err is set and the workgroup
+// continues, so the kernel always terminates (the host then reports an
+// error).  All workgroups of the launch must be resident (the launch size
+// is capped by the occupancy limit and launched cooperatively).
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, unsigned* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived =
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 24)) {
+          __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+template <typename R, int MODEL>
+__global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
+                                                       const int* item_inst, int nitems,
+                                                       int ninst, int steps_per_launch,
+                                                       unsigned* bar, unsigned* err) {
+  __shared__ double smem[8 * kWaves];
+  for (int it = 0; it < steps_per_launch; ++it) {
+    // exit when every instance is done (same answer in every workgroup)
+    int active = 0;
+    for (int i = 0; i < ninst; ++i) active |= desc[i].st[0].ctl->done ? 0 : 1;
+    if (!active) break;
+#pragma unroll 1
+    for (int stage = 1; stage <= 5; ++stage) {
+      for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int inst = item_inst[item];
+        const BatchDesc& d = desc[inst];
+        const int tile = item - d.item0;
+        switch (stage) {
+          case 1: stage4_tile<R, MODEL, 1>(d.st[0], tile, tile, smem); break;
+          case 2: stage4_tile<R, MODEL, 2>(d.st[1], tile, tile, smem); break;
+          case 3: stage4_tile<R, MODEL, 3>(d.st[2], tile, tile, smem); break;
+          case 4: stage4_tile<R, MODEL, 4>(d.st[3], tile, tile, smem); break;
+          default: stage4_tile<R, MODEL, 5>(d.st[4], tile, tile, smem); break;
+        }
+      }
+      grid_barrier(bar, gridDim.x, err);
+    }
+    for (int inst = blockIdx.x; inst < ninst; inst += gridDim.x) {
+      const BatchDesc& d = desc[inst];
+      controller_body(d.st[0].ctl, d.p1, d.ntiles, d.p5, d.ntiles, d.h3, smem);
+    }
+    grid_barrier(bar, gridDim.x, err);
+  }
+}
+
+template <typename R, int MODEL>
+static hipError_t launch_batch_t(const BatchDesc* desc, const int* item_inst, int nitems,
+                                 int ninst, int steps, int grid_blocks, unsigned* bar,
+                                 unsigned* err, hipStream_t s) {
+  void* args[] = {(void*)&desc, (void*)&item_inst, (void*)&nitems, (void*)&ninst,
+                  (void*)&steps, (void*)&bar, (void*)&err};
+  return hipLaunchCooperativeKernel((const void*)batch_kernel<R, MODEL>, dim3(grid_blocks),
+                                    dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int* item_inst,
+                        int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
+                        unsigned* err, hipStream_t s) {
+  if (precision == PF_FP64) {
+    if (model == PF_MODEL_AC)
+      return launch_batch_t<double, PF_MODEL_AC>(desc, item_inst, nitems, ninst, steps,
+                                                 grid_blocks, bar, err, s);
+    return launch_batch_t<double, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, steps,
+                                                    grid_blocks, bar, err, s);
+  }
+  if (model == PF_MODEL_AC)
+    return launch_batch_t<float, PF_MODEL_AC>(desc, item_inst, nitems, ninst, steps,
+                                              grid_blocks, bar, err, s);
+  return launch_batch_t<float, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, steps,
+                                                 grid_blocks, bar, err, s);
+}
+
+int batch_max_blocks(int precision, int model) {
+  int per_cu = 0;
+  hipError_t e;
+  if (precision == PF_FP64)
+    e = model == PF_MODEL_AC
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<double, PF_MODEL_AC>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<double, PF_MODEL_COUPLED>, kBlock, 0);
+  else
+    e = model == PF_MODEL_AC
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<float, PF_MODEL_AC>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<float, PF_MODEL_COUPLED>, kBlock, 0);
+  if (e != hipSuccess || per_cu < 1) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
 }
 
 // ---------------------------------------------------------------------------
@@ -572,8 +712,8 @@ __device__ __forceinline__ R shfl_down1(R v) {
 }
 
 template <typename R, int MODEL, int STAGE>
-__global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
-  __shared__ double smem[8 * kWaves];
+__device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
+                                            const int slot, double* smem) {
   const ModelConst& m = a.mc;
   double t0 = a.t_fixed, dt = 0.0;
   int cur = 0;
@@ -589,8 +729,6 @@ __global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
   constexpr bool kCoupled = MODEL == PF_MODEL_COUPLED;
   constexpr int NV = kCoupled ? 2 : 1;
 
-  const int nblk = gridDim.x;
-  const int tile = xcd_tile(blockIdx.x, nblk);
   const int tp = tile % a.tiles_p, tz = tile / a.tiles_p;
   const uint32_t plane = (uint32_t)m.n1 * (uint32_t)m.n2;
   const uint32_t p = ((uint32_t)tp * kBlock + threadIdx.x) * 4u;
@@ -765,13 +903,21 @@ __global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
     const int ops[4] = {1, 0, 0, 0};
     block_reduce<4>(v, ops, smem);
     if (threadIdx.x == 0)
-      for (int i = 0; i < 4; ++i) a.part[(size_t)blockIdx.x * kPartS1 + i] = v[i];
+      for (int i = 0; i < 4; ++i) a.part[(size_t)slot * kPartS1 + i] = v[i];
+    __syncthreads();  // smem is reused by the next tile of a persistent block
   } else if (STAGE == 5) {
     double v[1] = {red0};
     const int ops[1] = {1};
     block_reduce<1>(v, ops, smem);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) a.part[slot] = v[0];
+    __syncthreads();
   }
+}
+
+template <typename R, int MODEL, int STAGE>
+__global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
+  __shared__ double smem[8 * kWaves];
+  stage4_tile<R, MODEL, STAGE>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,146 @@
+"""Batched sweep (one persistent cooperative kernel for many instances)
+against per-instance runs and the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import pf_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2401_01672_amd as pf  # noqa: E402
+
+
+def small_instances(k, precision="fp32", fixed_dt=None, seed0=500):
+    """k micro-scale instances of uneven sizes (n1 divisible by 4), each with
+    its own supercooling and surface-tension scale."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(k):
+        n1 = int(rng.choice([8, 12, 16, 20, 24]))
+        n2 = int(rng.integers(5, 19))
+        n3 = int(rng.integers(4, 23))
+        c = pi.sweep_instance(seed0 + i, edge=48)
+        p = dict(c.params, n1=n1, n2=n2, n3=n3)
+        p["dT"] = float(rng.uniform(0.05, 1.5))
+        p["alpha"] = pi.ALPHA_REAL / float(rng.choice([1, 10, 100, 1000]))
+        mask = (rng.random((n3, n2, n1)) < 0.25).astype(np.uint8)
+        phi = np.zeros((n3, n2, n1))
+        phi[n3 // 2 - 1:n3 // 2 + 1, n2 // 3:n2 // 3 + 3, n1 // 4:n1 // 4 + 4] = 1.0
+        phi[mask == 1] = 0.0
+        run = dict(c.run)
+        if fixed_dt is not None:
+            run["tol"] = 0.0
+        out.append((p, mask, phi, run))
+    return out
+
+
+def make_solvers(insts, precision, dt0):
+    npdt = np.float64 if precision == "fp64" else np.float32
+    ss = []
+    for p, mask, phi, run in insts:
+        s = pf.Solver(p, mask, precision, run)
+        s.set_state(phi.astype(npdt))
+        s.set_time(0.0, dt0)
+        ss.append(s)
+    return ss
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_individual_runs(precision):
+    insts = small_instances(7, precision)
+    batch = make_solvers(insts, precision, 1e-3)
+    stats_b = pf.batch_integrate(batch, max_steps=150)
+    single = make_solvers(insts, precision, 1e-3)
+    for i, s in enumerate(single):
+        st = s.integrate(max_steps=150)
+        sb = stats_b[i]
+        assert (st["steps_accepted"], st["steps_rejected"]) == \
+            (sb["steps_accepted"], sb["steps_rejected"])
+        assert st["t"] == sb["t"]
+        a, _ = s.get_state()
+        b, _ = batch[i].get_state()
+        assert np.array_equal(a, b), i
+        assert st["ice_count"] == sb["ice_count"]
+        assert sb["sum_phi"] == pytest.approx(st["sum_phi"], rel=1e-12)
+    for s in batch + single:
+        s.close()
+
+
+def test_batch_fp64_fixed_step_matches_oracle():
+    insts = small_instances(5, "fp64", fixed_dt=True, seed0=900)
+    # a common fixed step inside Merson's stability interval for every
+    # instance: dt * 12/(alpha h^2) <= 2 (the stiffest Laplacian mode)
+    dt = min(2.0 * p["alpha"] * p["h"] ** 2 / 12.0 for p, _, _, _ in insts)
+    batch = make_solvers(insts, "fp64", dt)
+    stats = pf.batch_integrate(batch, max_steps=25)
+    for i, (p, mask, phi, run) in enumerate(insts):
+        P = oracle.make_params(p)
+        ph_o, _, _ = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt, phi,
+                                      max_steps=25)
+        g, _ = batch[i].get_state()
+        gap = float(np.abs(g - ph_o).max() / max(np.abs(ph_o).max(), 1e-300))
+        assert gap <= 1e-12, (i, gap)
+        assert stats[i]["steps_accepted"] == 25
+        od = oracle.diagnostics(P, mask, ph_o)
+        assert stats[i]["ice_count"] == od["ice_count"]
+    for s in batch:
+        s.close()
+
+
+def test_batch_instances_finish_independently():
+    insts = small_instances(4, "fp32", seed0=1300)
+    ss = make_solvers(insts, "fp32", 1e-3)
+    # instance 1 gets a NaN: it must fail alone
+    phi = insts[1][2].astype(np.float32).copy()
+    phi.flat[3] = np.nan
+    ss[1].set_state(phi)
+    # instance 2 stops early at its own t_end via a short step budget
+    stats = pf.batch_integrate(ss, max_steps=60, raise_on_error=False)
+    assert stats[1]["status"] == pf.PF_ENONFINITE and stats[1]["steps_rejected"] == 1
+    for i in (0, 2, 3):
+        assert stats[i]["status"] == pf.PF_MAXSTEPS
+        assert stats[i]["steps_accepted"] + stats[i]["steps_rejected"] == 60
+    # a second call with a time limit: each instance clips to t_end itself
+    for i in (0, 2, 3):
+        ss[i].set_time(0.0, 1e-3)
+    st2 = pf.batch_integrate([ss[0], ss[2], ss[3]], t_end=0.05)
+    for st in st2:
+        assert st["status"] == pf.PF_OK and st["t"] == 0.05
+    for s in ss:
+        s.close()
+
+
+def test_batch_rejects_mixed_instances():
+    insts = small_instances(2, "fp32", seed0=1700)
+    a = make_solvers(insts[:1], "fp32", 1e-3)[0]
+    b = make_solvers(insts[1:], "fp64", 1e-3)[0]
+    with pytest.raises(pf.PFError):
+        pf.batch_integrate([a, b], max_steps=5)
+    a.close()
+    b.close()
+
+
+def test_sweep_instances_batch_to_equilibrium_small_subset():
+    """Four instances of the parametric sweep generator, run to equilibrium in
+    one batch; each agrees with its own single run."""
+    cases = [pi.sweep_instance(4000 + i) for i in (5, 9, 17, 27)]  # 48^3 edges
+    ss, single = [], []
+    for c in cases:
+        for lst in (ss, single):
+            s = pf.Solver(c.params, c.mask, "fp32", c.run)
+            s.set_state(c.phi0.astype(np.float32))
+            s.set_time(0.0, c.run["dt0"])
+            lst.append(s)
+    stats = pf.batch_integrate(ss, max_steps=400000, eq_tol=1e-6)
+    for i, s in enumerate(single):
+        st = s.integrate(max_steps=400000, eq_tol=1e-6)
+        assert stats[i]["status"] == pf.PF_EQUILIBRIUM == st["status"]
+        assert stats[i]["steps_accepted"] == st["steps_accepted"]
+        assert stats[i]["ice_count"] == st["ice_count"]
+    for s in ss + single:
+        s.close()
