@@ -190,16 +190,31 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
 
 /* Batched sweep: integrate n independent instances (same model and
  * precision, each with n1 divisible by 4, each with its own geometry,
- * constants, state, t and dt) with ONE persistent cooperative kernel per
- * batch of attempts: every stage pass processes the tiles of all unfinished
- * instances together, then each instance's own controller runs (per-instance
- * adaptive dt, equilibrium test and status).  Stops each instance at t_end,
+ * constants, state, t and dt) together: every stage pass processes the tiles
+ * of all unfinished instances in one launch (or one persistent cooperative
+ * kernel runs all passes of a poll interval, see pf_batch_options), then each
+ * instance's own controller runs (per-instance adaptive dt, equilibrium test
+ * and status); finished instances drop out.  Stops each instance at t_end,
  * max_steps attempts, or equilibrium (eq_tol > 0), like pf_integrate.
  * out[i] receives instance i's statistics (wall_s: the whole batch).  stream:
  * a hipStream_t cast to uintptr_t, 0 = the first instance's stream.
  * Returns PF_OK or the first instance error code; synchronous. */
+typedef struct {
+  int32_t mode;           /* 1: persistent cooperative kernel: one launch
+                                per poll interval, grid barriers between
+                                stages;
+                             2 (default): one launch per stage over all
+                                instances, the poll interval's attempts
+                                captured once and replayed as a HIP graph  */
+  int32_t z_chunk;        /* planes per work item (0: 4)                   */
+  int32_t steps_per_poll; /* attempts between host checks (0: 32)          */
+  int32_t pad;
+} pf_batch_options;
+
+/* opts may be NULL (defaults). */
 int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t max_steps,
-                       double eq_tol, pf_run_stats* out, uintptr_t stream);
+                       double eq_tol, pf_run_stats* out, uintptr_t stream,
+                       const pf_batch_options* opts);
 
 /* Diagnostics of the current state into stats (ice/pore counts, sum_phi,
  * enthalpy); the step counters and t are left as the last run set them. */

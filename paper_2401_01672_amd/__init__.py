@@ -76,7 +76,8 @@ SIGNATURES = [
     ("pf_integrate", C.c_int, [_H, C.c_double, C.c_int64, C.c_double, C.POINTER(PFRunStats)]),
     ("pf_diagnostics", C.c_int, [_H, C.POINTER(PFRunStats)]),
     ("pf_batch_integrate", C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_int64,
-                                     C.c_double, C.POINTER(PFRunStats), C.c_size_t]),
+                                     C.c_double, C.POINTER(PFRunStats), C.c_size_t,
+                                     C.c_void_p]),
     ("pf_set_loop", C.c_int, [_H, C.c_int32, C.c_int32]),
     ("pf_set_tile", C.c_int, [_H, C.c_int32]),
     ("pf_set_schedule", C.c_int, [_H, C.c_int32]),
@@ -293,14 +294,26 @@ class Solver:
         self._check(lib().pf_synchronize(self.h))
 
 
+class PFBatchOptions(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("z_chunk", C.c_int32), ("steps_per_poll", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+BATCH_MODES = {"persistent": 1, "graph": 2}
+
+
 def batch_integrate(solvers, t_end: float = float("inf"), max_steps: int = 2**62,
-                    eq_tol: float = 0.0, raise_on_error: bool = True):
-    """pf_batch_integrate over Solver objects (one persistent kernel for all).
-    Returns one stats dict per solver."""
+                    eq_tol: float = 0.0, raise_on_error: bool = True, mode: str = "graph",
+                    z_chunk: int = 0, steps_per_poll: int = 0):
+    """pf_batch_integrate over Solver objects: 'persistent' (one cooperative
+    kernel per poll interval) or 'graph' (per-stage launches replayed as a
+    HIP graph).  Returns one stats dict per solver."""
     n = len(solvers)
     hs = (C.c_void_p * n)(*[s.h for s in solvers])
     out = (PFRunStats * n)()
-    rc = lib().pf_batch_integrate(hs, n, float(t_end), int(max_steps), float(eq_tol), out, 0)
+    opts = PFBatchOptions(BATCH_MODES[mode], int(z_chunk), int(steps_per_poll), 0)
+    rc = lib().pf_batch_integrate(hs, n, float(t_end), int(max_steps), float(eq_tol), out, 0,
+                                  C.byref(opts))
     if rc < 0 and raise_on_error:
         raise PFError(rc, lib().pf_last_error(solvers[0].h).decode() or
                       lib().pf_last_error(None).decode())

@@ -746,8 +746,13 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
 }
 
 int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t max_steps,
-                       double eq_tol, pf_run_stats* out, uintptr_t stream) {
+                       double eq_tol, pf_run_stats* out, uintptr_t stream,
+                       const pf_batch_options* opts) {
   if (!inst || n < 1 || !out) return fail(nullptr, PF_EINVAL, "batch: inst, n >= 1 and out required");
+  const int mode = (opts && opts->mode) ? opts->mode : 2;
+  if (mode != 1 && mode != 2) return fail(nullptr, PF_EINVAL, "batch: mode must be 1 or 2");
+  if (opts && (opts->z_chunk < 0 || opts->steps_per_poll < 0))
+    return fail(nullptr, PF_EINVAL, "batch: negative option");
   auto w0 = std::chrono::steady_clock::now();
   for (int i = 0; i < n; ++i) {
     if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
@@ -758,8 +763,10 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   }
   pf_handle* h0 = inst[0];
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : h0->own_stream;
-  const int kBatchZ = 4;        // planes per work item: fine-grained load balance
-  const int kStepsPerLaunch = 32;
+  // planes per work item (small: fine-grained load balance) and attempts
+  // between host checks of the control blocks
+  const int kBatchZ = (opts && opts->z_chunk) ? opts->z_chunk : 4;
+  const int kStepsPerLaunch = (opts && opts->steps_per_poll) ? opts->steps_per_poll : 32;
   std::vector<pf::BatchDesc> desc(n);
   std::vector<int> item_inst;
   int item0 = 0;
@@ -823,13 +830,33 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     return fail(h0, PF_EHIP, "batch: occupancy query failed");
   }
   if (grid > nitems) grid = nitems;
+  hipGraphExec_t gexec = nullptr;
+  if (mode == 2) {
+    // capture kStepsPerLaunch attempts of all instances once, replay below
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
+      e = pf::launch_batch_step(h0->P.precision, h0->P.model, ddesc, ditem, nitems, n, s);
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e == hipSuccess && e2 == hipSuccess) {
+      e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess || e2 != hipSuccess) {
+      cleanup();
+      return fail(h0, PF_EHIP, "batch: graph capture failed");
+    }
+  }
   for (;;) {
     bool any = false;
     for (int i = 0; i < n; ++i) any |= !inst[i]->hctl->done;
     if (!any) break;
-    hipError_t e = pf::launch_batch(h0->P.precision, h0->P.model, ddesc, ditem, nitems, n,
-                                    kStepsPerLaunch, grid, dbar, dbar + 2, s);
+    hipError_t e = mode == 1 ? pf::launch_batch(h0->P.precision, h0->P.model, ddesc, ditem,
+                                                nitems, n, kStepsPerLaunch, grid, dbar,
+                                                dbar + 2, s)
+                             : hipGraphLaunch(gexec, s);
     if (e != hipSuccess) {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
       cleanup();
       return fail(h0, PF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
@@ -845,10 +872,12 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       return fail(h0, PF_EHIP, "batch: synchronize failed");
     }
     if (hbar[2]) {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
       cleanup();
       return fail(h0, PF_EHIP, "batch: a grid barrier wait overran its bound");
     }
   }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
   cleanup();
   const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
   int ret = PF_OK;

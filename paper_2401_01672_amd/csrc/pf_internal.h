@@ -152,4 +152,7 @@ hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const i
                         int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
                         unsigned* err, hipStream_t s);
 int batch_max_blocks(int precision, int model);
+// batched sweep, multi-launch form: one attempt = 5 stage launches + 1 controller
+hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc,
+                             const int* item_inst, int nitems, int ninst, hipStream_t s);
 }  // namespace pf

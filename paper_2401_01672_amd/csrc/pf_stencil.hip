@@ -547,6 +547,50 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
   }
 }
 
+// Multi-launch form of the batched sweep: one launch per stage over all
+// (instance, tile) items (one item per workgroup, XCD-aware order), one
+// controller launch with one workgroup per instance; the host captures a run
+// of attempts into a HIP graph.  Same per-cell arithmetic as batch_kernel.
+template <typename R, int MODEL, int STAGE>
+__global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchDesc* desc,
+                                                             const int* item_inst) {
+  __shared__ double smem[8 * kWaves];
+  const int item = xcd_tile(blockIdx.x, gridDim.x);
+  const BatchDesc& d = desc[item_inst[item]];
+  const int tile = item - d.item0;
+  stage4_tile<R, MODEL, STAGE>(d.st[STAGE - 1], tile, tile, smem);
+}
+
+__global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc) {
+  __shared__ double smem[8 * kWaves];
+  const BatchDesc& d = desc[blockIdx.x];
+  controller_body(d.st[0].ctl, d.p1, d.ntiles, d.p5, d.ntiles, d.h3, smem);
+}
+
+template <typename R, int MODEL>
+static hipError_t launch_batch_step_t(const BatchDesc* desc, const int* item_inst, int nitems,
+                                      int ninst, hipStream_t s) {
+  const dim3 g((unsigned)nitems), b(kBlock);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1>), g, b, 0, s, desc, item_inst);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2>), g, b, 0, s, desc, item_inst);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3>), g, b, 0, s, desc, item_inst);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4>), g, b, 0, s, desc, item_inst);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5>), g, b, 0, s, desc, item_inst);
+  hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc,
+                             const int* item_inst, int nitems, int ninst, hipStream_t s) {
+  if (precision == PF_FP64)
+    return model == PF_MODEL_AC
+               ? launch_batch_step_t<double, PF_MODEL_AC>(desc, item_inst, nitems, ninst, s)
+               : launch_batch_step_t<double, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, s);
+  return model == PF_MODEL_AC
+             ? launch_batch_step_t<float, PF_MODEL_AC>(desc, item_inst, nitems, ninst, s)
+             : launch_batch_step_t<float, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, s);
+}
+
 template <typename R, int MODEL>
 static hipError_t launch_batch_t(const BatchDesc* desc, const int* item_inst, int nitems,
                                  int ninst, int steps, int grid_blocks, unsigned* bar,

@@ -50,11 +50,12 @@ def make_solvers(insts, precision, dt0):
     return ss
 
 
+@pytest.mark.parametrize("mode", ["persistent", "graph"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_batch_equals_individual_runs(precision):
+def test_batch_equals_individual_runs(precision, mode):
     insts = small_instances(7, precision)
     batch = make_solvers(insts, precision, 1e-3)
-    stats_b = pf.batch_integrate(batch, max_steps=150)
+    stats_b = pf.batch_integrate(batch, max_steps=150, mode=mode, z_chunk=3, steps_per_poll=7)
     single = make_solvers(insts, precision, 1e-3)
     for i, s in enumerate(single):
         st = s.integrate(max_steps=150)
@@ -136,7 +137,7 @@ def test_sweep_instances_batch_to_equilibrium_small_subset():
             s.set_state(c.phi0.astype(np.float32))
             s.set_time(0.0, c.run["dt0"])
             lst.append(s)
-    stats = pf.batch_integrate(ss, max_steps=400000, eq_tol=1e-6)
+    stats = pf.batch_integrate(ss, max_steps=400000, eq_tol=1e-6, mode="graph")
     for i, s in enumerate(single):
         st = s.integrate(max_steps=400000, eq_tol=1e-6)
         assert stats[i]["status"] == pf.PF_EQUILIBRIUM == st["status"]

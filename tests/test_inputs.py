@@ -112,6 +112,10 @@ def test_sweep_instances_draws():
         assert s.params["alpha"] == pytest.approx(pi.ALPHA_REAL / m["sigma_scale"])
         assert 0.28 <= m["solid_fraction"] <= 0.42
         assert s.phi0.sum() > 0 and np.all(s.phi0[s.mask == 1] == 0)
+        # the stiffest phase-field mode times the tolerance stays below half
+        # the equilibrium threshold
+        lam_max = 12.0 / (s.params["alpha"] * s.params["h"] ** 2)
+        assert s.run["tol"] <= 1e-6 and lam_max * s.run["tol"] <= 0.5 * s.run["eq_tol"] * 1.0001
     w = pi.warmstart_instance(10000)
     assert w.mask.shape == (96, 96, 96)
 
