@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 #                      | S5 r Y5 P C, w y_new
 PASS_WORDS = {"five": [3, 3, 5, 7, 4], "paired": [3, 6, 4]}
 PASS_NAMES = {"five": ["S1", "S2", "S3", "S4", "S5"], "paired": ["S1+S2", "S3+S4", "S5"]}
-PASS_KERNELS = {"five": ["stage_kernel<..,1>", "stage_kernel<..,2>", "stage_kernel<..,3>",
-                         "stage_kernel<..,4>", "stage_kernel<..,5>"],
+PASS_KERNELS = {"five": ["stage4_kernel<..,1>", "stage4_kernel<..,2>", "stage4_kernel<..,3>",
+                         "stage4_kernel<..,4>", "stage4_kernel<..,5>"],
                 "paired": ["pair_kernel<..,1,..>", "pair_kernel<..,3,..>",
                            "stage_kernel<..,5>"]}
 

@@ -94,7 +94,7 @@ def pass_of(name: str, schedule: str):
     args = _template_args(name)
     if "pair_kernel<" in name and schedule == "paired" and len(args) >= 3:
         return 1 if args[2] == "1" else 2
-    if "stage_kernel<" in name and len(args) >= 3:
+    if ("stage_kernel<" in name or "stage4_kernel<" in name) and len(args) >= 3:
         st = int(args[2])
         if schedule == "five":
             return st if st >= 1 else None
@@ -133,9 +133,46 @@ def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_
     print("\n".join(written))
 
 
+def kernel_stats(title: str, trace_dir: str, command: str, out: str):
+    """Markdown table of per-kernel durations from a rocprofv3 kernel trace.
+
+    Besides the plain average over all dispatches it gives the average over
+    working dispatches: a stencil pass launched after the step controller has
+    already stopped (the tail of a captured batch of attempts) exits at once,
+    and those few-microsecond dispatches are excluded there (duration below
+    20% of the kernel's median)."""
+    import statistics
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no kernel_trace.csv under {trace_dir}")
+    by = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            by.setdefault(r["Kernel_Name"], []).append(d)
+    total = sum(sum(v) for v in by.values())
+    lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (repo root):", "", "```",
+             command, "```", "",
+             "| kernel | calls | avg us | working calls | working avg us | min us | max us | % time |",
+             "|---|---|---|---|---|---|---|---|"]
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        med = statistics.median(v)
+        w = [x for x in v if x >= 0.2 * med]
+        lines.append(f"| `{k[:90]}` | {len(v)} | {sum(v) / len(v):.2f} | {len(w)} | "
+                     f"{sum(w) / len(w):.2f} | {min(v):.2f} | {max(v):.2f} | "
+                     f"{100 * sum(v) / total:.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("stats")
+    k.add_argument("--title", required=True)
+    k.add_argument("--trace", required=True)
+    k.add_argument("--command", required=True)
+    k.add_argument("--out", required=True)
     r = sub.add_parser("run")
     r.add_argument("--workload", default="coupled_256_fp32")
     r.add_argument("--schedule", default="five", choices=["paired", "five"])
@@ -147,7 +184,9 @@ def main():
     s.add_argument("--write", required=True)
     s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
-    if a.cmd == "run":
+    if a.cmd == "stats":
+        kernel_stats(a.title, a.trace, a.command, a.out)
+    elif a.cmd == "run":
         run(a.workload, a.schedule, a.steps)
     else:
         summarize(a.workload, a.schedule, a.fetch, a.write, a.out)
