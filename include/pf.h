@@ -265,6 +265,107 @@ int pf_synchronize(pf_handle* h);
  * allocate matching buffers). */
 int64_t pf_num_cells(const pf_handle* h);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method: an accelerator for
+ * sweeps to equilibrium).  A 3D U-Net maps the glass mask, the supercooling
+ * dT and the surface-tension scale s (alpha = alpha_real / s) of a
+ * micro-scale problem to a phase field phi0 on the water cells, which then
+ * relaxes to equilibrium under the model of Sec. 2.4 (pf_integrate).
+ *
+ * Architecture: input channels {glass (0/1), log10(dT / 0.2 K),
+ * (log10 s - 1.5) / 1.5, 5 zero channels}; levels of 16, 32, 64 channels
+ * at full, half and quarter resolution; per level (and per decoder stage)
+ * two 3x3x3 convolutions (zero padding) + ReLU; 2x average pooling; nearest
+ * 2x upsampling; skip connections by channel concatenation [upsampled,
+ * skip]; 1x1 head + sigmoid, 0 on glass cells.  Convolutions run as
+ * implicit GEMMs on BF16 matrix cores with FP32 accumulation; activations
+ * are BF16, parameters, gradients and Adam moments FP32.
+ *
+ * Flat parameter vector (pf_unet_num_params floats): for each of the ten
+ * convolutions in the order enc1a, enc1b, enc2a, enc2b, enc3a, enc3b,
+ * dec2a, dec2b, dec1a, dec1b: weights [cout][27][cin] with tap
+ * (dz+1)*9 + (dy+1)*3 + (dx+1) (dx along x1, dz along x3), then bias
+ * [cout]; then the head's 16 weights and 1 bias.  Channel counts (cin ->
+ * cout): 8->16, 16->16, 16->32, 32->32, 32->64, 64->64, 96->32, 32->32,
+ * 48->16, 16->16 (pf_unet_layer_info).
+ *
+ * Grids: n1, n2, n3 positive multiples of 4 with n1*n2*n3 < 2^24.  All
+ * pointers named mask/target/out are device pointers: mask n cells of
+ * uint8 (nonzero = glass), target and out n floats, layout
+ * i1 + n1*(i2 + n2*i3).  Each call works on the network's stream
+ * (pf_unet_set_stream; default the null stream).  A network object must not
+ * be used from two threads at once.
+ * ------------------------------------------------------------------------ */
+typedef struct pf_unet pf_unet;
+
+/* New network with He-normal weights drawn from SplitMix64(seed) and zero
+ * biases.  Errors: PF_EINVAL (out NULL), PF_ENOMEM, PF_EHIP. */
+int pf_unet_create(uint64_t seed, pf_unet** out);
+void pf_unet_destroy(pf_unet* net);
+const char* pf_unet_last_error(const pf_unet* net);
+int pf_unet_set_stream(pf_unet* net, uintptr_t stream);
+int64_t pf_unet_num_params(void);
+
+/* Copy the parameter vector out / in (host pointers, pf_unet_num_params
+ * floats).  Setting parameters resets the Adam state.  Synchronous. */
+int pf_unet_get_params(pf_unet* net, float* host_out);
+int pf_unet_set_params(pf_unet* net, const float* host_in);
+
+/* Inference: out = network(mask, dT, s) with log10_sigma_scale = log10 s.
+ * Asynchronous on the network's stream. */
+int pf_unet_forward(pf_unet* net, const uint8_t* mask, int32_t n1, int32_t n2, int32_t n3,
+                    double dT, double log10_sigma_scale, float* out);
+
+/* Loss L = mean over water cells of (out - target)^2 and its gradient with
+ * respect to the parameter vector (written to grad_host if non-NULL;
+ * *loss if non-NULL).  No update.  Synchronous. */
+int pf_unet_grad(pf_unet* net, const uint8_t* mask, const float* target, int32_t n1, int32_t n2,
+                 int32_t n3, double dT, double log10_sigma_scale, float* grad_host,
+                 double* loss);
+
+/* One training step on one sample: the gradient as in pf_unet_grad, then one
+ * Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr.  Asynchronous unless loss is non-NULL (then it waits for
+ * the loss of this sample, before the update). */
+int pf_unet_train_step(pf_unet* net, const uint8_t* mask, const float* target, int32_t n1,
+                       int32_t n2, int32_t n3, double dT, double log10_sigma_scale, double lr,
+                       double* loss);
+
+/* Mean duration of each of the ten forward convolutions on an n1 x n2 x n3
+ * input (ms[0..9]; reps launches back to back between HIP events on the
+ * network's stream; the activation buffers hold whatever the last call
+ * left).  Synchronous. */
+int pf_unet_time_layers(pf_unet* net, int32_t n1, int32_t n2, int32_t n3, int32_t reps,
+                        double* ms);
+
+/* out[0..7] = {cin, cout, weight offset, bias offset, grid level (0 full,
+ * 1 half, 2 quarter), head weight offset, head bias offset, number of
+ * convolutions} of convolution `layer`. */
+int pf_unet_layer_info(int32_t layer, int32_t* out);
+
+/* Write the network's prediction for the handle's mask (PF_MODEL_AC or
+ * PF_MODEL_COUPLED; dT > 0, log10_sigma_scale = log10 s) into the handle's
+ * current phi (in its precision; theta, t and dt are not changed).  The
+ * handle's n1, n2, n3 must satisfy the network's grid rule.  Synchronous. */
+int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale);
+
+/* Building blocks (each call allocates and frees its own scratch; device
+ * pointers; BF16 tensors channels-last [n][c], FP32 weights [cout][27][cin],
+ * taps as above).  y = act(conv3x3x3(x) + b) with act = ReLU if relu != 0;
+ * cin % 8 == 0, cout in {16, 32, 48, 64, 96}; b may be NULL.  Synchronous. */
+int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b, int32_t relu,
+                  uint16_t* y, int32_t cout, int32_t n1, int32_t n2, int32_t n3,
+                  uintptr_t stream);
+/* Gradients of y = conv3x3x3(x) + b given dy: dw [cout][27][cin], db [cout],
+ * and dx [n][cin] if dx is non-NULL (then cin in {16, 32, 48, 64, 96}).
+ * (cout/16) * ceil(cin/16) <= 16.  Synchronous. */
+int pf_conv3_bf16_backward(const uint16_t* x, int32_t cin, const float* w, const uint16_t* dy,
+                           int32_t cout, int32_t n1, int32_t n2, int32_t n3, uint16_t* dx,
+                           float* dw, float* db, uintptr_t stream);
+/* One 16x16x32 BF16 matrix-core product c = a b (a 16x32, b 32x16, c 16x16,
+ * row-major FP32, device pointers; inputs rounded to BF16). */
+int pf_mfma_probe(const float* a, const float* b, float* c, uintptr_t stream);
+
 /* Library ABI version. */
 int pf_abi_version(void);
 

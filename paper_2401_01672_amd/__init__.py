@@ -88,6 +88,29 @@ SIGNATURES = [
     ("pf_synchronize", C.c_int, [_H]),
     ("pf_num_cells", C.c_int64, [_H]),
     ("pf_abi_version", C.c_int, []),
+    ("pf_unet_create", C.c_int, [C.c_uint64, C.POINTER(C.c_void_p)]),
+    ("pf_unet_destroy", None, [_H]),
+    ("pf_unet_last_error", C.c_char_p, [_H]),
+    ("pf_unet_set_stream", C.c_int, [_H, C.c_size_t]),
+    ("pf_unet_num_params", C.c_int64, []),
+    ("pf_unet_get_params", C.c_int, [_H, _VP]),
+    ("pf_unet_set_params", C.c_int, [_H, _VP]),
+    ("pf_unet_forward", C.c_int, [_H, _VP, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                  C.c_double, _VP]),
+    ("pf_unet_grad", C.c_int, [_H, _VP, _VP, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                               C.c_double, _VP, C.POINTER(C.c_double)]),
+    ("pf_unet_train_step", C.c_int, [_H, _VP, _VP, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(C.c_double)]),
+    ("pf_unet_time_layers", C.c_int, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_double)]),
+    ("pf_unet_layer_info", C.c_int, [C.c_int32, C.POINTER(C.c_int32)]),
+    ("pf_warmstart", C.c_int, [_H, _H, C.c_double, C.c_double]),
+    ("pf_conv3_bf16", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32,
+                                C.c_int32, C.c_int32, C.c_int32, C.c_size_t]),
+    ("pf_conv3_bf16_backward", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, C.c_int32,
+                                         C.c_int32, C.c_int32, _VP, _VP, _VP, C.c_size_t]),
+    ("pf_mfma_probe", C.c_int, [_VP, _VP, _VP, C.c_size_t]),
 ]
 
 
@@ -318,3 +341,155 @@ def batch_integrate(solvers, t_end: float = float("inf"), max_steps: int = 2**62
         raise PFError(rc, lib().pf_last_error(solvers[0].h).decode() or
                       lib().pf_last_error(None).decode())
     return [Solver._stats(out[i], rc) for i in range(n)]
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start
+
+
+def unet_num_params() -> int:
+    return int(lib().pf_unet_num_params())
+
+
+def unet_layer_info(layer: int) -> Dict:
+    out = (C.c_int32 * 8)()
+    rc = lib().pf_unet_layer_info(int(layer), out)
+    if rc != 0:
+        raise PFError(rc, f"no convolution {layer}")
+    v = list(out)
+    return dict(cin=v[0], cout=v[1], w_off=v[2], b_off=v[3], level=v[4], head_w=v[5],
+                head_b=v[6], layers=v[7])
+
+
+def _dev_ptr(t, dtype=None) -> int:
+    """Address of a contiguous CUDA tensor (optionally of a given dtype)."""
+    assert t.is_cuda and t.is_contiguous(), "device tensor expected"
+    if dtype is not None:
+        assert t.dtype == dtype, (t.dtype, dtype)
+    return t.data_ptr()
+
+
+class UNet:
+    """Warm-start network: owns a pf_unet (parameters, Adam state, buffers)."""
+
+    def __init__(self, seed: int = 0):
+        h = C.c_void_p()
+        rc = lib().pf_unet_create(C.c_uint64(int(seed)), C.byref(h))
+        if rc != 0:
+            raise PFError(rc, "pf_unet_create failed")
+        self.h = h
+
+    def _check(self, rc: int) -> int:
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_unet_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pf_unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(unet_num_params(), np.float32)
+        self._check(lib().pf_unet_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == unet_num_params()
+        self._check(lib().pf_unet_set_params(self.h, p.ctypes.data))
+
+    def forward(self, mask, dT: float, log10_s: float, out=None):
+        """mask: uint8 CUDA tensor (n3, n2, n1), nonzero = glass; returns the
+        FP32 prediction (CUDA tensor of the same shape)."""
+        import torch
+        n3, n2, n1 = mask.shape
+        if out is None:
+            out = torch.empty(mask.shape, dtype=torch.float32, device=mask.device)
+        self._check(lib().pf_unet_forward(self.h, _dev_ptr(mask, torch.uint8), n1, n2, n3,
+                                          float(dT), float(log10_s),
+                                          _dev_ptr(out, torch.float32)))
+        torch.cuda.synchronize()
+        return out
+
+    def grad(self, mask, target, dT: float, log10_s: float):
+        """(loss, gradient vector) of the masked MSE, no update."""
+        import torch
+        n3, n2, n1 = mask.shape
+        g = np.empty(unet_num_params(), np.float32)
+        loss = C.c_double()
+        self._check(lib().pf_unet_grad(self.h, _dev_ptr(mask, torch.uint8),
+                                       _dev_ptr(target, torch.float32), n1, n2, n3, float(dT),
+                                       float(log10_s), g.ctypes.data, C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, mask, target, dT: float, log10_s: float, lr: float,
+                   want_loss: bool = True):
+        import torch
+        n3, n2, n1 = mask.shape
+        loss = C.c_double()
+        self._check(lib().pf_unet_train_step(self.h, _dev_ptr(mask, torch.uint8),
+                                             _dev_ptr(target, torch.float32), n1, n2, n3,
+                                             float(dT), float(log10_s), float(lr),
+                                             C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def time_layers(self, shape, reps: int = 5):
+        n3, n2, n1 = shape
+        out = (C.c_double * 10)()
+        self._check(lib().pf_unet_time_layers(self.h, n1, n2, n3, int(reps), out))
+        return list(out)
+
+    def warmstart(self, solver: "Solver", dT: float, log10_s: float):
+        """Write the prediction into the solver's current phi."""
+        solver._check(lib().pf_warmstart(solver.h, self.h, float(dT), float(log10_s)))
+
+
+def conv3_bf16(x, w, b, relu: bool, cout: int):
+    """Building block: y = act(conv3x3x3(x) + b); x (n3, n2, n1, cin) as
+    int16 bit patterns of BF16 (CUDA), w (cout, 27, cin) FP32 CUDA, b (cout,)
+    FP32 CUDA or None.  Returns y (n3, n2, n1, cout) BF16 bits."""
+    import torch
+    n3, n2, n1, cin = x.shape
+    y = torch.empty((n3, n2, n1, cout), dtype=torch.int16, device=x.device)
+    rc = lib().pf_conv3_bf16(_dev_ptr(x, torch.int16), cin, _dev_ptr(w, torch.float32),
+                             0 if b is None else _dev_ptr(b, torch.float32), 1 if relu else 0,
+                             _dev_ptr(y), cout, n1, n2, n3, 0)
+    if rc != 0:
+        raise PFError(rc, "pf_conv3_bf16 failed")
+    return y
+
+
+def conv3_bf16_backward(x, w, dy, want_dx: bool = True):
+    """Building block: (dx BF16 bits or None, dw FP32, db FP32) for
+    y = conv3x3x3(x) + b given dy (n3, n2, n1, cout) BF16 bits."""
+    import torch
+    n3, n2, n1, cin = x.shape
+    cout = dy.shape[-1]
+    dx = torch.empty_like(x) if want_dx else None
+    dw = torch.empty((cout, 27, cin), dtype=torch.float32, device=x.device)
+    db = torch.empty((cout,), dtype=torch.float32, device=x.device)
+    rc = lib().pf_conv3_bf16_backward(_dev_ptr(x, torch.int16), cin, _dev_ptr(w, torch.float32),
+                                      _dev_ptr(dy, torch.int16), cout, n1, n2, n3,
+                                      0 if dx is None else _dev_ptr(dx), _dev_ptr(dw),
+                                      _dev_ptr(db), 0)
+    if rc != 0:
+        raise PFError(rc, "pf_conv3_bf16_backward failed")
+    return dx, dw, db
+
+
+def mfma_probe(a, b):
+    """c = a b through one 16x16x32 BF16 matrix-core instruction."""
+    import torch
+    c = torch.empty((16, 16), dtype=torch.float32, device=a.device)
+    rc = lib().pf_mfma_probe(_dev_ptr(a, torch.float32), _dev_ptr(b, torch.float32),
+                             _dev_ptr(c), 0)
+    if rc != 0:
+        raise PFError(rc, "pf_mfma_probe failed")
+    return c

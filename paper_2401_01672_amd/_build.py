@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpf.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["pf_stencil.hip", "pf_api.hip"]
+SOURCES = ["pf_stencil.hip", "pf_api.hip", "pf_unet.hip", "pf_unet_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "pf_internal.h"
+#include "pf_unet_internal.h"
 
 using pf::DevCtl;
 using pf::ModelConst;
@@ -395,6 +396,21 @@ int autotune(pf_handle* h) {
 extern "C" {
 
 int pf_abi_version(void) { return 1; }
+
+int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale) {
+  if (!h) return PF_EINVAL;
+  if (!net) return fail(h, PF_EINVAL, "network must be non-NULL");
+  if (h->P.model != PF_MODEL_AC && h->P.model != PF_MODEL_COUPLED)
+    return fail(h, PF_EINVAL, "warm start needs a phase-field model (PF_MODEL_AC or PF_MODEL_COUPLED)");
+  if (!(dT > 0.0)) return fail(h, PF_EINVAL, "dT must be positive");
+  std::string e;
+  const int r = pfu_forward_into(net, h->code, h->P.n1, h->P.n2, h->P.n3, dT, log10_sigma_scale,
+                                 h->y[h->cur][0], h->P.precision == PF_FP64 ? 1 : 0, h->stream,
+                                 &e);
+  if (r != PF_OK) return fail(h, r, "warm start: " + e);
+  PF_HIP(h, hipStreamSynchronize(h->stream));
+  return PF_OK;
+}
 
 const char* pf_last_error(const pf_handle* h) {
   if (!h) return g_create_err.c_str();

@@ -1,0 +1,654 @@
+// Learned warm start: a small 3D U-Net trained and evaluated with
+// hand-written BF16 MFMA kernels for gfx950 (v_mfma_f32_16x16x32_bf16).
+//
+// Activations are channels-last BF16: element (voxel v, channel c) of a view
+// {ptr, C, stride, offset} sits at ptr[v * stride + offset + c], so the two
+// halves of a skip concatenation are written in place by their producers.
+// Master weights are FP32 [co][tap][ci] (tap = (dz+1)*9 + (dy+1)*3 + (dx+1));
+// the kernels read BF16 copies: forward [co][k] with k = tap*Cin + ci, and
+// the data-gradient copy [ci][k'] with k' = (26 - tap)*Cout + co (taps
+// mirrored), both zero-padded to a multiple of 32 in k.  All accumulation is
+// FP32.
+//
+// MFMA 16x16x32 BF16 operand layout (one wavefront, lane l, g = l / 16):
+//   A (16 x 32): lane holds A[l % 16][8g .. 8g+7]
+//   B (32 x 16): lane holds B[8g .. 8g+7][l % 16]
+//   D (16 x 16): lane holds D[4g .. 4g+3][l % 16]
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pf_unet_internal.h"
+
+namespace pfu {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+// round to nearest even
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+  bf16x8 z;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+  return z;
+}
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+// ---------------------------------------------------------------------------
+// Probe of the MFMA operand layout (used by a test): C = A(16x32) B(32x16)
+// with A, B row-major FP32 inputs converted to BF16.
+__global__ void mfma_layout_probe(const float* A, const float* B, float* C) {
+  const int l = threadIdx.x, g = l >> 4, r = l & 15;
+  bf16x8 a, b;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a[j] = (__bf16)A[r * 32 + 8 * g + j];
+    b[j] = (__bf16)B[(8 * g + j) * 16 + r];
+  }
+  f32x4 d = {0.f, 0.f, 0.f, 0.f};
+  d = mfma16(a, b, d);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) C[(4 * g + i) * 16 + r] = d[i];
+}
+
+// ---------------------------------------------------------------------------
+// 3x3x3 convolution, stride 1, zero padding, as an implicit GEMM:
+//   out[v][co] = act( bias[co] + sum_k W[co][k] X[k][v] ),
+//   X[k = tap*Cin + ci][v] = in[v + offset(tap)][ci]  (0 outside the grid).
+// A workgroup has 4 wavefronts; a wavefront owns NT tiles of 16 consecutive
+// voxels and all Cout/16 output-channel tiles.  Per k-block of 32 each lane
+// loads 8 input channels of one tap for one voxel (16 bytes) and the matching
+// weights, and issues MT x NT MFMAs.  The epilogue adds the bias, applies the
+// ReLU, and stores 4 consecutive BF16 channels per lane.
+
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void conv3_fwd_kernel(ConvArgs a) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long nvox = (long long)a.n1 * a.n2 * a.n3;
+  const long long vbase = (long long)wave * (16 * NT);
+  if (vbase >= nvox) return;
+  // this lane's voxel in each tile (B operand column / D column)
+  int vx[NT], vy[NT], vz[NT];
+  bool vin[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const long long v = vbase + 16 * t + r;
+    vin[t] = v < nvox;
+    const long long vv = vin[t] ? v : 0;
+    vx[t] = (int)(vv % a.n1);
+    vy[t] = (int)((vv / a.n1) % a.n2);
+    vz[t] = (int)(vv / ((long long)a.n1 * a.n2));
+  }
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int kblocks = a.kpad / 32;
+  for (int kb = 0; kb < kblocks; ++kb) {
+    const int k0 = kb * 32 + 8 * g;
+    const int tap = k0 / a.cin, ci0 = k0 - tap * a.cin;
+    bf16x8 bfrag[NT];
+    if (tap < 27) {
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int x = vx[t] + dx, y = vy[t] + dy, z = vz[t] + dz;
+        const bool ok = vin[t] && x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3;
+        const long long src = ((long long)z * a.n2 + y) * a.n1 + x;
+        bfrag[t] = ok ? ld8(a.in + src * a.in_stride + a.in_off + ci0) : zero8();
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bfrag[t] = zero8();
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const bf16x8 afrag = ld8(a.w + (long long)(m * 16 + r) * a.kpad + k0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = mfma16(afrag, bfrag[t], acc[m][t]);
+    }
+  }
+  // epilogue: lane holds channels m*16 + 4g .. +3 of voxel vbase + 16t + r
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (!vin[t]) continue;
+    const long long v = vbase + 16 * t + r;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int co = m * 16 + 4 * g;
+      uint16_t o[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float y = acc[m][t][i] + (a.bias ? a.bias[co + i] : 0.0f);
+        if (a.relu) y = y > 0.0f ? y : 0.0f;
+        o[i] = f2bf(y);
+      }
+      uint2 pk;
+      pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+      pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+      *reinterpret_cast<uint2*>(a.out + v * a.out_stride + a.out_off + co) = pk;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient as an implicit GEMM over voxels:
+//   dW[co][tap][ci] = sum_v dY[v][co] X[v + offset(tap)][ci],  db[co] = sum_v dY[v][co].
+// Grid (voxel ranges) x (27 taps).  A workgroup walks its voxel range in
+// chunks of kWgChunk: the chunk of dY and the shifted chunk of X are loaded
+// 8 channels (16 bytes) at a time and stored transposed in LDS
+// ([channel][voxel], rows padded by 8 elements against bank conflicts), so
+// an MFMA operand (8 consecutive voxels of one channel) is one 16-byte LDS
+// read.  The (cout/16) x (cin16/16) output tiles are spread over the four
+// wavefronts.  Partial sums per workgroup are reduced in a fixed order by a
+// second kernel, so the result is deterministic.
+
+constexpr int kWgPitch = kWgChunk + 8;
+
+__device__ __forceinline__ void stage_t(uint16_t* dst, int row0, int vv, const uint4& q) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    dst[(row0 + 2 * j) * kWgPitch + vv] = (uint16_t)(w[j] & 0xffffu);
+    dst[(row0 + 2 * j + 1) * kWgPitch + vv] = (uint16_t)(w[j] >> 16);
+  }
+}
+
+__global__ __launch_bounds__(256) void conv3_wgrad_kernel(WgradArgs a) {
+  extern __shared__ uint16_t lds[];
+  const int cin16 = (a.cin + 15) & ~15;
+  uint16_t* dyt = lds;                        // [cout][kWgPitch]
+  uint16_t* xt = lds + a.cout * kWgPitch;     // [cin16][kWgPitch]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, g = lane >> 4, r = lane & 15, wave = tid >> 6;
+  const int tap = blockIdx.y;
+  const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const long long nvox = (long long)a.n1 * a.n2 * a.n3;
+  const long long per = (nvox + gridDim.x - 1) / gridDim.x;
+  const long long v0 = (long long)blockIdx.x * per;
+  const long long v1 = v0 + per < nvox ? v0 + per : nvox;
+  const int ntl = cin16 / 16, ntiles = (a.cout / 16) * ntl;
+  const int cg = a.cout >> 3, xg = cin16 >> 3, xgv = a.cin >> 3;
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  f32x4 acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.0f;
+  for (long long c0 = v0; c0 < v1; c0 += kWgChunk) {
+    __syncthreads();
+    for (int i = tid; i < kWgChunk * cg; i += 256) {
+      const int vv = i % kWgChunk, c8 = i / kWgChunk;
+      const long long v = c0 + vv;
+      const uint4 q = v < v1 ? *reinterpret_cast<const uint4*>(a.dy + v * a.dy_stride + a.dy_off + 8 * c8)
+                             : z4;
+      stage_t(dyt, 8 * c8, vv, q);
+    }
+    for (int i = tid; i < kWgChunk * xg; i += 256) {
+      const int vv = i % kWgChunk, c8 = i / kWgChunk;
+      const long long v = c0 + vv;
+      uint4 q = z4;
+      if (v < v1 && c8 < xgv) {
+        const int x = (int)(v % a.n1) + dx;
+        const int y = (int)((v / a.n1) % a.n2) + dy;
+        const int z = (int)(v / ((long long)a.n1 * a.n2)) + dz;
+        if (x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3) {
+          const long long src = ((long long)z * a.n2 + y) * a.n1 + x;
+          q = *reinterpret_cast<const uint4*>(a.x + src * a.x_stride + a.x_off + 8 * c8);
+        }
+      }
+      stage_t(xt, 8 * c8, vv, q);
+    }
+    __syncthreads();
+    if (tap == 13 && tid < a.cout) {
+      for (int vv = 0; vv < kWgChunk; ++vv) bsum += bf2f(dyt[tid * kWgPitch + vv]);
+    }
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      const int tl = wave + 4 * sl;
+      if (tl < ntiles) {
+        const int m = tl / ntl, n = tl - m * ntl;
+#pragma unroll
+        for (int kk = 0; kk < kWgChunk / 32; ++kk) {
+          const bf16x8 af =
+              *reinterpret_cast<const bf16x8*>(dyt + (m * 16 + r) * kWgPitch + kk * 32 + 8 * g);
+          const bf16x8 bv =
+              *reinterpret_cast<const bf16x8*>(xt + (n * 16 + r) * kWgPitch + kk * 32 + 8 * g);
+          acc[sl] = mfma16(af, bv, acc[sl]);
+        }
+      }
+    }
+  }
+  // lane holds dW rows co = m*16 + 4g .. +3 of column ci = n*16 + r
+  float* part = a.part + (size_t)blockIdx.x * a.cout * 27 * a.cin;
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    const int tl = wave + 4 * sl;
+    if (tl < ntiles) {
+      const int m = tl / ntl, n = tl - m * ntl;
+      const int ci = n * 16 + r;
+      if (ci < a.cin) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int co = m * 16 + 4 * g + i;
+          part[((size_t)co * 27 + tap) * a.cin + ci] = acc[sl][i];
+        }
+      }
+    }
+  }
+  if (tap == 13 && tid < a.cout) a.part_bias[(size_t)blockIdx.x * a.cout + tid] = bsum;
+}
+
+// sum of per-workgroup partials in workgroup order (deterministic)
+__global__ void reduce_parts_kernel(const float* part, int nparts, long long len, float* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.0f;
+  for (int p = 0; p < nparts; ++p) s += part[(size_t)p * len + i];
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise pieces
+
+// dY <- dY * (Y > 0) (ReLU backward), in place on the gradient view
+__global__ void relu_bwd_kernel(uint16_t* dy, int dy_stride, int dy_off, const uint16_t* y,
+                                int y_stride, int y_off, int c, long long nvox) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * c) return;
+  const long long v = i / c;
+  const int ch = (int)(i - v * c);
+  const float yy = bf2f(y[v * y_stride + y_off + ch]);
+  if (!(yy > 0.0f)) dy[v * dy_stride + dy_off + ch] = 0;
+}
+
+// 2x average pooling; out grid (m1, m2, m3) = input / 2
+__global__ void pool_fwd_kernel(const uint16_t* in, int in_stride, int in_off, uint16_t* out,
+                                int out_stride, int out_off, int c, int m1, int m2, int m3) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nv = (long long)m1 * m2 * m3;
+  if (i >= nv * c) return;
+  const long long v = i / c;
+  const int ch = (int)(i - v * c);
+  const int x = (int)(v % m1), y = (int)((v / m1) % m2), z = (int)(v / ((long long)m1 * m2));
+  const int n1 = 2 * m1, n2 = 2 * m2;
+  float s = 0.0f;
+  for (int d = 0; d < 8; ++d) {
+    const long long src = ((long long)(2 * z + (d >> 2)) * n2 + (2 * y + ((d >> 1) & 1))) * n1 +
+                          (2 * x + (d & 1));
+    s += bf2f(in[src * in_stride + in_off + ch]);
+  }
+  out[v * out_stride + out_off + ch] = f2bf(0.125f * s);
+}
+
+// pooling backward: dIn[child] (+)= dOut[parent] / 8
+__global__ void pool_bwd_kernel(const uint16_t* dout, int dout_stride, int dout_off,
+                                uint16_t* din, int din_stride, int din_off, int c, int n1, int n2,
+                                int n3, int accumulate) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nv = (long long)n1 * n2 * n3;
+  if (i >= nv * c) return;
+  const long long v = i / c;
+  const int ch = (int)(i - v * c);
+  const int x = (int)(v % n1), y = (int)((v / n1) % n2), z = (int)(v / ((long long)n1 * n2));
+  const int m1 = n1 / 2, m2 = n2 / 2;
+  const long long p = ((long long)(z / 2) * m2 + y / 2) * m1 + x / 2;
+  float g = 0.125f * bf2f(dout[p * dout_stride + dout_off + ch]);
+  uint16_t* dst = din + v * din_stride + din_off + ch;
+  if (accumulate) g += bf2f(*dst);
+  *dst = f2bf(g);
+}
+
+// nearest 2x upsampling (output grid n = 2 m)
+__global__ void up_fwd_kernel(const uint16_t* in, int in_stride, int in_off, uint16_t* out,
+                              int out_stride, int out_off, int c, int n1, int n2, int n3) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nv = (long long)n1 * n2 * n3;
+  if (i >= nv * c) return;
+  const long long v = i / c;
+  const int ch = (int)(i - v * c);
+  const int x = (int)(v % n1), y = (int)((v / n1) % n2), z = (int)(v / ((long long)n1 * n2));
+  const int m1 = n1 / 2, m2 = n2 / 2;
+  const long long p = ((long long)(z / 2) * m2 + y / 2) * m1 + x / 2;
+  out[v * out_stride + out_off + ch] = in[p * in_stride + in_off + ch];
+}
+
+// upsampling backward: dIn[parent] = sum of the 8 children's gradients
+__global__ void up_bwd_kernel(const uint16_t* dout, int dout_stride, int dout_off, uint16_t* din,
+                              int din_stride, int din_off, int c, int m1, int m2, int m3) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nv = (long long)m1 * m2 * m3;
+  if (i >= nv * c) return;
+  const long long v = i / c;
+  const int ch = (int)(i - v * c);
+  const int x = (int)(v % m1), y = (int)((v / m1) % m2), z = (int)(v / ((long long)m1 * m2));
+  const int n1 = 2 * m1, n2 = 2 * m2;
+  float s = 0.0f;
+  for (int d = 0; d < 8; ++d) {
+    const long long src = ((long long)(2 * z + (d >> 2)) * n2 + (2 * y + ((d >> 1) & 1))) * n1 +
+                          (2 * x + (d & 1));
+    s += bf2f(dout[src * dout_stride + dout_off + ch]);
+  }
+  din[v * din_stride + din_off + ch] = f2bf(s);
+}
+
+// network input: channel 0 glass mask, 1 supercooling feature, 2 surface
+// tension feature, 3..7 zero (the first convolution takes 8 channels)
+__global__ void input_kernel(const uint8_t* glass, int glass_from_code, float f1, float f2,
+                             uint16_t* out, long long nvox) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  const uint8_t gb = glass[v];
+  const float gm = glass_from_code ? ((gb & 0x40u) ? 1.0f : 0.0f) : (gb ? 1.0f : 0.0f);
+  uint16_t* o = out + v * 8;
+  o[0] = f2bf(gm);
+  o[1] = f2bf(f1);
+  o[2] = f2bf(f2);
+  for (int c = 3; c < 8; ++c) o[c] = 0;
+}
+
+// number of water cells: per-workgroup partial counts (exact in FP32 below 2^24)
+__global__ __launch_bounds__(256) void count_water_kernel(const uint8_t* glass, int from_code,
+                                                         long long nvox, float* part) {
+  __shared__ float red[256];
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  float c = 0.0f;
+  if (v < nvox) c = (from_code ? !(glass[v] & 0x40u) : !glass[v]) ? 1.0f : 0.0f;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// head: yhat = sigmoid(b + sum_c w[c] h[v][c]) on water cells, 0 on glass.
+// With a target: squared error on water cells, the gradient wrt h of the
+// mean over water cells, and per-workgroup partial sums of the squared error
+// and of the head's weight and bias gradients (fixed-order tree sums).
+__global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
+  __shared__ float red[kHeadParts][256];
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool in = v < a.nvox;
+  float hv[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) hv[c] = 0.0f;
+  float dz = 0.0f, loss = 0.0f;
+  if (in) {
+    const bool water = a.code_glass ? !(a.glass[v] & 0x40u) : !a.glass[v];
+    float z = a.b[0];
+    const uint4* hp = reinterpret_cast<const uint4*>(a.h + v * a.h_stride + a.h_off);
+    const uint4 q0 = hp[0], q1 = hp[1];
+    const uint32_t w8[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      hv[2 * j] = bf2f((uint16_t)(w8[j] & 0xffffu));
+      hv[2 * j + 1] = bf2f((uint16_t)(w8[j] >> 16));
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) z += a.w[c] * hv[c];
+    const float sg = 1.0f / (1.0f + expf(-z));
+    const float yhat = water ? sg : 0.0f;
+    if (a.out) {
+      if (a.out_fp64) static_cast<double*>(a.out)[v] = (double)yhat;
+      else static_cast<float*>(a.out)[v] = yhat;
+    }
+    if (a.target && water) {
+      const float e = sg - a.target[v];
+      loss = e * e;
+      dz = 2.0f * e * sg * (1.0f - sg) / a.count[0];
+    }
+    if (a.target) {
+      uint32_t o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        o[j] = (uint32_t)f2bf(dz * a.w[2 * j]) | ((uint32_t)f2bf(dz * a.w[2 * j + 1]) << 16);
+      uint4* dp = reinterpret_cast<uint4*>(a.dh + v * 16);
+      dp[0] = make_uint4(o[0], o[1], o[2], o[3]);
+      dp[1] = make_uint4(o[4], o[5], o[6], o[7]);
+    }
+  }
+  if (!a.target) return;
+  red[0][threadIdx.x] = loss;
+  red[1][threadIdx.x] = dz;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) red[2 + c][threadIdx.x] = dz * hv[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int j = 0; j < kHeadParts; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < kHeadParts) a.part[(size_t)blockIdx.x * kHeadParts + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// master FP32 weights [co][27][ci] -> BF16 forward copy [co][kpad] and
+// data-gradient copy [ci][kpad_t] (taps mirrored: k' = (26 - tap) * cout + co)
+__global__ void weights_kernel(const float* wm, int cout, int cin, int kpad, int kpad_t,
+                               uint16_t* wf, uint16_t* wd) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nf = (long long)cout * kpad, nd = (long long)cin * kpad_t;
+  if (i < nf) {
+    const int co = (int)(i / kpad), k = (int)(i - (long long)co * kpad);
+    wf[i] = k < 27 * cin ? f2bf(wm[((size_t)co * 27 + k / cin) * cin + k % cin]) : (uint16_t)0;
+  } else if (wd && i < nf + nd) {
+    const long long j = i - nf;
+    const int ci = (int)(j / kpad_t), k = (int)(j - (long long)ci * kpad_t);
+    uint16_t val = 0;
+    if (k < 27 * cout) {
+      const int tapf = k / cout, co = k % cout, tap = 26 - tapf;
+      val = f2bf(wm[((size_t)co * 27 + tap) * cin + ci]);
+    }
+    wd[j] = val;
+  }
+}
+
+// Adam with bias correction (Kingma and Ba 2015) on the flat FP32 parameters
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, long long n, float lr,
+                            float b1, float b2, float eps, float bc1, float bc2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void f32_to_bf16_kernel(const float* in, uint16_t* out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f2bf(in[i]);
+}
+
+__global__ void bf16_to_f32_kernel(const uint16_t* in, float* out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = bf2f(in[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+
+static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
+  if (a.cin % 8 || a.cout % 16 || a.in_stride % 8 || a.in_off % 8 || a.out_stride % 4 ||
+      a.out_off % 4 || a.kpad % 32 || a.kpad < 27 * a.cin)
+    return hipErrorInvalidValue;
+  const long long nvox = (long long)a.n1 * a.n2 * a.n3;
+  if (nvox == 0) return hipSuccess;
+  const int mt = a.cout / 16;
+  const dim3 block(256);
+#define PFU_CONV(MT, NT)                                                          \
+  do {                                                                            \
+    const long long waves = (nvox + 16 * (NT)-1) / (16 * (NT));                   \
+    hipLaunchKernelGGL((conv3_fwd_kernel<MT, NT>), dim3(blocks_for(waves, 4)), block, 0, s, a); \
+  } while (0)
+  switch (mt) {
+    case 1: PFU_CONV(1, 4); break;
+    case 2: PFU_CONV(2, 4); break;
+    case 3: PFU_CONV(3, 2); break;
+    case 4: PFU_CONV(4, 2); break;
+    case 6: PFU_CONV(6, 2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PFU_CONV
+  return hipGetLastError();
+}
+
+int wgrad_blocks(long long nvox) {
+  long long nb = nvox / 4096;
+  if (nb < 1) nb = 1;
+  if (nb > 64) nb = 64;
+  return (int)nb;
+}
+
+hipError_t launch_conv_wgrad(const WgradArgs& a, int nblocks, float* dw, float* db,
+                             hipStream_t s) {
+  const int cin16 = (a.cin + 15) & ~15;
+  if (a.cin % 8 || a.cout % 16 || (a.cout / 16) * (cin16 / 16) > kConvMaxTiles ||
+      a.dy_stride % 8 || a.dy_off % 8 || a.x_stride % 8 || a.x_off % 8 || nblocks < 1)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)(a.cout + cin16) * kWgPitch * sizeof(uint16_t);
+  hipLaunchKernelGGL(conv3_wgrad_kernel, dim3(nblocks, 27), dim3(256), lds, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long len = 27LL * a.cout * a.cin;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, a.part,
+                     nblocks, len, dw);
+  e = hipGetLastError();
+  if (e != hipSuccess || !db) return e;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(a.cout, 256)), dim3(256), 0, s,
+                     a.part_bias, nblocks, (long long)a.cout, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_bwd(uint16_t* dy, int dys, int dyo, const uint16_t* y, int ys, int yo,
+                           int c, long long nvox, hipStream_t s) {
+  if (nvox * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks_for(nvox * c, 256)), dim3(256), 0, s, dy, dys,
+                     dyo, y, ys, yo, c, nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_fwd(const View& in, const View& out, int c, int m1, int m2, int m3,
+                           hipStream_t s) {
+  const long long n = (long long)m1 * m2 * m3 * c;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pool_fwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in.p, in.stride,
+                     in.off, out.p, out.stride, out.off, c, m1, m2, m3);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_bwd(const View& dout, const View& din, int c, int n1, int n2, int n3,
+                           int accumulate, hipStream_t s) {
+  const long long n = (long long)n1 * n2 * n3 * c;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pool_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dout.p,
+                     dout.stride, dout.off, din.p, din.stride, din.off, c, n1, n2, n3, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_up_fwd(const View& in, const View& out, int c, int n1, int n2, int n3,
+                         hipStream_t s) {
+  const long long n = (long long)n1 * n2 * n3 * c;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(up_fwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in.p, in.stride,
+                     in.off, out.p, out.stride, out.off, c, n1, n2, n3);
+  return hipGetLastError();
+}
+
+hipError_t launch_up_bwd(const View& dout, const View& din, int c, int m1, int m2, int m3,
+                         hipStream_t s) {
+  const long long n = (long long)m1 * m2 * m3 * c;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(up_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dout.p,
+                     dout.stride, dout.off, din.p, din.stride, din.off, c, m1, m2, m3);
+  return hipGetLastError();
+}
+
+hipError_t launch_input(const uint8_t* glass, int from_code, float f1, float f2, uint16_t* out,
+                        long long nvox, hipStream_t s) {
+  if (nvox == 0) return hipSuccess;
+  hipLaunchKernelGGL(input_kernel, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, glass, from_code,
+                     f1, f2, out, nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_water(const uint8_t* glass, int from_code, long long nvox, float* part,
+                              float* count, hipStream_t s) {
+  const int nb = (int)blocks_for(nvox, 256);
+  hipLaunchKernelGGL(count_water_kernel, dim3(nb), dim3(256), 0, s, glass, from_code, nvox, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce(part, nb, 1, count, s);
+}
+
+int head_blocks(long long nvox) { return (int)blocks_for(nvox, 256); }
+
+hipError_t launch_head(const HeadArgs& a, hipStream_t s) {
+  if (a.h_stride % 8 || a.h_off % 8) return hipErrorInvalidValue;
+  if (a.nvox == 0) return hipSuccess;
+  hipLaunchKernelGGL(head_kernel, dim3(head_blocks(a.nvox)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const float* wm, int cout, int cin, int kpad, int kpad_t, uint16_t* wf,
+                          uint16_t* wd, hipStream_t s) {
+  const long long n = (long long)cout * kpad + (wd ? (long long)cin * kpad_t : 0);
+  hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, wm, cout, cin, kpad,
+                     kpad_t, wf, wd);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const float* part, int nparts, long long len, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, part, nparts,
+                     len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr,
+                       float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1,
+                     b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_bf16(const float* in, uint16_t* out, long long n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16_to_f32(const uint16_t* in, float* out, long long n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_probe(const float* A, const float* B, float* C, hipStream_t s) {
+  hipLaunchKernelGGL(mfma_layout_probe, dim3(1), dim3(64), 0, s, A, B, C);
+  return hipGetLastError();
+}
+
+}  // namespace pfu
