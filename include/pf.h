@@ -345,9 +345,16 @@ int pf_unet_layer_info(int32_t layer, int32_t* out);
 
 /* Write the network's prediction for the handle's mask (PF_MODEL_AC or
  * PF_MODEL_COUPLED; dT > 0, log10_sigma_scale = log10 s) into the handle's
- * current phi (in its precision; theta, t and dt are not changed).  The
- * handle's n1, n2, n3 must satisfy the network's grid rule.  Synchronous. */
-int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale);
+ * current phi (in its precision; theta, t and dt are not changed).  With
+ * restrict_to_nucleus != 0 the current phi is read first as the nucleus: the
+ * prediction is kept only on the water cells connected through water-water
+ * faces to a water cell with phi > 1/2, and is 0 elsewhere (with no
+ * phase-field flux through glass faces, a face-connected water component
+ * without ice keeps phi = 0, since phi = 0 is a fixed point of the reaction
+ * term of the phase-field equation, Sec. 2.2).  The handle's
+ * n1, n2, n3 must satisfy the network's grid rule.  Synchronous. */
+int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale,
+                 int32_t restrict_to_nucleus);
 
 /* Building blocks (each call allocates and frees its own scratch; device
  * pointers; BF16 tensors channels-last [n][c], FP32 weights [cout][27][cin],

@@ -225,3 +225,13 @@ def conv3_cl_grads(x: np.ndarray, w: np.ndarray, dy: np.ndarray) -> Dict[str, np
     Y = conv3(X.permute(3, 0, 1, 2), W, B).permute(1, 2, 3, 0)
     Y.backward(torch.from_numpy(np.asarray(dy, np.float64)))
     return dict(dx=X.grad.numpy(), dw=Wt.grad.numpy(), db=B.grad.numpy())
+
+
+def nucleus_component(mask: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """Water cells (mask == 0) in a face-connected water component that holds
+    a water cell with phi > 1/2 (bool array of the mask's shape)."""
+    from scipy import ndimage
+    water = np.asarray(mask) == 0
+    lab, _ = ndimage.label(water, structure=ndimage.generate_binary_structure(3, 1))
+    seeds = np.unique(lab[water & (np.asarray(phi) > 0.5)])
+    return np.isin(lab, seeds[seeds > 0]) & water

@@ -105,7 +105,7 @@ SIGNATURES = [
     ("pf_unet_time_layers", C.c_int, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_double)]),
     ("pf_unet_layer_info", C.c_int, [C.c_int32, C.POINTER(C.c_int32)]),
-    ("pf_warmstart", C.c_int, [_H, _H, C.c_double, C.c_double]),
+    ("pf_warmstart", C.c_int, [_H, _H, C.c_double, C.c_double, C.c_int32]),
     ("pf_conv3_bf16", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32,
                                 C.c_int32, C.c_int32, C.c_int32, C.c_size_t]),
     ("pf_conv3_bf16_backward", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, C.c_int32,
@@ -446,9 +446,12 @@ class UNet:
         self._check(lib().pf_unet_time_layers(self.h, n1, n2, n3, int(reps), out))
         return list(out)
 
-    def warmstart(self, solver: "Solver", dT: float, log10_s: float):
-        """Write the prediction into the solver's current phi."""
-        solver._check(lib().pf_warmstart(solver.h, self.h, float(dT), float(log10_s)))
+    def warmstart(self, solver: "Solver", dT: float, log10_s: float,
+                  restrict_to_nucleus: bool = True):
+        """Write the prediction into the solver's current phi; by default only
+        on the water cells connected to the current nucleus (phi > 1/2)."""
+        solver._check(lib().pf_warmstart(solver.h, self.h, float(dT), float(log10_s),
+                                         1 if restrict_to_nucleus else 0))
 
 
 def conv3_bf16(x, w, b, relu: bool, cout: int):

@@ -397,7 +397,8 @@ extern "C" {
 
 int pf_abi_version(void) { return 1; }
 
-int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale) {
+int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale,
+                 int32_t restrict_to_nucleus) {
   if (!h) return PF_EINVAL;
   if (!net) return fail(h, PF_EINVAL, "network must be non-NULL");
   if (h->P.model != PF_MODEL_AC && h->P.model != PF_MODEL_COUPLED)
@@ -405,8 +406,8 @@ int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale
   if (!(dT > 0.0)) return fail(h, PF_EINVAL, "dT must be positive");
   std::string e;
   const int r = pfu_forward_into(net, h->code, h->P.n1, h->P.n2, h->P.n3, dT, log10_sigma_scale,
-                                 h->y[h->cur][0], h->P.precision == PF_FP64 ? 1 : 0, h->stream,
-                                 &e);
+                                 h->y[h->cur][0], h->P.precision == PF_FP64 ? 1 : 0,
+                                 restrict_to_nucleus ? 1 : 0, h->stream, &e);
   if (r != PF_OK) return fail(h, r, "warm start: " + e);
   PF_HIP(h, hipStreamSynchronize(h->stream));
   return PF_OK;

@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) z += a.w[c] * hv[c];
     const float sg = 1.0f / (1.0f + expf(-z));
-    const float yhat = water ? sg : 0.0f;
+    const float yhat = (water && !(a.keep && !a.keep[v])) ? sg : 0.0f;
     if (a.out) {
       if (a.out_fp64) static_cast<double*>(a.out)[v] = (double)yhat;
       else static_cast<float*>(a.out)[v] = yhat;
@@ -485,6 +485,42 @@ __global__ void bf16_to_f32_kernel(const uint16_t* in, float* out, long long n) 
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = bf2f(in[i]);
 }
+
+// ---------------------------------------------------------------------------
+// Water cells reachable from the nucleus.  Under the phase-field equation
+// with zero phi-flux across glass faces, a face-connected component of water
+// cells that holds no ice keeps phi = 0 for ever (no flux in, and phi = 0 is
+// a fixed point of the reaction term), so ice can only appear in the
+// components that contain the initial nucleus.
+
+__global__ void reach_seed_kernel(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
+                                  long long n) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double p = fp64 ? static_cast<const double*>(phi)[v]
+                        : (double)static_cast<const float*>(phi)[v];
+  reach[v] = (!(code[v] & 0x40u) && p > 0.5) ? 1 : 0;
+}
+
+// one in-place sweep: a water cell joins when a face neighbour across a
+// water-water face has joined (monotone, so concurrent updates are benign)
+__global__ void reach_sweep_kernel(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
+                                   int* changed) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long pl = (long long)n1 * n2;
+  if (v >= pl * n3) return;
+  const unsigned c = code[v];
+  if ((c & 0x40u) || reach[v]) return;
+  const bool hit = ((c & 1u) && reach[v - 1]) || ((c & 2u) && reach[v + 1]) ||
+                   ((c & 4u) && reach[v - n1]) || ((c & 8u) && reach[v + n1]) ||
+                   ((c & 16u) && reach[v - pl]) || ((c & 32u) && reach[v + pl]);
+  if (hit) {
+    reach[v] = 1;
+    atomicOr(changed, 1);
+  }
+}
+
+__global__ void clear_int_kernel(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------------------
 // Host launchers
@@ -643,6 +679,25 @@ hipError_t launch_f32_to_bf16(const float* in, uint16_t* out, long long n, hipSt
 hipError_t launch_bf16_to_f32(const uint16_t* in, float* out, long long n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reach_seed(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
+                             long long n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(reach_seed_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, code, phi, fp64,
+                     reach, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
+                               int sweeps, int* changed, hipStream_t s) {
+  const long long n = (long long)n1 * n2 * n3;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, s, changed);
+  for (int i = 0; i < sweeps; ++i)
+    hipLaunchKernelGGL(reach_sweep_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, code, reach,
+                       n1, n2, n3, changed);
   return hipGetLastError();
 }
 

@@ -106,6 +106,8 @@ struct pf_unet {
   float* hsum = nullptr;    // [kHeadParts] reduced head sums
   float* count = nullptr;   // number of water cells
   float* cpart = nullptr;   // count partials
+  uint8_t* reach = nullptr; // water cells connected to the nucleus
+  int* changed = nullptr;   // reachability sweep flag
   float* hostbuf = nullptr; // pinned, 32 floats
 };
 
@@ -170,6 +172,8 @@ int ensure_grid(pf_unet* n, int n1, int n2, int n3, int train) {
     n->hsum = c.take<float>(32);
     n->count = c.take<float>(1);
     n->cpart = c.take<float>(hb);
+    n->reach = c.take<uint8_t>(N);
+    n->changed = c.take<int>(1);
     if (train) {
       n->gN16a = c.take<uint16_t>(N * 16);
       n->gN16b = c.take<uint16_t>(N * 16);
@@ -298,7 +302,7 @@ float feature_scale(double log10_s) { return (float)((log10_s - 1.5) / 1.5); }
 
 // forward pass; with target != null also the backward pass into n->grad
 int run_net(pf_unet* n, const uint8_t* glass, int from_code, double dT, double log10_s,
-            void* out, int out_fp64, const float* target) {
+            void* out, int out_fp64, const float* target, const uint8_t* keep = nullptr) {
   const int N1 = n->n1, N2 = n->n2, N3 = n->n3;
   const int M1 = N1 / 2, M2 = N2 / 2, M3 = N3 / 2;
   const int Q1 = N1 / 4, Q2 = N2 / 4, Q3 = N3 / 4;
@@ -331,6 +335,7 @@ int run_net(pf_unet* n, const uint8_t* glass, int from_code, double dT, double l
   h.b = n->params + n->head_b;
   h.glass = glass;
   h.code_glass = from_code;
+  h.keep = keep;
   h.nvox = N;
   h.out = out;
   h.out_fp64 = out_fp64;
@@ -400,14 +405,40 @@ int read_loss(pf_unet* n, double* loss) {
 
 }  // namespace
 
+namespace {
+
+// reach = water cells connected through water-water faces to a water cell
+// with phi > 1/2: sweeps in batches of kSweeps until one batch changes
+// nothing (each batch ends with one flag read by the host)
+int nucleus_reach(pf_unet* n, const uint8_t* code, const void* phi, int fp64) {
+  const long long N = (long long)n->n1 * n->n2 * n->n3;
+  constexpr int kSweeps = 32;
+  PFU_HIP(n, pfu::launch_reach_seed(code, phi, fp64, n->reach, N, n->stream));
+  int* flag = reinterpret_cast<int*>(n->hostbuf + 16);
+  for (long long done = 0; done <= N; done += kSweeps) {
+    PFU_HIP(n, pfu::launch_reach_sweeps(code, n->reach, n->n1, n->n2, n->n3, kSweeps, n->changed,
+                                        n->stream));
+    PFU_HIP(n, hipMemcpyAsync(flag, n->changed, sizeof(int), hipMemcpyDeviceToHost, n->stream));
+    PFU_HIP(n, hipStreamSynchronize(n->stream));
+    if (*flag == 0) return PF_OK;
+  }
+  return ufail(n, PF_EHIP, "reachability sweeps did not converge");
+}
+
+}  // namespace
+
 // internal entry used by pf_warmstart: forward pass into a solver state
 int pfu_forward_into(pf_unet* n, const uint8_t* code, int n1, int n2, int n3, double dT,
-                     double log10_s, void* out, int out_fp64, hipStream_t s, std::string* err) {
+                     double log10_s, void* out, int out_fp64, int keep_from_phi,
+                     hipStream_t s, std::string* err) {
   hipStream_t saved = n->stream;
   n->stream = s;
   int r = check_dims(n, n1, n2, n3);
   if (r == PF_OK) r = ensure_grid(n, n1, n2, n3, n->train);
-  if (r == PF_OK) r = run_net(n, code, 1, dT, log10_s, out, out_fp64, nullptr);
+  if (r == PF_OK && keep_from_phi) r = nucleus_reach(n, code, out, out_fp64);
+  if (r == PF_OK)
+    r = run_net(n, code, 1, dT, log10_s, out, out_fp64, nullptr,
+                keep_from_phi ? n->reach : nullptr);
   n->stream = saved;
   if (r != PF_OK && err) *err = n->err;
   return r;

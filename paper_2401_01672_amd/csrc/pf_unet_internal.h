@@ -41,6 +41,7 @@ struct HeadArgs {
   const float* b;      // [1]
   const uint8_t* glass;
   int code_glass;      // 1: glass flag is bit 6 of a solver cell code; 0: mask byte != 0
+  const uint8_t* keep; // if non-null: the prediction is 0 where keep[v] == 0
   long long nvox;
   void* out;           // prediction (water cells; 0 on glass) or null
   int out_fp64;
@@ -82,6 +83,10 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n
 hipError_t launch_f32_to_bf16(const float* in, uint16_t* out, long long n, hipStream_t s);
 hipError_t launch_bf16_to_f32(const uint16_t* in, float* out, long long n, hipStream_t s);
 hipError_t launch_mfma_probe(const float* A, const float* B, float* C, hipStream_t s);
+hipError_t launch_reach_seed(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
+                             long long n, hipStream_t s);
+hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
+                               int sweeps, int* changed, hipStream_t s);
 
 }  // namespace pfu
 
@@ -91,5 +96,9 @@ hipError_t launch_mfma_probe(const float* A, const float* B, float* C, hipStream
 
 // forward pass of the network on a solver's cell codes (glass = bit 6),
 // writing phi0 (FP32 or FP64) into out on stream s; used by pf_warmstart
+// If keep_from_phi: before out is written, the water cells connected through
+// water-water faces to a cell with out > 1/2 (the current nucleus) are found,
+// and the prediction is zero on every other cell.
 int pfu_forward_into(pf_unet* n, const uint8_t* code, int n1, int n2, int n3, double dT,
-                     double log10_s, void* out, int out_fp64, hipStream_t s, std::string* err);
+                     double log10_s, void* out, int out_fp64, int keep_from_phi,
+                     hipStream_t s, std::string* err);

@@ -195,9 +195,38 @@ def test_warmstart_writes_prediction(precision):
     net = pf.UNet(seed=8)
     dT, ls = c.params["dT"], 0.0
     pred = net.forward(_dev(c.mask, torch.uint8), dT, ls).cpu().numpy()
-    net.warmstart(s, dT, ls)
+    net.warmstart(s, dT, ls, restrict_to_nucleus=False)
     phi, _ = s.get_state()
     assert np.array_equal(phi.reshape(pred.shape), pred.astype(phi.dtype))
+    # restricted to the water component(s) of the nucleus
+    s.set_state(c.phi0.astype(phi.dtype))
+    net.warmstart(s, dT, ls)
+    phi2, _ = s.get_state()
+    keep = U.nucleus_component(c.mask, c.phi0)
+    assert np.array_equal(phi2[keep], pred[keep].astype(phi.dtype))
+    assert np.all(phi2[~keep] == 0)
+    s.close()
+
+
+@pytest.mark.parametrize("seed", [20000, 20001])
+def test_nucleus_component_on_bead_packs(seed):
+    """Reachable water on a generated bead pack with sealed pockets, and on a
+    grid where a glass wall cuts the box in two."""
+    c = pi.warmstart_instance(seed, edge=48)
+    mask = c.mask.copy()
+    cx = c.meta["nucleus_centre"] % 48
+    mask[:, :, (cx + 24) % 48] = 1  # a glass wall half a box away from the nucleus
+    mask[:, :, (cx + 25) % 48] = 1
+    s = pf.Solver(dict(c.params), mask, "fp32", c.run)
+    phi0 = c.phi0.astype(np.float32)
+    phi0[mask == 1] = 0
+    s.set_state(phi0)
+    net = pf.UNet(seed=2)
+    net.warmstart(s, c.meta["dT"], 1.0)
+    phi, _ = s.get_state()
+    keep = U.nucleus_component(mask, phi0)
+    assert keep.sum() > 0 and (~keep & (mask == 0)).sum() > 0
+    assert np.all(phi[~keep] == 0) and np.all(phi[keep] > 0)
     s.close()
 
 
