@@ -7,8 +7,9 @@ conductance matrix), and the Runge-Kutta-Merson step is written as a Butcher
 tableau.  Only meant for grids of a few hundred cells.
 
 Model: Sec. 2.1-2.2 of the paper (blending, heat equation, Allen-Cahn with
-the SigmaP1-P reaction, water indicator, boundary conditions), Sec. 2.4
-(micro-scale reduction) and Sec. 2.5 (method of lines, Merson integrator).
+the SigmaP1-P or GradP reaction, water indicator, boundary conditions),
+Sec. 2.3 (Temp model), Sec. 2.4 (micro-scale reduction) and Sec. 2.5
+(method of lines, Merson integrator).
 """
 from __future__ import annotations
 
@@ -84,22 +85,79 @@ def dirichlet_T(p, t):
     return p["bc_T0"]
 
 
+def gradient_norm(G, phi, h, face_mask=True):
+    """|grad phi| per cell: for each axis the difference quotient over the
+    open faces (both open: central, one open: one-sided, none: 0).  A face is
+    open when the neighbour exists and (face_mask) both cells are water."""
+    G = np.asarray(G, np.float64)
+    ph = np.asarray(phi, np.float64)
+    g2 = np.zeros(G.shape)
+    for ax in (2, 1, 0):  # x1, x2, x3 in array order (n3, n2, n1)
+        n = G.shape[ax]
+        for i in range(n):
+            sl = [slice(None)] * 3
+            sl[ax] = i
+            sl = tuple(sl)
+            if i > 0:
+                lo = [slice(None)] * 3
+                lo[ax] = i - 1
+                lo = tuple(lo)
+                om = (G[sl] < 0.5) & (G[lo] < 0.5) if face_mask else np.ones(G[sl].shape, bool)
+                phm = np.where(om, ph[lo], ph[sl])
+            else:
+                om = np.zeros(G[sl].shape, bool)
+                phm = ph[sl]
+            if i < n - 1:
+                hi = [slice(None)] * 3
+                hi[ax] = i + 1
+                hi = tuple(hi)
+                oq = (G[sl] < 0.5) & (G[hi] < 0.5) if face_mask else np.ones(G[sl].shape, bool)
+                phq = np.where(oq, ph[hi], ph[sl])
+            else:
+                oq = np.zeros(G[sl].shape, bool)
+                phq = ph[sl]
+            width = np.where(om & oq, 2.0 * h, h)
+            g2[sl] += ((phq - phm) / width) ** 2
+    return np.sqrt(g2)
+
+
+def temp_phase(p, G, T):
+    """Temp model: phi = I_W(G) (1 - tanh(gamma (T - T*)))/2 and its
+    derivative in T."""
+    IW = np.maximum(0.0, 1 - p["zeta"] * np.asarray(G, np.float64))
+    th = np.tanh(p.get("gamma", 2.0) * (np.asarray(T, np.float64) - p["t_star"]))
+    return 0.5 * IW * (1 - th), -0.5 * IW * p.get("gamma", 2.0) * (1 - th * th)
+
+
 def rhs(p, G, t, phi, T=None):
-    """(kphi, kT) of the micro-scale ("ac") or coupled model, dense form."""
+    """(kphi, kT) of the micro-scale ("ac"), coupled or Temp model, dense form.
+    Temp model: phi is ignored and kphi = varphi'(T) kT."""
     shape = np.shape(G)
     Gf = np.asarray(G, np.float64).ravel()
-    ph = np.asarray(phi, np.float64).ravel()
-    coupled = p["model"] == "coupled"
-    Tc = np.asarray(T, np.float64).ravel() if coupled else np.full(Gf.size, p["t_star"] - p["dT"])
+    model = p["model"]
+    coupled = model == "coupled"
+    if model == "temp":
+        Tc = np.asarray(T, np.float64).ravel()
+        ph, dph = temp_phase(p, Gf, Tc)
+    else:
+        ph = np.asarray(phi, np.float64).ravel()
+        Tc = np.asarray(T, np.float64).ravel() if coupled else \
+            np.full(Gf.size, p["t_star"] - p["dT"])
     xi, al = p["xi"], p["alpha"]
-    Lphi = phase_laplacian(np.reshape(Gf, shape), p["h"], bool(p.get("phi_face_mask", 1))) @ ph
-    drive = 0.5 * xi * p["b"] * p["mu"] * al * smoothstep(ph, p["eps0"], p["eps1"]) \
-        * smoothstep(1 - ph, p["eps0"], p["eps1"]) * (p["t_star"] - Tc)
-    f = 2 * ph * (1 - ph) * (ph - 0.5 + drive)
-    IW = np.maximum(0.0, 1 - p["zeta"] * Gf)
-    kphi = IW * (Lphi + f / (xi * xi)) / al
-    if not coupled:
-        return kphi.reshape(shape), None
+    if model != "temp":
+        fm = bool(p.get("phi_face_mask", 1))
+        Lphi = phase_laplacian(np.reshape(Gf, shape), p["h"], fm) @ ph
+        if p.get("reaction", "sigma") == "gradp":
+            gn = gradient_norm(np.reshape(Gf, shape), np.reshape(ph, shape), p["h"], fm).ravel()
+            f = 2 * ph * (1 - ph) * (ph - 0.5) + xi * xi * p["mu"] * al * gn * (p["t_star"] - Tc)
+        else:
+            drive = 0.5 * xi * p["b"] * p["mu"] * al * smoothstep(ph, p["eps0"], p["eps1"]) \
+                * smoothstep(1 - ph, p["eps0"], p["eps1"]) * (p["t_star"] - Tc)
+            f = 2 * ph * (1 - ph) * (ph - 0.5 + drive)
+        IW = np.maximum(0.0, 1 - p["zeta"] * Gf)
+        kphi = IW * (Lphi + f / (xi * xi)) / al
+        if not coupled:
+            return kphi.reshape(shape), None
     lam = blend(Gf, ph, p["lam"])
     n = Gf.size
     pairs, bnd = _faces(shape)
@@ -115,6 +173,9 @@ def rhs(p, G, t, phi, T=None):
             A[c, c] -= 2 * lam[c]
             src[c] += 2 * lam[c] * TD
     divq = (A @ Tc + src) / (p["h"] ** 2)
+    if model == "temp":
+        kT = divq / (blend(Gf, ph, p["rhoc"]) - p["Lv"] * dph)
+        return (dph * kT).reshape(shape), kT.reshape(shape)
     kT = (divq + p["Lv"] * kphi) / blend(Gf, ph, p["rhoc"])
     return kphi.reshape(shape), kT.reshape(shape)
 

@@ -323,7 +323,9 @@ int or_rkm_step(const or_params* p, const double* G, const or_ctl* c, double t_e
       if (G[i] < 0.5 && fabs(k[0][i]) > maxk1) maxk1 = fabs(k[0][i]);
   }
   info->maxk1 = maxk1;
-  if (eq_tol > 0.0 && maxk1 < eq_tol) {
+  /* the equilibrium test measures the phase-field equation, which the Temp
+   * model does not have */
+  if (eq_tol > 0.0 && p->model != OR_MODEL_TEMP && maxk1 < eq_tol) {
     info->status = OR_EQUILIBRIUM;
     info->dt_used = 0.0;
     info->dt_next = *dt;

@@ -218,9 +218,11 @@ class Solver:
     # -- state ----------------------------------------------------------------
     def set_state(self, phi, theta=None):
         """phi, theta (= T - T*): torch tensors (cuda) or numpy arrays in the
-        handle's precision, ncells elements each."""
-        if isinstance(phi, np.ndarray):
-            phi = np.ascontiguousarray(phi, dtype=self.np_dtype)
+        handle's precision, ncells elements each (Temp model: theta only,
+        phi may be None)."""
+        if isinstance(phi, np.ndarray) or isinstance(theta, np.ndarray):
+            if phi is not None:
+                phi = np.ascontiguousarray(phi, dtype=self.np_dtype)
             if theta is not None:
                 theta = np.ascontiguousarray(theta, dtype=self.np_dtype)
         pp, dev = _ptr(phi)
@@ -228,15 +230,19 @@ class Solver:
         self._check(lib().pf_set_state(self.h, pp, tp, dev))
 
     def get_state(self, device: bool = False):
+        """(phi, theta); theta is None for the micro-scale model, phi is None
+        for the Temp model."""
+        has_phi = self.model != "temp"
+        has_th = self.model != "ac"
         if device:
             import torch
-            phi = torch.empty(self.shape, dtype=self.torch_dtype(), device="cuda")
-            th = torch.empty(self.shape, dtype=self.torch_dtype(), device="cuda") \
-                if self.model == "coupled" else None
+            mk = (lambda: torch.empty(self.shape, dtype=self.torch_dtype(), device="cuda"))
+            phi = mk() if has_phi else None
+            th = mk() if has_th else None
             torch.cuda.current_stream().synchronize()
         else:
-            phi = np.empty(self.shape, dtype=self.np_dtype)
-            th = np.empty(self.shape, dtype=self.np_dtype) if self.model == "coupled" else None
+            phi = np.empty(self.shape, dtype=self.np_dtype) if has_phi else None
+            th = np.empty(self.shape, dtype=self.np_dtype) if has_th else None
         self._check(lib().pf_get_state(self.h, _ptr(phi)[0], _ptr(th)[0], 1 if device else 0))
         return phi, th
 

@@ -28,7 +28,7 @@ struct pf_handle {
   ModelConst mc;
   long long ncell = 0;
   size_t esize = 0;
-  int nvar = 0;  // 1: phi (AC); 2: phi, theta (coupled)
+  int nvar = 0;  // 1: phi (AC) or theta (Temp); 2: phi, theta (coupled)
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   void* slab = nullptr;
@@ -106,6 +106,15 @@ void fill_model_const(const pf_params& P, ModelConst& m) {
   m.h3 = P.h * P.h * P.h;
   m.gamma = P.gamma;
   m.dT = P.dT;
+  m.reaction = P.reaction;
+  m.gpc = P.xi * P.xi * P.mu * P.alpha;
+  m.inv_h = 1.0 / P.h;
+}
+
+// the four-cell, paired and batched kernels implement the SigmaP1-P phase
+// equation of the AC and coupled models only
+bool simple_kernels_only(const pf_params& P) {
+  return P.model == PF_MODEL_TEMP || P.reaction != PF_REACT_SIGMA;
 }
 
 int validate(const pf_params* P, const uint8_t* mask) {
@@ -115,16 +124,18 @@ int validate(const pf_params* P, const uint8_t* mask) {
   const long long nc = (long long)P->n1 * P->n2 * P->n3;
   if (nc >= (1LL << 31) - 2LL * P->n1 * P->n2)
     return fail(nullptr, PF_EINVAL, "grid too large (cell index must fit in int32)");
-  if (P->model != PF_MODEL_AC && P->model != PF_MODEL_COUPLED)
-    return fail(nullptr, PF_EINVAL, "model must be PF_MODEL_AC or PF_MODEL_COUPLED");
+  if (P->model != PF_MODEL_AC && P->model != PF_MODEL_COUPLED && P->model != PF_MODEL_TEMP)
+    return fail(nullptr, PF_EINVAL, "model must be PF_MODEL_AC, PF_MODEL_COUPLED or PF_MODEL_TEMP");
   if (P->precision != PF_FP64 && P->precision != PF_FP32)
     return fail(nullptr, PF_EINVAL, "precision must be PF_FP64 or PF_FP32");
-  if (P->reaction != PF_REACT_SIGMA)
-    return fail(nullptr, PF_EINVAL, "reaction must be PF_REACT_SIGMA");
+  if (P->reaction != PF_REACT_SIGMA && P->reaction != PF_REACT_GRADP)
+    return fail(nullptr, PF_EINVAL, "reaction must be PF_REACT_SIGMA or PF_REACT_GRADP");
+  if (P->model == PF_MODEL_TEMP && P->reaction != PF_REACT_SIGMA)
+    return fail(nullptr, PF_EINVAL, "the Temp model has no reaction term (use PF_REACT_SIGMA)");
   if (!(P->h > 0) || !(P->xi > 0) || !(P->alpha > 0))
     return fail(nullptr, PF_EINVAL, "h, xi and alpha must be positive");
   if (!(P->eps1 != P->eps0)) return fail(nullptr, PF_EINVAL, "eps1 must differ from eps0");
-  if (P->model == PF_MODEL_COUPLED) {
+  if (P->model != PF_MODEL_AC) {
     for (int i = 0; i < 3; ++i)
       if (!(P->rhoc[i] > 0)) return fail(nullptr, PF_EINVAL, "rhoc must be positive");
   }
@@ -430,7 +441,7 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
   h->ncell = (long long)params->n1 * params->n2 * params->n3;
   h->esize = params->precision == PF_FP64 ? 8 : 4;
   h->nvar = params->model == PF_MODEL_COUPLED ? 2 : 1;
-  h->vec = params->n1 % 4 == 0 ? 1 : 0;
+  h->vec = (params->n1 % 4 == 0 && !simple_kernels_only(*params)) ? 1 : 0;
   h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
 
   auto bail = [&](int code, const std::string& msg) {
@@ -534,6 +545,10 @@ int pf_set_time(pf_handle* h, double t, double dt) {
 
 int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device) {
   if (!h) return PF_EINVAL;
+  if (h->P.model == PF_MODEL_TEMP) {  // the single unknown theta lives in slot 0
+    if (!theta) return fail(h, PF_EINVAL, "theta must be non-NULL for the Temp model");
+    phi = theta;
+  }
   if (!phi) return fail(h, PF_EINVAL, "phi must be non-NULL");
   if (h->nvar == 2 && !theta) return fail(h, PF_EINVAL, "theta must be non-NULL for the coupled model");
   const size_t bytes = (size_t)h->ncell * h->esize;
@@ -549,6 +564,10 @@ int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device) {
   if (!h) return PF_EINVAL;
   const size_t bytes = (size_t)h->ncell * h->esize;
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (h->P.model == PF_MODEL_TEMP) {
+    phi = theta;
+    theta = nullptr;
+  }
   if (phi) PF_HIP(h, hipMemcpyAsync(phi, h->y[h->cur][0], bytes, k, h->stream));
   if (theta && h->nvar == 2) PF_HIP(h, hipMemcpyAsync(theta, h->y[h->cur][1], bytes, k, h->stream));
   PF_HIP(h, hipStreamSynchronize(h->stream));
@@ -558,6 +577,22 @@ int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device) {
 int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dphi,
            void* dtheta) {
   if (!h) return PF_EINVAL;
+  if (h->P.model == PF_MODEL_TEMP) {
+    // unknown theta in slot 0; the optional second output is d phi/dt
+    if (!theta || !dtheta)
+      return fail(h, PF_EINVAL, "theta and dtheta must be non-NULL for the Temp model");
+    StageArgs a = stage_args(h, 0);
+    a.ignore_done = 1;
+    a.t_fixed = t;
+    a.vec = 0;
+    pf::grid_blocks(h->mc, h->z_chunk, 0, &a.tiles_p, &a.tiles_z);
+    a.in[0] = theta;
+    a.in[1] = nullptr;
+    a.out[0] = dtheta;
+    a.out[1] = dphi;
+    PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, h->stream));
+    return PF_OK;
+  }
   if (!phi || !dphi) return fail(h, PF_EINVAL, "phi and dphi must be non-NULL");
   if (h->nvar == 2 && (!theta || !dtheta))
     return fail(h, PF_EINVAL, "theta and dtheta must be non-NULL for the coupled model");
@@ -583,6 +618,8 @@ int pf_set_vector(pf_handle* h, int32_t enable) {
   if (!h) return PF_EINVAL;
   if (enable && h->P.n1 % 4 != 0)
     return fail(h, PF_EINVAL, "four-cell kernels need n1 divisible by 4");
+  if (enable && simple_kernels_only(h->P))
+    return fail(h, PF_EINVAL, "four-cell kernels implement the SigmaP1-P AC and coupled models only");
   h->vec = enable ? 1 : 0;
   return set_tiles(h, h->z_chunk);
 }
@@ -660,7 +697,9 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
     if (rc) return rc;
   }
   DevCtl& c = *h->hctl;
-  init_ctl(h, c, t_end, max_steps, eq_tol);
+  // the equilibrium test measures the phase-field equation, which the Temp
+  // model does not have
+  init_ctl(h, c, t_end, max_steps, h->P.model == PF_MODEL_TEMP ? 0.0 : eq_tol);
   if (h->t >= t_end) {
     c.done = 1;
     c.status = PF_OK;
@@ -775,6 +814,8 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
     if (inst[i]->P.precision != inst[0]->P.precision || inst[i]->P.model != inst[0]->P.model)
       return fail(nullptr, PF_EINVAL, "batch: all instances need the same model and precision");
+    if (simple_kernels_only(inst[i]->P))
+      return fail(nullptr, PF_EINVAL, "batch: the SigmaP1-P AC and coupled models only");
     if (inst[i]->P.n1 % 4 != 0)
       return fail(nullptr, PF_EINVAL, "batch: every instance needs n1 divisible by 4");
   }
@@ -922,6 +963,8 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
 
 int pf_set_schedule(pf_handle* h, int32_t schedule) {
   if (!h || (schedule != pf::kSchedFive && schedule != pf::kSchedPaired)) return PF_EINVAL;
+  if (schedule == pf::kSchedPaired && simple_kernels_only(h->P))
+    return fail(h, PF_EINVAL, "the paired schedule implements the SigmaP1-P AC and coupled models only");
   h->sched = schedule;
   h->autotune_pending = 1;
   drop_graph(h);

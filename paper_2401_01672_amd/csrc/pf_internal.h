@@ -62,6 +62,10 @@ struct ModelConst {
   double h3;        // h^3 for the enthalpy
   double gamma;     // Temp model
   double dT;        // supercooling of the micro-scale model (theta = -dT)
+  int reaction;     // PF_REACT_SIGMA or PF_REACT_GRADP
+  int pad_r;
+  double gpc;       // GradP drive coefficient xi^2 mu alpha
+  double inv_h;     // 1/h (GradP gradient)
 };
 
 struct Buffers {

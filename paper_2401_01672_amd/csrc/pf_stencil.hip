@@ -135,7 +135,26 @@ __device__ __forceinline__ float div_fast(float a, float b) {
 }
 __device__ __forceinline__ double div_fast(double a, double b) { return a / b; }  // IEEE
 
-template <typename R, int MODEL>
+// |grad phi| at the cell centre (GradP): central differences, one-sided where
+// a face is closed to the phase field, zero along an axis with both faces
+// closed (the zero-flux condition makes the normal derivative vanish there).
+template <typename R>
+__device__ __forceinline__ R grad_norm(const ModelConst& m, R phic, const R (&phn)[6],
+                                       unsigned code) {
+  R g2 = R(0);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const bool om = (code >> (2 * ax)) & 1u, oq = (code >> (2 * ax + 1)) & 1u;
+    const R q = oq ? phn[2 * ax + 1] : phic;
+    const R mm = om ? phn[2 * ax] : phic;
+    const R w = (om && oq) ? R(0.5 * m.inv_h) : R(m.inv_h);
+    const R d = (q - mm) * w;
+    g2 += d * d;
+  }
+  return sqrt(g2);
+}
+
+template <typename R, int MODEL, int REACT = PF_REACT_SIGMA>
 struct CellRHS {
   // phn/thn: neighbour values through faces 0..5.  Precondition: for a face
   // on the domain boundary thn[f] == thc (the caller passes the cell's own
@@ -151,10 +170,18 @@ struct CellRHS {
     R lap = R(0);
 #pragma unroll
     for (int f = 0; f < 6; ++f) lap += keep_if_bit(code, f, phn[f] - phic);
-    const R sa = limiter_fast(phic, R(m.inv_de), R(m.e0 * m.inv_de));
-    const R sb = limiter_fast(R(1) - phic, R(m.inv_de), R(m.e0 * m.inv_de));
-    const R drive = (MODEL == PF_MODEL_AC) ? R(m.betaAC) : R(m.beta0) * (-thc);
-    const R f = R(2) * phic * (R(1) - phic) * (phic - R(0.5) + drive * sa * sb);
+    R f;
+    if (REACT == PF_REACT_GRADP) {
+      // eq. reaction-term-GradP: 2 phi (1 - phi)(phi - 1/2) + xi^2 mu alpha |grad phi| (T* - T)
+      const R gn = glass ? R(0) : grad_norm(m, phic, phn, code);
+      const R under = (MODEL == PF_MODEL_AC) ? R(m.dT) : -thc;
+      f = R(2) * phic * (R(1) - phic) * (phic - R(0.5)) + R(m.gpc) * gn * under;
+    } else {
+      const R sa = limiter_fast(phic, R(m.inv_de), R(m.e0 * m.inv_de));
+      const R sb = limiter_fast(R(1) - phic, R(m.inv_de), R(m.e0 * m.inv_de));
+      const R drive = (MODEL == PF_MODEL_AC) ? R(m.betaAC) : R(m.beta0) * (-thc);
+      f = R(2) * phic * (R(1) - phic) * (phic - R(0.5) + drive * sa * sb);
+    }
     // glass: no phase-field flux and the water indicator of glass
     kphi = glass ? R(m.iw_glass) * (R(m.cR) * f) : R(m.cL) * lap + R(m.cR) * f;
     if (MODEL == PF_MODEL_COUPLED) {
@@ -175,10 +202,49 @@ struct CellRHS {
   }
 };
 
+// Temp model (Sec. 2.3): the unknown is theta alone and the phase field
+// follows it, phi = varphi(T) = I_W(G) (1 - tanh(gamma (T - T*)))/2
+// (eq. explicit-p-dependence-on-T); the heat equation becomes
+// rho [c - L varphi'(T)] dT/dt = div(lambda grad T) (eq.
+// combined-heat-xfer-phase-transition).  The caller passes the theta
+// neighbours in thn (boundary faces: the cell's own value); kth receives
+// d theta/dt and kphi = varphi'(T) d theta/dt.
+template <typename R>
+__device__ __forceinline__ R temp_phi(const ModelConst& m, R th, R iw) {
+  return R(0.5) * iw * (R(1) - tanh(R(m.gamma) * th));
+}
+
+template <typename R, int REACT>
+struct CellRHS<R, PF_MODEL_TEMP, REACT> {
+  __device__ __forceinline__ static void eval(const ModelConst& m, R thc, R /*unused*/,
+                                              const R (&thn)[6], const R (&/*unused*/)[6],
+                                              unsigned code, unsigned inb, unsigned dirf,
+                                              R thD, R& kth, R& kphi) {
+    const bool glass = code & kGlassBit;
+    const R iw = glass ? R(m.iw_glass) : R(1);
+    const R tc = tanh(R(m.gamma) * thc);
+    const R phic = R(0.5) * iw * (R(1) - tc);
+    const R lamc = glass ? R(m.lamG) : R(m.lamL) + phic * R(m.dlam);
+    R qq = R(0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const R lamn =
+          ((code >> f) & 1u) ? R(m.lamL) + temp_phi(m, thn[f], R(1)) * R(m.dlam) : R(m.lamG);
+      qq += (lamc + lamn) * (thn[f] - thc);
+    }
+    const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
+    if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
+    const R rc = glass ? R(m.rcG) : R(m.rcL) + phic * R(m.drc);
+    const R dphi = R(-0.5) * iw * R(m.gamma) * (R(1) - tc * tc);
+    kth = (R(0.5) * R(m.cH) * qq) / (rc - R(m.Lv) * dphi);
+    kphi = dphi * kth;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Stage kernel.  STAGE 0 = standalone RHS (in -> out as k).
 
-template <typename R, int MODEL, int STAGE>
+template <typename R, int MODEL, int STAGE, int REACT = PF_REACT_SIGMA>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
   const ModelConst& m = a.mc;
@@ -276,11 +342,13 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
         for (int f = 0; f < 6; ++f) thn[f] = R(0);
       }
       R kp, kt;
-      CellRHS<R, MODEL>::eval(m, pc, tc, phn, thn, code, inb, dirf, thD, kp, kt);
+      // Temp model: the single unknown (theta) travels in the first slot;
+      // kp = d theta/dt, kt = d phi/dt
+      CellRHS<R, MODEL, REACT>::eval(m, pc, tc, phn, thn, code, inb, dirf, thD, kp, kt);
 
       if (STAGE == 0) {
         oP[n] = kp;
-        if (kCoupled) oT[n] = kt;
+        if (kCoupled || (MODEL == PF_MODEL_TEMP && oT)) oT[n] = kt;
       } else if (STAGE == 1) {
         k1P[n] = kp;
         oP[n] = pc + rdt * (R(1.0 / 3.0) * kp);
@@ -289,11 +357,16 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
           oT[n] = tc + rdt * (R(1.0 / 3.0) * kt);
         }
         const bool water = !(code & kGlassBit);
-        const double dpc = (double)pc;
-        const double thc_d = kCoupled ? (double)tc : -m.dT;
+        double dpc = (double)pc;
+        double thc_d = kCoupled ? (double)tc : -m.dT;
+        if (MODEL == PF_MODEL_TEMP) {
+          thc_d = (double)pc;
+          dpc = (double)temp_phi(m, pc, water ? R(1) : R(m.iw_glass));
+        }
         const double rc = (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
         if (water) {
-          red0 = dmax_nf(red0, fabs((double)kp));
+          // no phase-field equation in the Temp model: no equilibrium measure
+          if (MODEL != PF_MODEL_TEMP) red0 = dmax_nf(red0, fabs((double)kp));
           red1 += dpc;
           red3 += (dpc > 0.5) ? 1.0 : 0.0;
         }
@@ -650,8 +723,13 @@ __global__ __launch_bounds__(kBlock) void diag_kernel(const uint8_t* code, const
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (long long)gridDim.x * kBlock) {
     const bool glass = code[i] & kGlassBit;
-    const double ph = (double)phi[i];
-    const double thc = MODEL == PF_MODEL_COUPLED ? (double)th[i] : -m.dT;
+    // Temp model: the state is theta alone (passed as phi), phi = varphi(T)
+    const double ph = MODEL == PF_MODEL_TEMP
+                          ? (double)temp_phi(m, phi[i], glass ? R(m.iw_glass) : R(1))
+                          : (double)phi[i];
+    const double thc = MODEL == PF_MODEL_COUPLED ? (double)th[i]
+                       : MODEL == PF_MODEL_TEMP  ? (double)phi[i]
+                                                 : -m.dT;
     const double rc = glass ? m.rcG : m.rcL + ph * m.drc;
     if (!glass) {
       v[0] += 1.0;
@@ -1276,9 +1354,29 @@ hipError_t launch_build_code(const uint8_t* mask, uint8_t* code, int n1, int n2,
   return hipGetLastError();
 }
 
+template <typename R, int MODEL, int REACT>
+static hipError_t launch_scalar_t(int stage, const StageArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
+  switch (stage) {
+    case 0: hipLaunchKernelGGL((stage_kernel<R, MODEL, 0, REACT>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((stage_kernel<R, MODEL, 1, REACT>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stage_kernel<R, MODEL, 2, REACT>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stage_kernel<R, MODEL, 3, REACT>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((stage_kernel<R, MODEL, 4, REACT>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((stage_kernel<R, MODEL, 5, REACT>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename R, int MODEL>
 static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
+  // GradP reaction: one-cell-per-thread kernels only
+  if (a.mc.reaction == PF_REACT_GRADP) {
+    if (a.vec) return hipErrorInvalidValue;
+    return launch_scalar_t<R, MODEL, PF_REACT_GRADP>(stage, a, s);
+  }
   if (a.vec) {
     switch (stage) {
       case 0: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 0>), grid, block, 0, s, a); break;
@@ -1344,12 +1442,18 @@ hipError_t launch_pair(int precision, int model, int first, int ts, const PairAr
 }
 
 hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a, hipStream_t s) {
+  if (model == PF_MODEL_TEMP && (a.vec || a.mc.reaction != PF_REACT_SIGMA))
+    return hipErrorInvalidValue;
   if (precision == PF_FP64) {
     if (model == PF_MODEL_AC) return launch_stage_t<double, PF_MODEL_AC>(stage, a, s);
     if (model == PF_MODEL_COUPLED) return launch_stage_t<double, PF_MODEL_COUPLED>(stage, a, s);
+    if (model == PF_MODEL_TEMP)
+      return launch_scalar_t<double, PF_MODEL_TEMP, PF_REACT_SIGMA>(stage, a, s);
   } else {
     if (model == PF_MODEL_AC) return launch_stage_t<float, PF_MODEL_AC>(stage, a, s);
     if (model == PF_MODEL_COUPLED) return launch_stage_t<float, PF_MODEL_COUPLED>(stage, a, s);
+    if (model == PF_MODEL_TEMP)
+      return launch_scalar_t<float, PF_MODEL_TEMP, PF_REACT_SIGMA>(stage, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1369,12 +1473,18 @@ hipError_t launch_diag(int precision, int model, const uint8_t* code, const void
     if (model == PF_MODEL_COUPLED)
       hipLaunchKernelGGL((diag_kernel<double, PF_MODEL_COUPLED>), grid, block, 0, s, code,
                          (const double*)phi, (const double*)th, m, n, part);
+    else if (model == PF_MODEL_TEMP)
+      hipLaunchKernelGGL((diag_kernel<double, PF_MODEL_TEMP>), grid, block, 0, s, code,
+                         (const double*)phi, (const double*)th, m, n, part);
     else
       hipLaunchKernelGGL((diag_kernel<double, PF_MODEL_AC>), grid, block, 0, s, code,
                          (const double*)phi, (const double*)th, m, n, part);
   } else {
     if (model == PF_MODEL_COUPLED)
       hipLaunchKernelGGL((diag_kernel<float, PF_MODEL_COUPLED>), grid, block, 0, s, code,
+                         (const float*)phi, (const float*)th, m, n, part);
+    else if (model == PF_MODEL_TEMP)
+      hipLaunchKernelGGL((diag_kernel<float, PF_MODEL_TEMP>), grid, block, 0, s, code,
                          (const float*)phi, (const float*)th, m, n, part);
     else
       hipLaunchKernelGGL((diag_kernel<float, PF_MODEL_AC>), grid, block, 0, s, code,

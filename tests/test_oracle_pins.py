@@ -439,3 +439,69 @@ def test_gibbs_thomson_critical_radius():
     for v, R in ((v_small, Rs), (v_big, Rb)):
         theory = mu * dT - 2 / (alpha * R)
         assert abs(v - theory) <= 0.3 * abs(theory) + 0.1 * mu * dT, (v, theory, R)
+
+
+@pytest.mark.parametrize("model,reaction", [("ac", "gradp"), ("coupled", "gradp"),
+                                            ("temp", "sigma")])
+@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 3, 5), (1, 2, 6)])
+def test_rhs_variants_match_brute_force(model, reaction, shape):
+    """GradP reaction (eq. reaction-term-GradP) and the Temp model (Sec. 2.3)
+    against the dense transcription."""
+    rng = np.random.default_rng(hash((model, reaction, shape)) % 2**32)
+    for trial in range(3):
+        p = _tiny_params(model, shape, rng, faces=int(rng.integers(0, 64)),
+                         bc_kind=int(rng.integers(0, 3)))
+        p["reaction"] = reaction
+        p["gamma"] = 1.5
+        G = (rng.random(shape) < 0.3).astype(float)
+        phi = rng.random(shape)
+        phi[G == 1] = 0.0
+        T = 273.15 + rng.normal(0, 1.5, shape)
+        P = oracle.make_params(p)
+        t = float(rng.random() * 3)
+        if model == "temp":
+            kp, kT = oracle.rhs(P, G, t, None, T)
+        else:
+            kp, kT = oracle.rhs(P, G, t, phi, T if model == "coupled" else None)
+        bp, bT = brute.rhs(p, G, t, phi, T)
+        assert np.abs(kp - bp).max() <= 1e-13 * max(np.abs(bp).max(), 1e-300)
+        if model != "ac":
+            assert np.abs(kT - bT).max() <= 1e-13 * np.abs(bT).max()
+
+
+def test_temp_model_enthalpy_balance_insulated():
+    """Temp model with insulated faces: sum over cells of
+    (rho c - L_v varphi'(T)) dT/dt is the sum of the face fluxes, zero."""
+    rng = np.random.default_rng(31)
+    shape = (6, 5, 7)
+    p = _tiny_params("temp", shape, rng, faces=0, bc_kind=0)
+    p["gamma"] = 2.0
+    G = (rng.random(shape) < 0.3).astype(float)
+    T = 273.15 + rng.normal(0, 0.7, shape)
+    P = oracle.make_params(p)
+    kp, kT = oracle.rhs(P, G, 0.0, None, T)
+    ph, dph = brute.temp_phase(p, G, T)
+    rc = brute.blend(G, ph, p["rhoc"])
+    w = (rc - p["Lv"] * dph) * kT
+    assert abs(w.sum()) <= 1e-12 * np.abs(w).sum()
+    # the phase rate is varphi'(T) times the temperature rate (1 - tanh^2
+    # cancels, so two tanh implementations agree to ~1e-12 relative only)
+    assert np.allclose(kp, dph * kT, rtol=1e-9, atol=0)
+
+
+def test_temp_model_far_from_melting_is_pure_conduction():
+    """Away from T* (|gamma (T - T*)| large) varphi is constant, the latent
+    term vanishes, and water cells conduct as the liquid (T > T*): a cosine
+    mode of an all-water box decays at the discrete Neumann rate."""
+    n1, h = 8, 1e-3
+    p = _tiny_params("temp", (1, 1, n1), np.random.default_rng(0), faces=0, bc_kind=0)
+    p.update(h=h, gamma=200.0, lam=(0.6, 2.2, 1.0), rhoc=(4.2e6, 1.9e6, 2.0e6))
+    G = np.zeros((1, 1, n1))
+    i = np.arange(n1)
+    k = 2
+    T = 273.15 + 5.0 + 0.1 * np.cos(k * np.pi * (i + 0.5) / n1).reshape(1, 1, n1)
+    P = oracle.make_params(p)
+    _, kT = oracle.rhs(P, G, 0.0, None, T)
+    lam_k = -4.0 / h ** 2 * np.sin(k * np.pi / (2 * n1)) ** 2
+    want = 0.6 / 4.2e6 * lam_k * (T - 278.15)
+    assert np.allclose(kT, want, rtol=1e-10, atol=1e-18)
