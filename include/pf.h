@@ -304,6 +304,13 @@ int pf_unet_create(uint64_t seed, pf_unet** out);
 void pf_unet_destroy(pf_unet* net);
 const char* pf_unet_last_error(const pf_unet* net);
 int pf_unet_set_stream(pf_unet* net, uintptr_t stream);
+/* Forward (and data-gradient) convolution kernel of this network:
+ * 1 (default): LDS-tiled -- a 16 x 4 x 4 block of output voxels per
+ * workgroup with its input halo staged in LDS per chunk of input channels;
+ * 0: direct -- every B fragment gathered from memory.  Same products; the
+ * FP32 partial sums are taken in another order when cin spans several
+ * channel chunks. */
+int pf_unet_set_conv_kernel(pf_unet* net, int32_t variant);
 int64_t pf_unet_num_params(void);
 
 /* Copy the parameter vector out / in (host pointers, pf_unet_num_params

@@ -92,6 +92,7 @@ SIGNATURES = [
     ("pf_unet_destroy", None, [_H]),
     ("pf_unet_last_error", C.c_char_p, [_H]),
     ("pf_unet_set_stream", C.c_int, [_H, C.c_size_t]),
+    ("pf_unet_set_conv_kernel", C.c_int, [_H, C.c_int32]),
     ("pf_unet_num_params", C.c_int64, []),
     ("pf_unet_get_params", C.c_int, [_H, _VP]),
     ("pf_unet_set_params", C.c_int, [_H, _VP]),
@@ -400,6 +401,10 @@ class UNet:
             self.close()
         except Exception:
             pass
+
+    def set_conv_kernel(self, variant: str):
+        """'tiled' (default, LDS-staged input blocks) or 'direct'."""
+        self._check(lib().pf_unet_set_conv_kernel(self.h, {"direct": 0, "tiled": 1}[variant]))
 
     def get_params(self) -> np.ndarray:
         out = np.empty(unet_num_params(), np.float32)

@@ -152,6 +152,120 @@ __global__ __launch_bounds__(256) void conv3_fwd_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS-tiled form of the same convolution.  A workgroup owns a 16 x 4 x 4
+// block of output voxels (wavefront w: the plane z0 + w; N-tile t: the x-row
+// y0 + t; lane r: x0 + r) and all output channels.  The input block with its
+// one-voxel halo (18 x 6 x 6 voxels) is staged in LDS one chunk of CC input
+// channels at a time (row pitch CC + 8 channels, or 24 for CC = 8, so that
+// the 16 lanes of a group read 16-byte fragments from distinct banks); every
+// B fragment of the implicit GEMM is then one LDS read, and the input is read
+// from memory once per block instead of once per tap.  One k-block of 32 is
+// 32/CC taps x CC channels of the chunk, in the weight layout
+// k = tap * cin + ci (no re-layout).  The A fragments (weights) come from
+// memory through L1/L2, shared by all blocks.
+
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
+
+template <int CC>
+__host__ __device__ constexpr int tile_pitch() { return CC == 8 ? 24 : CC + 8; }
+
+template <int MT, int CC>
+__global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y,
+                                                          int tiles_z) {
+  constexpr int PITCH = tile_pitch<CC>();
+  constexpr int TPB = 32 / CC;  // taps per k-block
+  constexpr int KB = (27 + TPB - 1) / TPB;
+  __shared__ __align__(16) uint16_t sx[kHalo * PITCH];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, g = lane >> 4, r = lane & 15, w = tid >> 6;
+  // XCD-aware order: consecutive tiles of a row stay on one XCD
+  const int nblk = gridDim.x;
+  const int b = blockIdx.x;
+  const int q = nblk >> 3, rem = nblk & 7, xcd = b & 7, kk = b >> 3;
+  const int tile = (xcd < rem) ? xcd * (q + 1) + kk : rem * (q + 1) + (xcd - rem) * q + kk;
+  const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+  (void)tiles_z;
+
+  f32x4 acc[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunks = a.cin / CC;
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();
+    // stage the halo block of this channel chunk (zeros outside the grid)
+    constexpr int G8 = CC / 8;
+    for (int i = tid; i < kHalo * G8; i += 256) {
+      const int c8 = i % G8, hv = i / G8;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3) {
+        const long long src = ((long long)z * a.n2 + y) * a.n1 + x;
+        val = *reinterpret_cast<const uint4*>(a.in + src * a.in_stride + a.in_off + c * CC +
+                                              8 * c8);
+      }
+      *reinterpret_cast<uint4*>(sx + hv * PITCH + 8 * c8) = val;
+    }
+    __syncthreads();
+    const int cig = (8 * g) % CC;   // this lane group's channels within the chunk
+    const int tg = (8 * g) / CC;    // and its tap within the k-block
+#pragma unroll 3
+    for (int kb = 0; kb < KB; ++kb) {
+      const int tap = kb * TPB + tg;
+      bf16x8 bfrag[4];
+      if (tap < 27) {
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // halo offsets 0..2
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int hv = ((w + dz) * kHY + (t + dy)) * kHX + (r + dx);
+          bfrag[t] = *reinterpret_cast<const bf16x8*>(sx + hv * PITCH + cig);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bfrag[t] = zero8();
+      }
+      const int kw = (tap < 27 ? tap : 26) * a.cin + c * CC + cig;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const bf16x8 afrag = ld8(a.w + (long long)(m * 16 + r) * a.kpad + kw);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[m][t] = mfma16(afrag, bfrag[t], acc[m][t]);
+      }
+    }
+  }
+  // epilogue: lane holds channels m*16 + 4g .. +3 of voxel (x0 + r, y0 + t, z0 + w)
+  const int x = x0 + r, z = z0 + w;
+  if (x >= a.n1 || z >= a.n3) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int y = y0 + t;
+    if (y >= a.n2) continue;
+    const long long v = ((long long)z * a.n2 + y) * a.n1 + x;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int co = m * 16 + 4 * g;
+      uint16_t o[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float yv = acc[m][t][i] + (a.bias ? a.bias[co + i] : 0.0f);
+        if (a.relu) yv = yv > 0.0f ? yv : 0.0f;
+        o[i] = f2bf(yv);
+      }
+      uint2 pk;
+      pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+      pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+      *reinterpret_cast<uint2*>(a.out + v * a.out_stride + a.out_off + co) = pk;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient as an implicit GEMM over voxels:
 //   dW[co][tap][ci] = sum_v dY[v][co] X[v + offset(tap)][ci],  db[co] = sum_v dY[v][co].
 // Grid (voxel ranges) x (27 taps).  A workgroup walks its voxel range in
@@ -502,22 +616,71 @@ __global__ void reach_seed_kernel(const uint8_t* code, const void* phi, int fp64
   reach[v] = (!(code[v] & 0x40u) && p > 0.5) ? 1 : 0;
 }
 
-// one in-place sweep: a water cell joins when a face neighbour across a
-// water-water face has joined (monotone, so concurrent updates are benign)
-__global__ void reach_sweep_kernel(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
-                                   int* changed) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Sweep: a water cell joins when a face neighbour across a water-water face
+// has joined.  A workgroup loads a 16^3 block of reach flags
+// with a one-cell halo (and the block's cell codes) into LDS and iterates the
+// update inside the block until nothing changes, so a path through the
+// block is crossed in one launch; blocks exchange the front through the
+// halo on the next launch.  Every productive inner iteration marks at least
+// one of the block's 4096 cells, which bounds the loop.
+constexpr int kRB = 16, kRH = kRB + 2;
+
+__global__ __launch_bounds__(256) void reach_block_kernel(const uint8_t* code, uint8_t* reach,
+                                                          int n1, int n2, int n3, int bx, int by,
+                                                          int* changed) {
+  __shared__ uint8_t sr[kRH * kRH * kRH];
+  __shared__ uint8_t sc[kRB * kRB * kRB];
+  __shared__ int flag, any;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int x0 = (b % bx) * kRB, y0 = ((b / bx) % by) * kRB, z0 = (b / (bx * by)) * kRB;
   const long long pl = (long long)n1 * n2;
-  if (v >= pl * n3) return;
-  const unsigned c = code[v];
-  if ((c & 0x40u) || reach[v]) return;
-  const bool hit = ((c & 1u) && reach[v - 1]) || ((c & 2u) && reach[v + 1]) ||
-                   ((c & 4u) && reach[v - n1]) || ((c & 8u) && reach[v + n1]) ||
-                   ((c & 16u) && reach[v - pl]) || ((c & 32u) && reach[v + pl]);
-  if (hit) {
-    reach[v] = 1;
-    atomicOr(changed, 1);
+  for (int i = tid; i < kRH * kRH * kRH; i += 256) {
+    const int hx = i % kRH, hy = (i / kRH) % kRH, hz = i / (kRH * kRH);
+    const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+    uint8_t v = 0;
+    if (x >= 0 && x < n1 && y >= 0 && y < n2 && z >= 0 && z < n3) v = reach[z * pl + (long long)y * n1 + x];
+    sr[i] = v;
   }
+  for (int i = tid; i < kRB * kRB * kRB; i += 256) {
+    const int lx = i % kRB, ly = (i / kRB) % kRB, lz = i / (kRB * kRB);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    // cells outside the grid behave as glass (never join, never spread)
+    sc[i] = (x < n1 && y < n2 && z < n3) ? code[z * pl + (long long)y * n1 + x] : (uint8_t)0x40u;
+  }
+  if (tid == 0) any = 0;
+  for (int iter = 0; iter <= kRB * kRB * kRB; ++iter) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int i = tid; i < kRB * kRB * kRB; i += 256) {
+      const unsigned c = sc[i];
+      const int lx = i % kRB, ly = (i / kRB) % kRB, lz = i / (kRB * kRB);
+      const int h = ((lz + 1) * kRH + (ly + 1)) * kRH + (lx + 1);
+      if ((c & 0x40u) || sr[h]) continue;
+      const bool hit = ((c & 1u) && sr[h - 1]) || ((c & 2u) && sr[h + 1]) ||
+                       ((c & 4u) && sr[h - kRH]) || ((c & 8u) && sr[h + kRH]) ||
+                       ((c & 16u) && sr[h - kRH * kRH]) || ((c & 32u) && sr[h + kRH * kRH]);
+      if (hit) {
+        sr[h] = 1;
+        flag = 1;
+      }
+    }
+    __syncthreads();
+    const int f = flag;
+    __syncthreads();
+    if (!f) break;
+    if (tid == 0) any = 1;
+  }
+  __syncthreads();
+  if (!any) return;
+  for (int i = tid; i < kRB * kRB * kRB; i += 256) {
+    const int lx = i % kRB, ly = (i / kRB) % kRB, lz = i / (kRB * kRB);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    if (x >= n1 || y >= n2 || z >= n3) continue;
+    const int h = ((lz + 1) * kRH + (ly + 1)) * kRH + (lx + 1);
+    if (sr[h]) reach[z * pl + (long long)y * n1 + x] = 1;
+  }
+  if (tid == 0) atomicOr(changed, 1);
 }
 
 __global__ void clear_int_kernel(int* p) { *p = 0; }
@@ -527,12 +690,32 @@ __global__ void clear_int_kernel(int* p) { *p = 0; }
 
 static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+template <int CC>
+static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
+  const int tx = (a.n1 + kTX - 1) / kTX, ty = (a.n2 + kTY - 1) / kTY, tz = (a.n3 + kTZ - 1) / kTZ;
+  const dim3 grid((unsigned)(tx * ty * tz)), block(256);
+  switch (a.cout / 16) {
+    case 1: hipLaunchKernelGGL((conv3_tile_kernel<1, CC>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 2: hipLaunchKernelGGL((conv3_tile_kernel<2, CC>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 3: hipLaunchKernelGGL((conv3_tile_kernel<3, CC>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 4: hipLaunchKernelGGL((conv3_tile_kernel<4, CC>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 6: hipLaunchKernelGGL((conv3_tile_kernel<6, CC>), grid, block, 0, s, a, tx, ty, tz); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
   if (a.cin % 8 || a.cout % 16 || a.in_stride % 8 || a.in_off % 8 || a.out_stride % 4 ||
       a.out_off % 4 || a.kpad % 32 || a.kpad < 27 * a.cin)
     return hipErrorInvalidValue;
   const long long nvox = (long long)a.n1 * a.n2 * a.n3;
   if (nvox == 0) return hipSuccess;
+  if (a.variant == 1) {
+    if (a.cin % 32 == 0) return launch_tile_cc<32>(a, s);
+    if (a.cin % 16 == 0) return launch_tile_cc<16>(a, s);
+    return launch_tile_cc<8>(a, s);
+  }
   const int mt = a.cout / 16;
   const dim3 block(256);
 #define PFU_CONV(MT, NT)                                                          \
@@ -695,9 +878,10 @@ hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int 
   const long long n = (long long)n1 * n2 * n3;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, s, changed);
+  const int bx = (n1 + kRB - 1) / kRB, by = (n2 + kRB - 1) / kRB, bz = (n3 + kRB - 1) / kRB;
   for (int i = 0; i < sweeps; ++i)
-    hipLaunchKernelGGL(reach_sweep_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, code, reach,
-                       n1, n2, n3, changed);
+    hipLaunchKernelGGL(reach_block_kernel, dim3((unsigned)(bx * by * bz)), dim3(256), 0, s, code,
+                       reach, n1, n2, n3, bx, by, changed);
   return hipGetLastError();
 }
 

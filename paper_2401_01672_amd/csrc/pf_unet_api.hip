@@ -95,6 +95,7 @@ struct pf_unet {
   uint16_t* wslab = nullptr;
   long long adam_step = 0;
   int weights_dirty = 1;
+  int conv_variant = 1;  // forward-convolution kernel (1 LDS-tiled, 0 direct)
   // grid-dependent buffers
   int n1 = 0, n2 = 0, n3 = 0, train = 0;
   void* slab = nullptr;
@@ -240,6 +241,7 @@ int conv(pf_unet* n, int i, View x, View y, int g1, int g2, int g3) {
   a.n1 = g1;
   a.n2 = g2;
   a.n3 = g3;
+  a.variant = n->conv_variant;
   PFU_HIP(n, pfu::launch_conv_fwd(a, n->stream));
   return PF_OK;
 }
@@ -286,6 +288,7 @@ int conv_bwd(pf_unet* n, int i, View dy, View y, View x, const View* dx, int g1,
     a.n1 = g1;
     a.n2 = g2;
     a.n3 = g3;
+    a.variant = n->conv_variant;
     PFU_HIP(n, pfu::launch_conv_fwd(a, n->stream));
   }
   return PF_OK;
@@ -412,7 +415,7 @@ namespace {
 // nothing (each batch ends with one flag read by the host)
 int nucleus_reach(pf_unet* n, const uint8_t* code, const void* phi, int fp64) {
   const long long N = (long long)n->n1 * n->n2 * n->n3;
-  constexpr int kSweeps = 32;
+  constexpr int kSweeps = 4;  // blocked sweeps between host checks
   PFU_HIP(n, pfu::launch_reach_seed(code, phi, fp64, n->reach, N, n->stream));
   int* flag = reinterpret_cast<int*>(n->hostbuf + 16);
   for (long long done = 0; done <= N; done += kSweeps) {
@@ -506,6 +509,13 @@ void pf_unet_destroy(pf_unet* n) {
 }
 
 const char* pf_unet_last_error(const pf_unet* n) { return n ? n->err.c_str() : "null network"; }
+
+int pf_unet_set_conv_kernel(pf_unet* n, int32_t variant) {
+  if (!n) return PF_EINVAL;
+  if (variant != 0 && variant != 1) return ufail(n, PF_EINVAL, "variant must be 0 or 1");
+  n->conv_variant = variant;
+  return PF_OK;
+}
 
 int pf_unet_set_stream(pf_unet* n, uintptr_t stream) {
   if (!n) return PF_EINVAL;
@@ -685,6 +695,7 @@ int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b
   a.n1 = n1;
   a.n2 = n2;
   a.n3 = n3;
+  a.variant = 1;
   if (rc == PF_OK && pfu::launch_conv_fwd(a, s) != hipSuccess) rc = PF_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;
   hipFree(wf);
@@ -748,6 +759,7 @@ int pf_conv3_bf16_backward(const uint16_t* x, int32_t cin, const float* w, const
     a.n1 = n1;
     a.n2 = n2;
     a.n3 = n3;
+    a.variant = 1;
     if (rc == PF_OK && pfu::launch_conv_fwd(a, s) != hipSuccess) rc = PF_EHIP;
   }
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;

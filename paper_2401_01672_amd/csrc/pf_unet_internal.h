@@ -22,6 +22,8 @@ struct ConvArgs {
   int out_stride, out_off, cout;
   int relu;
   int n1, n2, n3;
+  int variant;         // 1: LDS-tiled kernel, 0: direct kernel (same products,
+                       // FP32 sums in another order when cin spans several chunks)
 };
 
 struct WgradArgs {

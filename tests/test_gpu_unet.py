@@ -111,9 +111,11 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 20, 24)])
-def test_forward_matches_reference(shape):
+@pytest.mark.parametrize("variant", ["tiled", "direct"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 20, 24), (8, 36, 20)])
+def test_forward_matches_reference(shape, variant):
     net = pf.UNet(seed=3)
+    net.set_conv_kernel(variant)
     p = net.get_params().astype(np.float64)
     mask, _ = _sample(shape, 1)
     for dT, ls in ((0.5, 0.0), (0.03, 2.7)):
@@ -138,9 +140,11 @@ def test_forward_deterministic():
     assert np.array_equal(a, b)
 
 
-def test_gradient_matches_reference():
+@pytest.mark.parametrize("variant", ["tiled", "direct"])
+def test_gradient_matches_reference(variant):
     shape = (16, 16, 16)
     net = pf.UNet(seed=5)
+    net.set_conv_kernel(variant)
     p = net.get_params().astype(np.float64)
     mask, target = _sample(shape, 3)
     loss, g = net.grad(_dev(mask, torch.uint8), _dev(target, torch.float32), 0.4, 1.0)
