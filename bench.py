@@ -62,6 +62,24 @@ WORKLOADS = {
              "(cold) and from the network's prediction (warm, inference included); value = "
              "median cold/warm wall-time ratio over the problems whose cold run reaches "
              "equilibrium"),
+    "temp_256_fp32": dict(
+        case="case_coupled_256", precision="fp32", override=dict(model="temp", gamma=2.0),
+        kernel="stage_kernel",
+        desc="Temp model (Sec. 2.3: phi = varphi(T), apparent heat capacity), FP32 fields + "
+             "FP64 reductions, 256^3 bead pack of the coupled case, bottom Dirichlet ramp "
+             "-5 -> +5 C, adaptive RKM tol 1e-6, one-cell stage kernels"),
+    "gradp_256_fp32": dict(
+        case="case_coupled_256", precision="fp32", override=dict(reaction="gradp"),
+        kernel="stage_kernel",
+        desc="coupled heat + Allen-Cahn with the GradP reaction term, FP32 fields + FP64 "
+             "reductions, 256^3 bead pack of the coupled case, bottom Dirichlet ramp "
+             "-5 -> +5 C, adaptive RKM tol 1e-6, one-cell stage kernels"),
+    "paper_200_fp32": dict(
+        case="case_paper", case_args=dict(n3=200), precision="fp32", kernel="stage_kernel",
+        desc="paper mode (Sec. 2.1, Tab. 2): coupled heat + Allen-Cahn on a 100x100x200 "
+             "vessel, smooth glass field (RSA bead bed + glass cap), no phase-field face rule, "
+             "nucleation disk anchored in the cap, cap face cooled to T*-25 K from T*+20 K, "
+             "FP32 fields + FP64 reductions, adaptive RKM tol 1e-6, one-cell stage kernels"),
     "sweep48_fp32": dict(
         case=None, precision="fp32",
         desc="batched parametric sweep: 48 micro-scale Allen-Cahn instances (edges 48-96, "
@@ -201,24 +219,38 @@ def read_traffic(workload: str, kernel: str, src_hash: str):
     return d.get("bytes_per_launch")
 
 
-def run_gpu(args, wl):
+def make_solver(wl):
+    """(case, solver with its initial state set, model) of a stencil workload."""
     import numpy as np
-    import torch
 
     import paper_2401_01672_amd as pf
     import pf_inputs as pi
 
+    case = getattr(pi, wl["case"])(**wl.get("case_args", {}))
+    params = dict(case.params, **wl.get("override", {}))
+    model = params.get("model", case.model)
+    npdt = np.float64 if wl["precision"] == "fp64" else np.float32
+    s = pf.Solver(params, case.mask, wl["precision"], dict(case.run), glass_field=case.G)
+    th = None if case.T0 is None else (case.T0 - params["t_star"]).astype(npdt)
+    if model == "temp":
+        s.set_state(None, th)
+    else:
+        s.set_state(case.phi0.astype(npdt), th)
+    return case, s, model
+
+
+def run_gpu(args, wl):
+    import torch
+
     torch.cuda.set_device(0)
-    case = getattr(pi, wl["case"])()
     prec = wl["precision"]
-    npdt = np.float64 if prec == "fp64" else np.float32
+    case, s, model = make_solver(wl)
     run = dict(case.run)
-    s = pf.Solver(case.params, case.mask, prec, run)
     s.set_loop(args.steps_per_poll, not args.no_graph)
-    s.set_schedule(args.schedule)
+    if args.schedule != "five":
+        s.set_schedule(args.schedule)
     if args.z_chunk:
         s.set_tile(args.z_chunk)
-    s.set_state(case.phi0.astype(npdt), (case.T0 - case.params["t_star"]).astype(npdt))
     s.set_time(0.0, run["dt0"])
     torch.cuda.synchronize()
     # warmup (includes the tile autotuner on the first call)
@@ -238,13 +270,18 @@ def run_gpu(args, wl):
     cfg = s.get_config()
     sched = cfg["schedule"]
     esize = 8 if prec == "fp64" else 4
-    nvar = 2 if case.model == "coupled" else 1
+    nvar = 2 if model == "coupled" else 1
     sb = pass_bytes(sched, nvar, esize)
+    if case.G is not None:  # paper mode also reads the glass field in every pass
+        sb = [b + esize for b in sb]
     npass = len(sb)
     per_pass = []
     for i in range(npass):
         gbs = sb[i] * ncell / (ms[i] * 1e-3) / 1e9
-        per_pass.append(dict(pass_=PASS_NAMES[sched][i], kernel=PASS_KERNELS[sched][i],
+        kl = PASS_KERNELS[sched][i]
+        if wl.get("kernel") == "stage_kernel":
+            kl = kl.replace("stage4_kernel", "stage_kernel")
+        per_pass.append(dict(pass_=PASS_NAMES[sched][i], kernel=kl,
                              ms=round(ms[i], 5), bytes_per_cell=sb[i], gbs=round(gbs, 1)))
     dom = max(range(npass), key=lambda i: ms[i])
     step_ms = sum(ms[:npass]) + ms[5]
@@ -254,8 +291,8 @@ def run_gpu(args, wl):
     achieved = per_pass[dom]["gbs"]
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=f"{PASS_KERNELS[sched][dom]} = {PASS_NAMES[sched][dom]} "
-                       f"({prec}, {case.model})",
+                kernel=f"{per_pass[dom]['kernel']} = {PASS_NAMES[sched][dom]} "
+                       f"({prec}, {model}{', GradP' if 'gradp' in args.workload else ''})",
                 algorithmic_bytes_per_launch=sb[dom] * ncell)
     extra = dict(
         passes=per_pass,
@@ -278,12 +315,15 @@ def cpu_baseline(wl, sample_steps: int):
     import oracle
     import pf_inputs as pi
 
-    case = getattr(pi, wl["case"])()
-    P = oracle.make_params(case.params)
+    case = getattr(pi, wl["case"])(**wl.get("case_args", {}))
+    params = dict(case.params, **wl.get("override", {}))
+    P = oracle.make_params(params)
     ctl = oracle.make_ctl(tol=case.run["tol"])
     T0 = case.T0
+    phi0 = None if params.get("model") == "temp" else case.phi0
     t0 = time.perf_counter()
-    _, _, st = oracle.integrate(P, case.mask, ctl, 0.0, case.run["dt0"], case.phi0, T0,
+    G = case.mask if case.G is None else case.G
+    _, _, st = oracle.integrate(P, G, ctl, 0.0, case.run["dt0"], phi0, T0,
                                 max_steps=sample_steps)
     wall = time.perf_counter() - t0
     n = st["steps_accepted"] + st["steps_rejected"]

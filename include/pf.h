@@ -145,6 +145,17 @@ typedef struct {
  * NULL pointers), PF_ENOMEM, PF_EHIP. */
 int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out);
 
+/* Paper mode (Sec. 2.1): like pf_create, but the glass is a smooth field
+ * G in [0, 1] (host pointer, n1*n2*n3 doubles, read during the call only;
+ * eq. of G_balls and the cap).  The phase-field Laplacian then acts across
+ * every face inside the box (no face rule at glass; the water indicator
+ * I_W(G) = max(0, 1 - zeta G) masks the update), and lambda and rho c are
+ * blended with each cell's G (eq. material-properties-blending-formula).
+ * Water cells for the diagnostics and the equilibrium test: G < 1/2.  Runs
+ * on the one-cell stage kernels (no four-cell, paired or batched variants).
+ * Errors: as pf_create, PF_EINVAL for G outside [0, 1]. */
+int pf_create_field(const pf_params* params, const double* G, pf_handle** out);
+
 /* Free every resource of the handle.  NULL is ignored. */
 void pf_destroy(pf_handle* h);
 
@@ -164,6 +175,10 @@ int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device
 
 /* Copy the current state out (same layout rules as pf_set_state). */
 int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device);
+
+/* Change the error tolerance of later runs (params.tol at creation;
+ * <= 0: fixed steps). */
+int pf_set_tolerance(pf_handle* h, double tol);
 
 /* Set the current time and the next proposed step. */
 int pf_set_time(pf_handle* h, double t, double dt);

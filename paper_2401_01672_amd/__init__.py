@@ -64,12 +64,14 @@ _lib = None
 _VP, _H = C.c_void_p, C.c_void_p
 SIGNATURES = [
     ("pf_create", C.c_int, [C.POINTER(PFParams), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("pf_create_field", C.c_int, [C.POINTER(PFParams), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("pf_destroy", None, [_H]),
     ("pf_last_error", C.c_char_p, [_H]),
     ("pf_set_stream", C.c_int, [_H, C.c_size_t]),
     ("pf_set_state", C.c_int, [_H, _VP, _VP, C.c_int]),
     ("pf_get_state", C.c_int, [_H, _VP, _VP, C.c_int]),
     ("pf_set_time", C.c_int, [_H, C.c_double, C.c_double]),
+    ("pf_set_tolerance", C.c_int, [_H, C.c_double]),
     ("pf_rhs", C.c_int, [_H, C.c_double, _VP, _VP, _VP, _VP]),
     ("pf_rkm_step", C.c_int, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(PFStepInfo)]),
@@ -177,15 +179,25 @@ class Solver:
     """One grid: owns a pf_handle."""
 
     def __init__(self, params: Dict, mask: np.ndarray, precision: str = "fp64",
-                 run: Optional[Dict] = None):
+                 run: Optional[Dict] = None, glass_field: Optional[np.ndarray] = None):
+        """mask: uint8 (n3, n2, n1), nonzero = glass; or glass_field: a smooth
+        G in [0, 1] (paper mode, pf_create_field; mask is then ignored)."""
         self.P = make_params(params, precision, run)
         self.precision = precision
         self.model = params.get("model", "ac")
         self.shape = (int(params["n3"]), int(params["n2"]), int(params["n1"]))
-        m = np.ascontiguousarray(mask, dtype=np.uint8)
-        assert m.shape == self.shape, (m.shape, self.shape)
         self.np_dtype = np.float64 if precision == "fp64" else np.float32
         h = C.c_void_p()
+        if glass_field is not None:
+            g = np.ascontiguousarray(glass_field, dtype=np.float64)
+            assert g.shape == self.shape, (g.shape, self.shape)
+            rc = lib().pf_create_field(C.byref(self.P), g.ctypes.data, C.byref(h))
+            if rc != 0:
+                raise PFError(rc, lib().pf_last_error(None).decode())
+            self.h = h
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert m.shape == self.shape, (m.shape, self.shape)
         rc = lib().pf_create(C.byref(self.P), m.ctypes.data, C.byref(h))
         if rc != 0:
             raise PFError(rc, lib().pf_last_error(None).decode())
@@ -249,6 +261,9 @@ class Solver:
 
     def set_time(self, t: float, dt: float):
         self._check(lib().pf_set_time(self.h, float(t), float(dt)))
+
+    def set_tolerance(self, tol: float):
+        self._check(lib().pf_set_tolerance(self.h, float(tol)))
 
     # -- computation -----------------------------------------------------------
     def rhs(self, t: float, phi, theta, dphi, dtheta):

@@ -32,6 +32,8 @@ struct pf_handle {
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   void* slab = nullptr;
+  void* G = nullptr;  // smooth glass field (paper mode), field precision; else null
+  int smooth = 0;
   uint8_t* code = nullptr;
   void* y[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* a[2] = {nullptr, nullptr};
@@ -107,14 +109,15 @@ void fill_model_const(const pf_params& P, ModelConst& m) {
   m.gamma = P.gamma;
   m.dT = P.dT;
   m.reaction = P.reaction;
+  m.zeta = P.zeta;
   m.gpc = P.xi * P.xi * P.mu * P.alpha;
   m.inv_h = 1.0 / P.h;
 }
 
 // the four-cell, paired and batched kernels implement the SigmaP1-P phase
 // equation of the AC and coupled models only
-bool simple_kernels_only(const pf_params& P) {
-  return P.model == PF_MODEL_TEMP || P.reaction != PF_REACT_SIGMA;
+bool simple_kernels_only(const pf_params& P, int smooth) {
+  return P.model == PF_MODEL_TEMP || P.reaction != PF_REACT_SIGMA || smooth;
 }
 
 int validate(const pf_params* P, const uint8_t* mask) {
@@ -154,6 +157,7 @@ StageArgs stage_args(const pf_handle* h, int stage) {
   StageArgs a;
   memset(&a, 0, sizeof(a));
   a.code = h->code;
+  a.G = h->G;
   a.ctl = h->ctl;
   a.mc = h->mc;
   a.z_chunk = h->z_chunk;
@@ -429,7 +433,11 @@ const char* pf_last_error(const pf_handle* h) {
   return h->err.c_str();
 }
 
-int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
+namespace {
+
+// shared by pf_create (binary mask) and pf_create_field (smooth G: mask = G >= 1/2)
+int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
+                pf_handle** out) {
   if (!out) return fail(nullptr, PF_EINVAL, "out must be non-NULL");
   *out = nullptr;
   int rc = validate(params, mask);
@@ -438,10 +446,12 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
   if (!h) return fail(nullptr, PF_ENOMEM, "host allocation failed");
   h->P = *params;
   fill_model_const(h->P, h->mc);
+  h->smooth = G ? 1 : 0;
+  h->mc.smooth = h->smooth;
   h->ncell = (long long)params->n1 * params->n2 * params->n3;
   h->esize = params->precision == PF_FP64 ? 8 : 4;
   h->nvar = params->model == PF_MODEL_COUPLED ? 2 : 1;
-  h->vec = (params->n1 % 4 == 0 && !simple_kernels_only(*params)) ? 1 : 0;
+  h->vec = (params->n1 % 4 == 0 && !simple_kernels_only(*params, G ? 1 : 0)) ? 1 : 0;
   h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
 
   auto bail = [&](int code, const std::string& msg) {
@@ -465,7 +475,8 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
   const size_t code_bytes = ((size_t)h->ncell + 255) & ~(size_t)255;
   const size_t part_bytes = (((size_t)h->max_parts * (pf::kPartS1 + pf::kPartS5) + 64) *
                              sizeof(double) + 255) & ~(size_t)255;
-  const size_t total = field * 6 * h->nvar + code_bytes + part_bytes + 2 * 256;  // control block + timing copy
+  const size_t total = field * 6 * h->nvar + code_bytes + part_bytes + 2 * 256 +  // control block + timing copy
+                       (h->smooth ? field : 0);
   if (hipMalloc(&h->slab, total) != hipSuccess) return bail(PF_ENOMEM, "hipMalloc of work buffers failed");
   char* p = static_cast<char*>(h->slab);
   for (int v = 0; v < h->nvar; ++v) {
@@ -482,8 +493,21 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
   h->diag_out = h->part5 + h->max_parts;
   p += part_bytes;
   h->ctl = reinterpret_cast<DevCtl*>(p);
+  p += 2 * 256;
+  if (h->smooth) h->G = p;
   if (hipHostMalloc((void**)&h->hctl, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess)
     return bail(PF_ENOMEM, "hipHostMalloc failed");
+  if (h->smooth) {  // the glass field in the field precision
+    hipError_t eg;
+    if (h->esize == 8) {
+      eg = hipMemcpy(h->G, G, (size_t)h->ncell * 8, hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> gf((size_t)h->ncell);
+      for (long long i = 0; i < h->ncell; ++i) gf[(size_t)i] = (float)G[i];
+      eg = hipMemcpy(h->G, gf.data(), (size_t)h->ncell * 4, hipMemcpyHostToDevice);
+    }
+    if (eg != hipSuccess) return bail(PF_EHIP, "upload of the glass field failed");
+  }
 
   // neighbourhood codes from the host mask
   uint8_t* dmask = nullptr;
@@ -504,6 +528,26 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
     return bail(PF_EHIP, "control block init failed");
   *out = h;
   return PF_OK;
+}
+
+}  // namespace
+
+int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out) {
+  return create_impl(params, mask, nullptr, out);
+}
+
+int pf_create_field(const pf_params* params, const double* G, pf_handle** out) {
+  if (!params || !G) return fail(nullptr, PF_EINVAL, "params and G must be non-NULL");
+  if (params->n1 < 1 || params->n2 < 1 || params->n3 < 1)
+    return fail(nullptr, PF_EINVAL, "grid sizes must be >= 1");
+  const size_t n = (size_t)params->n1 * params->n2 * params->n3;
+  std::vector<uint8_t> mask(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!(G[i] >= 0.0 && G[i] <= 1.0))
+      return fail(nullptr, PF_EINVAL, "G must lie in [0, 1]");
+    mask[i] = G[i] >= 0.5 ? 1 : 0;
+  }
+  return create_impl(params, mask.data(), G, out);
 }
 
 void pf_destroy(pf_handle* h) {
@@ -532,6 +576,13 @@ int64_t pf_num_cells(const pf_handle* h) { return h ? h->ncell : -1; }
 int pf_synchronize(pf_handle* h) {
   if (!h) return PF_EINVAL;
   PF_HIP(h, hipStreamSynchronize(h->stream));
+  return PF_OK;
+}
+
+int pf_set_tolerance(pf_handle* h, double tol) {
+  if (!h) return PF_EINVAL;
+  if (!(tol == tol)) return fail(h, PF_EINVAL, "tol must not be NaN");
+  h->P.tol = tol;  // read into the control block at the start of each run
   return PF_OK;
 }
 
@@ -618,7 +669,7 @@ int pf_set_vector(pf_handle* h, int32_t enable) {
   if (!h) return PF_EINVAL;
   if (enable && h->P.n1 % 4 != 0)
     return fail(h, PF_EINVAL, "four-cell kernels need n1 divisible by 4");
-  if (enable && simple_kernels_only(h->P))
+  if (enable && simple_kernels_only(h->P, h->smooth))
     return fail(h, PF_EINVAL, "four-cell kernels implement the SigmaP1-P AC and coupled models only");
   h->vec = enable ? 1 : 0;
   return set_tiles(h, h->z_chunk);
@@ -657,7 +708,7 @@ int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info) {
 
 int pf_diagnostics(pf_handle* h, pf_run_stats* st) {
   if (!h || !st) return PF_EINVAL;
-  PF_HIP(h, pf::launch_diag(h->P.precision, h->P.model, h->code, h->y[h->cur][0],
+  PF_HIP(h, pf::launch_diag(h->P.precision, h->P.model, h->code, h->G, h->y[h->cur][0],
                             h->y[h->cur][1], h->mc, h->ncell, h->part1, h->max_parts > 1024 ? 1024 : h->max_parts,
                             h->diag_out, h->stream));
   double out[4];
@@ -814,7 +865,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
     if (inst[i]->P.precision != inst[0]->P.precision || inst[i]->P.model != inst[0]->P.model)
       return fail(nullptr, PF_EINVAL, "batch: all instances need the same model and precision");
-    if (simple_kernels_only(inst[i]->P))
+    if (simple_kernels_only(inst[i]->P, inst[i]->smooth))
       return fail(nullptr, PF_EINVAL, "batch: the SigmaP1-P AC and coupled models only");
     if (inst[i]->P.n1 % 4 != 0)
       return fail(nullptr, PF_EINVAL, "batch: every instance needs n1 divisible by 4");
@@ -963,7 +1014,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
 
 int pf_set_schedule(pf_handle* h, int32_t schedule) {
   if (!h || (schedule != pf::kSchedFive && schedule != pf::kSchedPaired)) return PF_EINVAL;
-  if (schedule == pf::kSchedPaired && simple_kernels_only(h->P))
+  if (schedule == pf::kSchedPaired && simple_kernels_only(h->P, h->smooth))
     return fail(h, PF_EINVAL, "the paired schedule implements the SigmaP1-P AC and coupled models only");
   h->sched = schedule;
   h->autotune_pending = 1;

@@ -63,7 +63,8 @@ struct ModelConst {
   double gamma;     // Temp model
   double dT;        // supercooling of the micro-scale model (theta = -dT)
   int reaction;     // PF_REACT_SIGMA or PF_REACT_GRADP
-  int pad_r;
+  int smooth;       // 1: smooth glass field G (paper mode), 0: binary mask
+  double zeta;      // water indicator I_W(G) = max(0, 1 - zeta G)
   double gpc;       // GradP drive coefficient xi^2 mu alpha
   double inv_h;     // 1/h (GradP gradient)
 };
@@ -79,6 +80,7 @@ struct Buffers {
 // Arguments of a stage kernel (passed by value).
 struct StageArgs {
   const uint8_t* code;
+  const void* G;      // smooth glass field (paper mode), in the field precision; else null
   DevCtl* ctl;
   double* part;       // per-workgroup partial reductions
   const void* in[2];  // stage input (stencil), per variable
@@ -140,9 +142,9 @@ hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a,
                         hipStream_t s);
 hipError_t launch_controller(DevCtl* ctl, const double* part1, int np1, const double* part5,
                              int np5, double h3, hipStream_t s);
-hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* phi,
-                       const void* th, const ModelConst& m, long long n, double* part,
-                       int nparts, double* out4, hipStream_t s);
+hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* G,
+                       const void* phi, const void* th, const ModelConst& m, long long n,
+                       double* part, int nparts, double* out4, hipStream_t s);
 int grid_blocks(const ModelConst& mc, int z_chunk, int vec, int* tiles_p, int* tiles_z);
 // paired kernels: tile shape index ts selects (TX, TY) from kPairTiles
 constexpr int kPairTiles[3][2] = {{64, 4}, {64, 8}, {32, 8}};

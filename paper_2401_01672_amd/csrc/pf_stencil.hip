@@ -209,9 +209,19 @@ struct CellRHS {
 // combined-heat-xfer-phase-transition).  The caller passes the theta
 // neighbours in thn (boundary faces: the cell's own value); kth receives
 // d theta/dt and kphi = varphi'(T) d theta/dt.
+// With e = exp(2x): (1 - tanh(x))/2 = 1/(1 + e) and (1 - tanh^2(x))/4 =
+// e/(1 + e)^2 = 1/(e + 2 + 1/e) -- no cancellation where tanh saturates.
+// exp in FP64, the hardware exp2 in FP32.
+__device__ __forceinline__ double exp2x(double x) { return exp(2.0 * x); }
+__device__ __forceinline__ float exp2x(float x) { return __expf(2.0f * x); }
+template <typename R>
+__device__ __forceinline__ R logistic_e(R e) { return R(1) / (R(1) + e); }
+template <typename R>
+__device__ __forceinline__ R bump_e(R e) { return R(1) / (e + R(2) + R(1) / e); }
+
 template <typename R>
 __device__ __forceinline__ R temp_phi(const ModelConst& m, R th, R iw) {
-  return R(0.5) * iw * (R(1) - tanh(R(m.gamma) * th));
+  return iw * logistic_e(exp2x(R(m.gamma) * th));
 }
 
 template <typename R, int REACT>
@@ -222,8 +232,8 @@ struct CellRHS<R, PF_MODEL_TEMP, REACT> {
                                               R thD, R& kth, R& kphi) {
     const bool glass = code & kGlassBit;
     const R iw = glass ? R(m.iw_glass) : R(1);
-    const R tc = tanh(R(m.gamma) * thc);
-    const R phic = R(0.5) * iw * (R(1) - tc);
+    const R e = exp2x(R(m.gamma) * thc);
+    const R phic = iw * logistic_e(e);  // I_W (1 - tanh(gamma theta))/2
     const R lamc = glass ? R(m.lamG) : R(m.lamL) + phic * R(m.dlam);
     R qq = R(0);
 #pragma unroll
@@ -235,16 +245,91 @@ struct CellRHS<R, PF_MODEL_TEMP, REACT> {
     const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
     if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
     const R rc = glass ? R(m.rcG) : R(m.rcL) + phic * R(m.drc);
-    const R dphi = R(-0.5) * iw * R(m.gamma) * (R(1) - tc * tc);
+    // varphi'(T) = -gamma I_W (1 - tanh^2)/2
+    const R dphi = R(-2) * iw * R(m.gamma) * bump_e(e);
     kth = (R(0.5) * R(m.cH) * qq) / (rc - R(m.Lv) * dphi);
     kphi = dphi * kth;
+  }
+};
+
+// Paper mode (Sec. 2.1): a smooth glass field G in [0, 1] instead of the
+// binary mask.  The phase-field Laplacian acts across every face inside the
+// box (no face rule at glass; I_W(G) = max(0, 1 - zeta G) masks the update,
+// eq. water-indicator), and lambda, rho c are blended with the cell's own G
+// (eq. material-properties-blending-formula).  Gn: G of the six neighbours
+// (boundary faces: any value, their differences vanish by the caller's
+// precondition thn[f] == thc, phn[f] == phic).  inb: bit f = the neighbour
+// through face f exists.
+template <typename R>
+__device__ __forceinline__ R blend3(R G, R phi, R wL, R dw, R wG) {
+  return G * wG + (R(1) - G) * (wL + phi * dw);
+}
+
+template <typename R, int MODEL, int REACT>
+struct CellRHSSmooth {
+  __device__ __forceinline__ static void eval(const ModelConst& m, R phic, R thc,
+                                              const R (&phn)[6], const R (&thn)[6], R Gc,
+                                              const R (&Gn)[6], unsigned inb, unsigned dirf,
+                                              R thD, R& kphi, R& kth) {
+    const R iw = fmax(R(0), R(1) - R(m.zeta) * Gc);
+    R pc = phic;
+    R pn[6];
+    R dphi = R(0);
+    if (MODEL == PF_MODEL_TEMP) {
+      // phi = varphi(T) = I_W(G) (1 - tanh(gamma theta)) / 2
+      const R e = exp2x(R(m.gamma) * thc);
+      pc = iw * logistic_e(e);
+      dphi = R(-2) * iw * R(m.gamma) * bump_e(e);
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+        pn[f] = temp_phi(m, thn[f], fmax(R(0), R(1) - R(m.zeta) * Gn[f]));
+      kphi = R(0);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 6; ++f) pn[f] = phn[f];
+      R lap = R(0);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) lap += pn[f] - pc;
+      R fr;
+      if (REACT == PF_REACT_GRADP) {
+        const R gn = grad_norm(m, pc, pn, inb);
+        const R under = (MODEL == PF_MODEL_AC) ? R(m.dT) : -thc;
+        fr = R(2) * pc * (R(1) - pc) * (pc - R(0.5)) + R(m.gpc) * gn * under;
+      } else {
+        const R sa = limiter_fast(pc, R(m.inv_de), R(m.e0 * m.inv_de));
+        const R sb = limiter_fast(R(1) - pc, R(m.inv_de), R(m.e0 * m.inv_de));
+        const R drive = (MODEL == PF_MODEL_AC) ? R(m.betaAC) : R(m.beta0) * (-thc);
+        fr = R(2) * pc * (R(1) - pc) * (pc - R(0.5) + drive * sa * sb);
+      }
+      kphi = iw * (R(m.cL) * lap + R(m.cR) * fr);
+    }
+    if (MODEL == PF_MODEL_AC) {
+      kth = R(0);
+      return;
+    }
+    const R lamc = blend3(Gc, pc, R(m.lamL), R(m.dlam), R(m.lamG));
+    R qq = R(0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const R lamn = blend3(Gn[f], pn[f], R(m.lamL), R(m.dlam), R(m.lamG));
+      qq += (lamc + lamn) * (thn[f] - thc);
+    }
+    const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
+    if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
+    const R rc = blend3(Gc, pc, R(m.rcL), R(m.drc), R(m.rcG));
+    if (MODEL == PF_MODEL_TEMP) {
+      kth = (R(0.5) * R(m.cH) * qq) / (rc - R(m.Lv) * dphi);
+      kphi = dphi * kth;
+    } else {
+      kth = (R(0.5) * R(m.cH) * qq + R(m.Lv) * kphi) / rc;
+    }
   }
 };
 
 // ---------------------------------------------------------------------------
 // Stage kernel.  STAGE 0 = standalone RHS (in -> out as k).
 
-template <typename R, int MODEL, int STAGE, int REACT = PF_REACT_SIGMA>
+template <typename R, int MODEL, int STAGE, int REACT = PF_REACT_SIGMA, int SMOOTH = 0>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
   const ModelConst& m = a.mc;
@@ -342,9 +427,29 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
         for (int f = 0; f < 6; ++f) thn[f] = R(0);
       }
       R kp, kt;
-      // Temp model: the single unknown (theta) travels in the first slot;
-      // kp = d theta/dt, kt = d phi/dt
-      CellRHS<R, MODEL, REACT>::eval(m, pc, tc, phn, thn, code, inb, dirf, thD, kp, kt);
+      R Gc = R(0);
+      if (SMOOTH) {
+        const R* Gf = static_cast<const R*>(a.G);
+        Gc = Gf[n];
+        R Gn[6];
+        Gn[0] = Gf[n + oxm];
+        Gn[1] = Gf[n + oxp];
+        Gn[2] = Gf[n + oym];
+        Gn[3] = Gf[n + oyp];
+        Gn[4] = z > 0 ? Gf[n - plane] : Gc;
+        Gn[5] = zp_in ? Gf[n + plane] : Gc;
+        // Temp model: the single unknown (theta) travels in the first slot
+        if (MODEL == PF_MODEL_TEMP)
+          CellRHSSmooth<R, MODEL, REACT>::eval(m, R(0), pc, thn, phn, Gc, Gn, inb, dirf, thD,
+                                               kt, kp);
+        else
+          CellRHSSmooth<R, MODEL, REACT>::eval(m, pc, tc, phn, thn, Gc, Gn, inb, dirf, thD, kp,
+                                               kt);
+      } else {
+        // Temp model: the single unknown (theta) travels in the first slot;
+        // kp = d theta/dt, kt = d phi/dt
+        CellRHS<R, MODEL, REACT>::eval(m, pc, tc, phn, thn, code, inb, dirf, thD, kp, kt);
+      }
 
       if (STAGE == 0) {
         oP[n] = kp;
@@ -361,9 +466,12 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
         double thc_d = kCoupled ? (double)tc : -m.dT;
         if (MODEL == PF_MODEL_TEMP) {
           thc_d = (double)pc;
-          dpc = (double)temp_phi(m, pc, water ? R(1) : R(m.iw_glass));
+          const R iw = SMOOTH ? fmax(R(0), R(1) - R(m.zeta) * Gc) : (water ? R(1) : R(m.iw_glass));
+          dpc = (double)temp_phi(m, pc, iw);
         }
-        const double rc = (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
+        const double Gd = (double)Gc;
+        const double rc = SMOOTH ? Gd * m.rcG + (1.0 - Gd) * (m.rcL + dpc * m.drc)
+                                 : (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
         if (water) {
           // no phase-field equation in the Temp model: no equilibrium measure
           if (MODEL != PF_MODEL_TEMP) red0 = dmax_nf(red0, fabs((double)kp));
@@ -715,22 +823,24 @@ int batch_max_blocks(int precision, int model) {
 // (water-cell count, sum phi over water, enthalpy sum, ice count).
 
 template <typename R, int MODEL>
-__global__ __launch_bounds__(kBlock) void diag_kernel(const uint8_t* code, const R* phi,
-                                                      const R* th, ModelConst m, long long n,
-                                                      double* part) {
+__global__ __launch_bounds__(kBlock) void diag_kernel(const uint8_t* code, const R* G,
+                                                      const R* phi, const R* th, ModelConst m,
+                                                      long long n, double* part) {
   __shared__ double smem[8 * kWaves];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (long long)gridDim.x * kBlock) {
     const bool glass = code[i] & kGlassBit;
+    const R Gc = G ? G[i] : R(0);
+    const R iw = G ? fmax(R(0), R(1) - R(m.zeta) * Gc) : (glass ? R(m.iw_glass) : R(1));
     // Temp model: the state is theta alone (passed as phi), phi = varphi(T)
-    const double ph = MODEL == PF_MODEL_TEMP
-                          ? (double)temp_phi(m, phi[i], glass ? R(m.iw_glass) : R(1))
-                          : (double)phi[i];
+    const double ph = MODEL == PF_MODEL_TEMP ? (double)temp_phi(m, phi[i], iw) : (double)phi[i];
     const double thc = MODEL == PF_MODEL_COUPLED ? (double)th[i]
                        : MODEL == PF_MODEL_TEMP  ? (double)phi[i]
                                                  : -m.dT;
-    const double rc = glass ? m.rcG : m.rcL + ph * m.drc;
+    const double Gd = (double)Gc;
+    const double rc = G ? Gd * m.rcG + (1.0 - Gd) * (m.rcL + ph * m.drc)
+                        : glass ? m.rcG : m.rcL + ph * m.drc;
     if (!glass) {
       v[0] += 1.0;
       v[1] += ph;
@@ -1354,29 +1464,36 @@ hipError_t launch_build_code(const uint8_t* mask, uint8_t* code, int n1, int n2,
   return hipGetLastError();
 }
 
-template <typename R, int MODEL, int REACT>
+template <typename R, int MODEL, int REACT, int SMOOTH>
 static hipError_t launch_scalar_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
   switch (stage) {
-    case 0: hipLaunchKernelGGL((stage_kernel<R, MODEL, 0, REACT>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((stage_kernel<R, MODEL, 1, REACT>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((stage_kernel<R, MODEL, 2, REACT>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((stage_kernel<R, MODEL, 3, REACT>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((stage_kernel<R, MODEL, 4, REACT>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((stage_kernel<R, MODEL, 5, REACT>), grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((stage_kernel<R, MODEL, 0, REACT, SMOOTH>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((stage_kernel<R, MODEL, 1, REACT, SMOOTH>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stage_kernel<R, MODEL, 2, REACT, SMOOTH>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stage_kernel<R, MODEL, 3, REACT, SMOOTH>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((stage_kernel<R, MODEL, 4, REACT, SMOOTH>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((stage_kernel<R, MODEL, 5, REACT, SMOOTH>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// GradP or the smooth glass field: one-cell-per-thread kernels only
+template <typename R, int MODEL>
+static hipError_t launch_simple_t(int stage, const StageArgs& a, hipStream_t s) {
+  if (a.vec || (a.mc.smooth && !a.G)) return hipErrorInvalidValue;
+  if (a.mc.reaction == PF_REACT_GRADP)
+    return a.mc.smooth ? launch_scalar_t<R, MODEL, PF_REACT_GRADP, 1>(stage, a, s)
+                       : launch_scalar_t<R, MODEL, PF_REACT_GRADP, 0>(stage, a, s);
+  return a.mc.smooth ? launch_scalar_t<R, MODEL, PF_REACT_SIGMA, 1>(stage, a, s)
+                     : launch_scalar_t<R, MODEL, PF_REACT_SIGMA, 0>(stage, a, s);
+}
+
 template <typename R, int MODEL>
 static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
-  // GradP reaction: one-cell-per-thread kernels only
-  if (a.mc.reaction == PF_REACT_GRADP) {
-    if (a.vec) return hipErrorInvalidValue;
-    return launch_scalar_t<R, MODEL, PF_REACT_GRADP>(stage, a, s);
-  }
+  if (a.mc.reaction == PF_REACT_GRADP || a.mc.smooth) return launch_simple_t<R, MODEL>(stage, a, s);
   if (a.vec) {
     switch (stage) {
       case 0: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 0>), grid, block, 0, s, a); break;
@@ -1447,13 +1564,11 @@ hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a,
   if (precision == PF_FP64) {
     if (model == PF_MODEL_AC) return launch_stage_t<double, PF_MODEL_AC>(stage, a, s);
     if (model == PF_MODEL_COUPLED) return launch_stage_t<double, PF_MODEL_COUPLED>(stage, a, s);
-    if (model == PF_MODEL_TEMP)
-      return launch_scalar_t<double, PF_MODEL_TEMP, PF_REACT_SIGMA>(stage, a, s);
+    if (model == PF_MODEL_TEMP) return launch_simple_t<double, PF_MODEL_TEMP>(stage, a, s);
   } else {
     if (model == PF_MODEL_AC) return launch_stage_t<float, PF_MODEL_AC>(stage, a, s);
     if (model == PF_MODEL_COUPLED) return launch_stage_t<float, PF_MODEL_COUPLED>(stage, a, s);
-    if (model == PF_MODEL_TEMP)
-      return launch_scalar_t<float, PF_MODEL_TEMP, PF_REACT_SIGMA>(stage, a, s);
+    if (model == PF_MODEL_TEMP) return launch_simple_t<float, PF_MODEL_TEMP>(stage, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1465,30 +1580,30 @@ hipError_t launch_controller(DevCtl* ctl, const double* part1, int np1, const do
   return hipGetLastError();
 }
 
-hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* phi,
-                       const void* th, const ModelConst& m, long long n, double* part, int nparts,
-                       double* out4, hipStream_t s) {
+hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* G,
+                       const void* phi, const void* th, const ModelConst& m, long long n,
+                       double* part, int nparts, double* out4, hipStream_t s) {
   const dim3 grid((unsigned)nparts), block(kBlock);
   if (precision == PF_FP64) {
     if (model == PF_MODEL_COUPLED)
       hipLaunchKernelGGL((diag_kernel<double, PF_MODEL_COUPLED>), grid, block, 0, s, code,
-                         (const double*)phi, (const double*)th, m, n, part);
+                         (const double*)G, (const double*)phi, (const double*)th, m, n, part);
     else if (model == PF_MODEL_TEMP)
       hipLaunchKernelGGL((diag_kernel<double, PF_MODEL_TEMP>), grid, block, 0, s, code,
-                         (const double*)phi, (const double*)th, m, n, part);
+                         (const double*)G, (const double*)phi, (const double*)th, m, n, part);
     else
       hipLaunchKernelGGL((diag_kernel<double, PF_MODEL_AC>), grid, block, 0, s, code,
-                         (const double*)phi, (const double*)th, m, n, part);
+                         (const double*)G, (const double*)phi, (const double*)th, m, n, part);
   } else {
     if (model == PF_MODEL_COUPLED)
       hipLaunchKernelGGL((diag_kernel<float, PF_MODEL_COUPLED>), grid, block, 0, s, code,
-                         (const float*)phi, (const float*)th, m, n, part);
+                         (const float*)G, (const float*)phi, (const float*)th, m, n, part);
     else if (model == PF_MODEL_TEMP)
       hipLaunchKernelGGL((diag_kernel<float, PF_MODEL_TEMP>), grid, block, 0, s, code,
-                         (const float*)phi, (const float*)th, m, n, part);
+                         (const float*)G, (const float*)phi, (const float*)th, m, n, part);
     else
       hipLaunchKernelGGL((diag_kernel<float, PF_MODEL_AC>), grid, block, 0, s, code,
-                         (const float*)phi, (const float*)th, m, n, part);
+                         (const float*)G, (const float*)phi, (const float*)th, m, n, part);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -49,14 +49,10 @@ def run(workload: str, schedule: str, steps: int):
     import pf_inputs as pi
 
     wl = bench.WORKLOADS[workload]
-    case = getattr(pi, wl["case"])()
-    prec = wl["precision"]
-    npdt = np.float64 if prec == "fp64" else np.float32
-    s = pf.Solver(case.params, case.mask, prec, case.run)
+    case, s, _ = bench.make_solver(wl)
     s.set_loop(16, False)
-    s.set_schedule(schedule)  # and the same tile autotuner as the benchmark
-    th = None if case.T0 is None else (case.T0 - case.params["t_star"]).astype(npdt)
-    s.set_state(case.phi0.astype(npdt), th)
+    if schedule != "five":
+        s.set_schedule(schedule)  # and the same tile autotuner as the benchmark
     s.set_time(0.0, case.run["dt0"])
     st = s.integrate(max_steps=steps)
     print(json.dumps(dict(steps=steps, accepted=st["steps_accepted"], config=s.get_config())),

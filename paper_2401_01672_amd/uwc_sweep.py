@@ -1,0 +1,119 @@
+"""Unfrozen water content versus supercooling at the paper's micro scales.
+
+The micro-scale experiment of Sec. 3.3: the vessel of Tab. 2 scaled so that
+the bead radius r is that of a real powder (L3 = 20 r; the paper uses
+polystyrene, r = 5 um, and graphitized carbon black, r = 0.12 um), the
+micro-scale model of Sec. 2.4 (Allen-Cahn at constant supercooling dT) with
+the realistic attachment coefficient of Tab. 1, ice growing from the
+nucleation disk anchored in the glass cap until the state is stationary, and
+the unfrozen water content of eq. UWC-formula evaluated over the bottom half
+of the vessel.  The geometry is the paper-mode vessel of
+``pf_inputs.case_paper`` (smooth glass field, no phase-field face rule) on a
+synthetic bead bed.
+
+Every run goes through the library (pf_create_field, pf_integrate, FP64 on
+the one-cell kernels: at the 0.12 um scale the right-hand side's FP32
+roundoff alone exceeds the 1e-6 s^-1 equilibrium threshold).
+
+Run ``python -m paper_2401_01672_amd.uwc_sweep --help``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from typing import Dict, List
+
+import numpy as np
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+
+import pf_inputs as pi  # noqa: E402
+
+MATERIALS = {"polystyrene": 5.0e-6, "carbon_black": 0.12e-6}
+DT_LIST = [0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0, 25.0]
+EQ_TOL = 1e-6
+
+
+def problem(r_m: float, dT: float, n3: int = 100, seed: int = 5):
+    """Paper-mode micro-scale problem.  Two tolerances: tol = 1e-6 while the
+    ice front moves, then tol_eq, at which the stiffest mode held at its
+    stability limit sits below half the equilibrium threshold (as for the
+    sweep instances); first step at the explicit stability limit."""
+    c = pi.case_paper(n3, seed=seed, model="ac", L3=20.0 * r_m, alpha=pi.ALPHA_REAL, dT=dT)
+    h, a = c.params["h"], c.params["alpha"]
+    lam_max = 12.0 / (a * h * h)
+    c.run.update(tol=1e-6, tol_eq=min(1e-6, 0.5 * EQ_TOL / lam_max), dt0=1.0 / lam_max,
+                 t_end=1e30, lam_max=lam_max)
+    return c
+
+
+def bottom_half_uwc(G: np.ndarray, phi: np.ndarray) -> Dict[str, float]:
+    """eq. UWC-formula over the bottom half x3 < L3/2: water cells G < 1/2,
+    ice cells among them phi > 1/2."""
+    n3 = G.shape[0]
+    Gb, pb = G[: n3 // 2], phi[: n3 // 2]
+    water = Gb < 0.5
+    nw = int(water.sum())
+    ni = int((water & (pb > 0.5)).sum())
+    return dict(water_cells=nw, ice_cells=ni, uwc=1.0 - ni / nw if nw else float("nan"))
+
+
+def run_one(c, budget: int) -> Dict:
+    """Phase 1 at tol = 1e-6 until max water |d phi/dt| falls below the level
+    that tolerance can resolve (4 lam_max tol); phase 2 at tol_eq down to the
+    1e-6 s^-1 equilibrium threshold."""
+    import paper_2401_01672_amd as pf
+    s = pf.Solver(c.params, None, "fp64", c.run, glass_field=c.G)
+    s.set_state(c.phi0)
+    s.set_time(0.0, c.run["dt0"])
+    t0 = time.perf_counter()
+    eq1 = max(EQ_TOL, 4.0 * c.run["lam_max"] * c.run["tol"])
+    st1 = s.integrate(max_steps=budget, eq_tol=eq1, raise_on_error=False)
+    n1 = st1["steps_accepted"] + st1["steps_rejected"]
+    st = st1
+    if st1["status"] == 1 and eq1 > EQ_TOL:
+        s.set_tolerance(c.run["tol_eq"])
+        st = s.integrate(max_steps=budget - n1, eq_tol=EQ_TOL, raise_on_error=False)
+    wall = time.perf_counter() - t0
+    phi, _ = s.get_state()
+    s.close()
+    n2 = st["steps_accepted"] + st["steps_rejected"] if st is not st1 else 0
+    out = dict(status=st["status"], attempts=n1 + n2, attempts_phase1=n1,
+               t=st["t"], wall_s=wall, cells=c.ncells)
+    out.update(bottom_half_uwc(c.G, phi))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--n3", type=int, default=100)
+    ap.add_argument("--materials", default="polystyrene,carbon_black")
+    ap.add_argument("--dT", default=",".join(str(v) for v in DT_LIST))
+    ap.add_argument("--budget", type=int, default=300000)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    res: List[Dict] = []
+    for mat in a.materials.split(","):
+        for dT in (float(v) for v in a.dT.split(",")):
+            c = problem(MATERIALS[mat], dT, a.n3)
+            r = dict(material=mat, r_m=MATERIALS[mat], dT=dT, h=c.params["h"], **run_one(c, a.budget))
+            res.append(r)
+            print(json.dumps(r), flush=True)
+    cells = sum(r["cells"] * r["attempts"] for r in res)
+    wall = sum(r["wall_s"] for r in res)
+    summary = dict(runs=len(res), equilibrium=sum(r["status"] == 1 for r in res),
+                   gcups=cells / wall / 1e9, wall_s=wall)
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        json.dump(dict(summary=summary, results=res, args=vars(a)), open(a.out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -52,6 +52,8 @@ __all__ = [
     "sweep_instance",
     "sweep_instances",
     "warmstart_instance",
+    "paper_glass_field",
+    "case_paper",
     "T_STAR",
     "ALPHA_REAL",
 ]
@@ -294,6 +296,7 @@ class Case:
     params: Dict[str, float]
     run: Dict[str, float] = field(default_factory=dict)
     meta: Dict[str, object] = field(default_factory=dict)
+    G: Optional[np.ndarray] = None  # smooth glass field (paper mode); mask = G >= 1/2
 
     @property
     def shape(self):
@@ -425,3 +428,97 @@ def warmstart_instance(seed: int, edge: int = 96) -> Case:
     """Sweep-generator instance at a fixed cube edge (training / evaluation
     problems of the learned warm start)."""
     return sweep_instance(seed, edge=edge)
+
+
+# ---------------------------------------------------------------------------
+# Paper mode: smooth glass field, glass cap, nucleation disk (Sec. 2.1, Tab. 2)
+
+def paper_glass_field(shape_zyx, centers: np.ndarray, r: float, xi_g: float,
+                      x3_cap: Optional[float] = None) -> np.ndarray:
+    """Smooth glass indicator of Sec. 2.1 in voxel units: for each sphere
+    1/2 (1 - tanh((|x - c| - r) / (2 xi_g))) at the cell centres (plain,
+    non-periodic distances), the maximum over the spheres, and with x3_cap
+    the cap 1/2 (1 + tanh((x3 - x3_cap) / (2 xi_g))) on top (maximum of the
+    two).  Each sphere is evaluated within r + 20 xi_g + 1 of its centre,
+    where its term drops below 1e-17."""
+    n3, n2, n1 = shape_zyx
+    G = np.zeros(shape_zyx, dtype=np.float64)
+    reach = r + 20.0 * xi_g + 1.0
+    for c in np.asarray(centers, dtype=np.float64):
+        lo = [max(0, int(math.floor(c[d] - reach))) for d in range(3)]
+        hi = [min(n, int(math.ceil(c[d] + reach)) + 1) for d, n in enumerate((n1, n2, n3))]
+        if any(h_ <= l_ for l_, h_ in zip(lo, hi)):
+            continue
+        x1 = np.arange(lo[0], hi[0]) + 0.5 - c[0]
+        x2 = np.arange(lo[1], hi[1]) + 0.5 - c[1]
+        x3 = np.arange(lo[2], hi[2]) + 0.5 - c[2]
+        d = np.sqrt(x3[:, None, None] ** 2 + x2[None, :, None] ** 2 + x1[None, None, :] ** 2)
+        g = 0.5 * (1.0 - np.tanh((d - r) / (2.0 * xi_g)))
+        sub = G[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        np.maximum(sub, g, out=sub)
+    if x3_cap is not None:
+        x3 = np.arange(n3) + 0.5
+        cap = 0.5 * (1.0 + np.tanh((x3 - x3_cap) / (2.0 * xi_g)))
+        np.maximum(G, cap[:, None, None], out=G)
+    return G
+
+
+def nucleation_disk(shape_zyx) -> np.ndarray:
+    """eq. nucleation-site: 0.87 L3 < x3 < 0.97 L3 and
+    (x1 - L1/2)^2 + (x2 - L2/2)^2 < (L1/3)^2, at cell centres (voxel units);
+    phi0 = 1 there, glass cells included (Sec. 3.1: the part inside the cap
+    keeps its value and anchors the nucleus)."""
+    n3, n2, n1 = shape_zyx
+    x1 = np.arange(n1) + 0.5
+    x2 = np.arange(n2) + 0.5
+    x3 = np.arange(n3) + 0.5
+    slab = (x3 > 0.87 * n3) & (x3 < 0.97 * n3)
+    circ = (x1[None, :] - n1 / 2.0) ** 2 + (x2[:, None] - n2 / 2.0) ** 2 < (n1 / 3.0) ** 2
+    return (slab[:, None, None] & circ[None, :, :]).astype(np.float64)
+
+
+def case_paper(n3: int = 100, seed: int = 5, model: str = "coupled",
+               L3: float = 0.06, alpha: float = ALPHA_LARGE_SIGMA, dT: float = 0.0,
+               bed_fraction: float = 0.35, bed_height: float = 0.75) -> Case:
+    """Paper-mode setup (Sec. 2.1, Sec. 3.1, Tab. 2) on a synthetic bead bed.
+
+    Vessel N1 x N2 x N3 = N3/2 x N3/2 x N3 cells, h = L3/N3; bead radius
+    r = L3/20; glass-water interface thickness xi_G = L3/500; glass cap from
+    x3 = 11/12 L3; xi = h; nucleation disk of eq. nucleation-site.  The DEM
+    packing of the paper is not available: spheres are placed by random
+    sequential addition (periodic in x1, x2 and within the bed) in the bottom
+    ``bed_height`` of the vessel to a voxel solid fraction ``bed_fraction``.
+    Coupled model: T_ini = T* + 20 K, the top face (the cap) held at
+    T* - 25 K for 5 h, then at T* + 20 K (freeze/thaw step); other faces
+    insulated.  Micro-scale model ("ac"): constant supercooling dT."""
+    if n3 % 2:
+        raise ValueError("n3 must be even")
+    n1 = n2 = n3 // 2
+    rng = SplitMix64(seed)
+    r_vox = n3 / 20.0
+    n_bed = int(round(bed_height * n3))
+    centers, _ = rsa_spheres((n_bed, n2, n1), r_vox, rng, solid_fraction=bed_fraction,
+                             stall_attempts=200_000)
+    G = paper_glass_field((n3, n2, n1), centers, r_vox, n3 / 500.0, x3_cap=11.0 / 12.0 * n3)
+    mask = (G >= 0.5).astype(np.uint8)
+    phi0 = nucleation_disk((n3, n2, n1))
+    h = L3 / n3
+    p = _base_params(n1, n2, n3, h, h, alpha, model)
+    p["phi_face_mask"] = 0
+    p["gamma"] = 2.0
+    if model == "ac":
+        p["dT"] = dT
+        T0 = None
+    else:
+        p["dirichlet_faces"] = 1 << 5  # top face x3+ (the cap)
+        p["bc_kind"] = 2
+        p["bc_T0"] = T_STAR - 25.0
+        p["bc_T1"] = T_STAR + 20.0
+        p["bc_t0"] = 5 * 3600.0
+        p["bc_t1"] = 0.0
+        T0 = np.full((n3, n2, n1), T_STAR + 20.0)
+    run = dict(tol=1e-6, dt0=1e-3, dt_min=1e-12, dt_max=1e30, t_end=10 * 3600.0,
+               max_steps=10**9, eq_tol=0.0, safety=0.8)
+    return Case(f"paper_{n3}", model, mask, phi0, T0, p, run,
+                dict(seed=seed, radius_vox=r_vox, spheres=len(centers), L3=L3,
+                     bed_cells=n_bed, solid_fraction_bed=float(mask[:n_bed].mean())), G=G)

@@ -184,3 +184,101 @@ def test_simple_kernels_only_errors():
     p["model"] = "temp"
     with pytest.raises(pf.PFError):  # GradP needs a phase-field equation
         pf.Solver(p, mask, "fp64")
+
+
+# ---------------------------------------------------------------------------
+# Paper mode: smooth glass field G (pf_create_field), no face rule at glass
+
+def smooth_problem(shape, model, reaction, seed, faces=0, bc_kind=0):
+    p, _, phi, T = problem(shape, model, reaction, seed, faces=faces, bc_kind=bc_kind)
+    rng = np.random.default_rng(seed + 1000)
+    G = rng.random(shape)
+    G[rng.random(shape) < 0.3] = 0.0
+    G[rng.random(shape) < 0.15] = 1.0
+    p["phi_face_mask"] = 0
+    return p, G, phi, T
+
+
+def gpu_rhs_smooth(p, G, t, phi, T, precision="fp64"):
+    s = pf.Solver(p, None, precision, glass_field=G)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    dev = lambda a: torch.tensor(a, dtype=dt, device="cuda").contiguous()  # noqa: E731
+    th = dev(T - T_STAR)
+    out_p = torch.empty_like(th)
+    out_t = torch.empty_like(th)
+    if p["model"] == "temp":
+        s.rhs(t, None, th, out_p, out_t)
+    elif p["model"] == "coupled":
+        s.rhs(t, dev(phi), th, out_p, out_t)
+    else:
+        s.rhs(t, dev(phi), None, out_p, None)
+    s.close()
+    return out_p.cpu().numpy(), out_t.cpu().numpy()
+
+
+SMOOTH_VARIANTS = [("ac", "sigma"), ("coupled", "sigma"), ("ac", "gradp"), ("coupled", "gradp"),
+                   ("temp", "sigma")]
+
+
+@pytest.mark.parametrize("model,reaction", SMOOTH_VARIANTS)
+@pytest.mark.parametrize("shape", [(8, 8, 8), (23, 29, 37), (1, 1, 9), (17, 3, 300)])
+def test_smooth_rhs_fp64_matches_oracle(model, reaction, shape):
+    for trial, faces in enumerate((0, 1 << 5, 63)):
+        p, G, phi, T = smooth_problem(shape, model, reaction, 500 + trial, faces=faces,
+                                      bc_kind=trial % 3)
+        kp, kT = oracle_rhs(p, G, 0.3 * (trial + 1), phi, T)
+        gp, gT = gpu_rhs_smooth(p, G, 0.3 * (trial + 1), phi, T)
+        assert rel(gp, kp) <= 1e-12
+        if model != "ac":
+            assert rel(gT, kT) <= 1e-12
+
+
+@pytest.mark.parametrize("model,reaction", SMOOTH_VARIANTS)
+def test_smooth_rhs_fp32_matches_oracle(model, reaction):
+    p, G, phi, T = smooth_problem((19, 33, 41), model, reaction, 9, faces=1 << 5, bc_kind=2)
+    phi = phi.astype(np.float32).astype(np.float64)
+    T = (T - T_STAR).astype(np.float32).astype(np.float64) + T_STAR
+    G = G.astype(np.float32).astype(np.float64)
+    kp, kT = oracle_rhs(p, G, 0.5, phi, T)
+    gp, gT = gpu_rhs_smooth(p, G, 0.5, phi, T, "fp32")
+    assert rel(gp, kp) <= 2e-5
+    if model != "ac":
+        assert rel(gT, kT) <= 2e-5
+
+
+def test_paper_case_fixed_steps_fp64_matches_oracle():
+    """The paper-mode vessel (smooth beads, glass cap, anchored nucleation
+    disk, cooled cap face) at N3 = 40, coupled model, 20 fixed steps."""
+    c = pi.case_paper(40, seed=5)
+    p = dict(c.params)
+    dt, steps = 5e-3, 20
+    P = oracle.make_params(p)
+    ph_o, T_o, _ = oracle.integrate(P, c.G, oracle.make_ctl(tol=0.0), 0.0, dt, c.phi0, c.T0,
+                                    max_steps=steps)
+    s = pf.Solver(p, None, "fp64", dict(tol=0.0), glass_field=c.G)
+    s.set_state(c.phi0, c.T0 - T_STAR)
+    s.set_time(0.0, dt)
+    st = s.integrate(max_steps=steps)
+    ph, th = s.get_state()
+    d = s.diagnostics()
+    s.close()
+    assert st["steps_accepted"] == steps
+    assert rel(ph, ph_o) <= 1e-12 and rel(th, T_o - T_STAR) <= 1e-12
+    od = oracle.diagnostics(P, c.G, ph_o, T_o)
+    assert d["pore_count"] == od["pore_count"] and d["ice_count"] == od["ice_count"]
+    assert abs(d["enthalpy"] - od["enthalpy"]) <= 1e-10 * abs(od["enthalpy"])
+
+
+def test_smooth_glass_errors():
+    p, G, phi, T = smooth_problem((8, 8, 8), "ac", "sigma", 3)
+    s = pf.Solver(p, None, "fp32", glass_field=G)
+    with pytest.raises(pf.PFError):
+        s.set_vector(True)
+    s.set_state(phi.astype(np.float32))
+    with pytest.raises(pf.PFError):
+        pf.batch_integrate([s], max_steps=2)
+    s.close()
+    bad = G.copy()
+    bad[0, 0, 0] = 1.5
+    with pytest.raises(pf.PFError):
+        pf.Solver(p, None, "fp32", glass_field=bad)

@@ -1,0 +1,36 @@
+"""Micro-scale UWC experiment (paper-mode vessel at the carbon-black scale):
+the GPU run to a stationary state against the FP64 oracle run to the same
+criterion, compared on the unfrozen water content of the bottom half."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2401_01672_amd import uwc_sweep as U  # noqa: E402
+
+
+@pytest.mark.parametrize("dT", [2.0, 0.2])
+def test_uwc_run_matches_oracle(dT):
+    c = U.problem(0.12e-6, dT, n3=40)
+    gpu = U.run_one(c, budget=200000)
+    # the oracle runs the same two phases
+    P = oracle.make_params(c.params)
+    eq1 = max(U.EQ_TOL, 4.0 * c.run["lam_max"] * c.run["tol"])
+    phi_o, _, st1 = oracle.integrate(P, c.G, oracle.make_ctl(tol=c.run["tol"]), 0.0,
+                                     c.run["dt0"], c.phi0, None, max_steps=200000, eq_tol=eq1)
+    phi_o, _, st = oracle.integrate(P, c.G, oracle.make_ctl(tol=c.run["tol_eq"]), st1["t"],
+                                    st1["dt"], phi_o, None, max_steps=200000, eq_tol=U.EQ_TOL)
+    ref = U.bottom_half_uwc(c.G, phi_o)
+    assert st["status"] == oracle.EQUILIBRIUM and gpu["status"] == 1
+    assert gpu["water_cells"] == ref["water_cells"]
+    assert gpu["ice_cells"] == ref["ice_cells"]
+    # the step sequences agree up to the error estimate's roundoff
+    n_o = st1["steps_accepted"] + st1["steps_rejected"] + st["steps_accepted"] + \
+        st["steps_rejected"]
+    assert abs(gpu["attempts"] - n_o) <= max(2, n_o // 1000)

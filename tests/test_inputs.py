@@ -126,3 +126,41 @@ def test_crop_case():
     assert k.mask.shape == (10, 12, 16)
     assert np.array_equal(k.mask, c.mask[0:10, 8:20, 4:20])
     assert k.params["n1"] == 16 and k.params["n2"] == 12 and k.params["n3"] == 10
+
+
+def test_paper_glass_field_and_case():
+    shape = (20, 12, 14)
+    c = np.array([[6.0, 5.5, 7.0]])
+    G = pi.paper_glass_field(shape, c, 3.0, 0.4, x3_cap=17.0)
+    assert G.min() >= 0 and G.max() <= 1
+    # value at a cell centre at distance d from the sphere centre
+    i1, i2, i3 = 8, 5, 7
+    d = np.sqrt((i1 + 0.5 - 6.0) ** 2 + (i2 + 0.5 - 5.5) ** 2 + (i3 + 0.5 - 7.0) ** 2)
+    assert G[i3, i2, i1] == pytest.approx(0.5 * (1 - np.tanh((d - 3.0) / 0.8)), abs=1e-15)
+    # the cap: 1/2 at x3 = x3_cap, -> 1 above
+    assert G[19, 0, 0] == pytest.approx(0.5 * (1 + np.tanh((19.5 - 17.0) / 0.8)))
+    d0 = np.sqrt((0.5 - 6.0) ** 2 + (0.5 - 5.5) ** 2 + (0.5 - 7.0) ** 2)
+    assert G[0, 0, 0] == pytest.approx(0.5 * (1 - np.tanh((d0 - 3.0) / 0.8)), rel=1e-12)
+    k = pi.case_paper(40, seed=5)
+    assert k.mask.shape == (40, 20, 20) and k.G.shape == k.mask.shape
+    assert np.array_equal(k.mask, (k.G >= 0.5).astype(np.uint8))
+    assert k.params["phi_face_mask"] == 0 and k.params["dirichlet_faces"] == 1 << 5
+    # cap from 11/12 L3 up; nucleation disk inside 0.87..0.97 L3
+    x3 = np.arange(40) + 0.5
+    assert np.all(k.mask[x3 > 11 / 12 * 40 + 1] == 1)
+    z = np.nonzero(k.phi0.sum(axis=(1, 2)))[0]
+    assert (z.min() + 0.5) > 0.87 * 40 and (z.max() + 0.5) < 0.97 * 40
+
+
+def test_bottom_half_uwc_definition():
+    from paper_2401_01672_amd.uwc_sweep import bottom_half_uwc
+    G = np.zeros((4, 2, 2))
+    G[0, 0, 0] = 1.0      # glass in the bottom half
+    G[3, :, :] = 1.0      # glass in the top half (ignored)
+    phi = np.zeros((4, 2, 2))
+    phi[1, :, :] = 0.9    # 4 ice cells in the bottom half
+    phi[0, 0, 1] = 0.5    # not ice (strict phi > 1/2)
+    phi[2, :, :] = 1.0    # top half (ignored)
+    r = bottom_half_uwc(G, phi)
+    assert r["water_cells"] == 7 and r["ice_cells"] == 4
+    assert r["uwc"] == pytest.approx(3 / 7)

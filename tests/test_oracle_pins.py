@@ -505,3 +505,50 @@ def test_temp_model_far_from_melting_is_pure_conduction():
     lam_k = -4.0 / h ** 2 * np.sin(k * np.pi / (2 * n1)) ** 2
     want = 0.6 / 4.2e6 * lam_k * (T - 278.15)
     assert np.allclose(kT, want, rtol=1e-10, atol=1e-18)
+
+
+@pytest.mark.parametrize("model,reaction", [("ac", "sigma"), ("coupled", "sigma"), ("ac", "gradp"),
+                                            ("coupled", "gradp"), ("temp", "sigma")])
+def test_rhs_smooth_glass_matches_brute_force(model, reaction):
+    """Paper mode (Sec. 2.1): a smooth glass field G in [0, 1], the
+    phase-field Laplacian across every face, I_W(G) and the blends with
+    fractional G."""
+    rng = np.random.default_rng(hash((model, reaction, "smooth")) % 2**32)
+    for shape in ((3, 4, 5), (2, 3, 6)):
+        p = _tiny_params(model, shape, rng, faces=int(rng.integers(0, 64)),
+                         bc_kind=int(rng.integers(0, 3)))
+        p.update(reaction=reaction, phi_face_mask=0, gamma=1.7)
+        G = rng.random(shape)
+        G[rng.random(shape) < 0.2] = 0.0
+        G[rng.random(shape) < 0.2] = 1.0
+        phi = rng.random(shape)
+        T = 273.15 + rng.normal(0, 1.5, shape)
+        P = oracle.make_params(p)
+        t = float(rng.random() * 3)
+        if model == "temp":
+            kp, kT = oracle.rhs(P, G, t, None, T)
+        else:
+            kp, kT = oracle.rhs(P, G, t, phi, T if model == "coupled" else None)
+        bp, bT = brute.rhs(p, G, t, phi, T)
+        assert np.abs(kp - bp).max() <= 1e-13 * max(np.abs(bp).max(), 1e-300)
+        if model != "ac":
+            assert np.abs(kT - bT).max() <= 1e-13 * np.abs(bT).max()
+
+
+def test_smooth_glass_limits():
+    """Paper mode reduces to the plain Allen-Cahn operator where G = 0, and a
+    cell with G = 1 does not evolve (I_W = 0 for zeta = 2); with G in {0, 1}
+    and no face rule, the water-water part of the Laplacian is the same as
+    with it."""
+    rng = np.random.default_rng(41)
+    shape = (4, 4, 4)
+    p = _tiny_params("ac", shape, rng)
+    p["phi_face_mask"] = 0
+    G = (rng.random(shape) < 0.3).astype(float)
+    phi = rng.random(shape)
+    kp, _ = oracle.rhs(oracle.make_params(p), G, 0.0, phi)
+    assert np.all(kp[G == 1] == 0)
+    kp0, _ = oracle.rhs(oracle.make_params(p), np.zeros(shape), 0.0, phi)
+    p1 = dict(p, phi_face_mask=1)
+    kp1, _ = oracle.rhs(oracle.make_params(p1), np.zeros(shape), 0.0, phi)
+    assert np.array_equal(kp0, kp1)
