@@ -261,16 +261,20 @@ int pf_set_vector(pf_handle* h, int32_t enable);
  * autotuner off. */
 int pf_set_pair_tile(pf_handle* h, int32_t tile_index, int32_t z_chunk);
 
-/* Current configuration, out[0..7] = {schedule, passes per attempt,
+/* Current configuration, out[0..8] = {schedule, passes per attempt,
  * single-stage z_chunk, single-stage workgroups, pair tile x, pair tile y,
- * pair z_chunk, pair workgroups} (after the autotuner, if it has run). */
+ * pair z_chunk, pair workgroups, four-cell kernels (1) or one-cell (0)}
+ * (after the autotuner, if it has run; it times both kernel forms unless
+ * pf_set_vector fixed one). */
 int pf_get_config(const pf_handle* h, int32_t* out);
 
-/* Time each kernel of one attempt from the current state and step: every
- * kernel is launched reps times back to back between two HIP events on the
- * handle's stream; ms[0..4] receive the mean duration of stages S1..S5 and
- * ms[5] that of the controller.  The state, t and dt are left unchanged.
- * Synchronous. */
+/* Time each kernel of one attempt from the current state and step: the
+ * passes of an attempt run in order with a HIP event between each two (so
+ * each pass reads what the previous one has just written, as in a run),
+ * reps times after one warm-up; ms[i] receives the mean duration of pass i
+ * (S1..S5, or the three passes of the paired schedule) and ms[5] that of the
+ * controller (reps back-to-back launches on a scratch control block).  The
+ * state, t and dt are left unchanged.  Synchronous. */
 int pf_time_kernels(pf_handle* h, int32_t reps, double* ms);
 
 /* Block the host until all work issued on the handle's stream is done. */

@@ -47,6 +47,8 @@ struct pf_handle {
   DevCtl* hctl = nullptr;  // pinned host mirror
   int sched = pf::kSchedFive;
   int vec = 0;  // four-cells-per-thread stage kernels (n1 % 4 == 0)
+  int vec_fixed = 0;  // set by pf_set_vector: the autotuner keeps vec
+  int stream_nt = 0;  // non-temporal streams: working set far above the caches
   int z_chunk = 16;  // single-stage passes
   int tiles_p = 0, tiles_z = 0, nparts = 0, max_parts = 0;
   int pair_ts = 1, pair_zc = 16;  // paired passes: tile shape index, planes per column
@@ -164,6 +166,7 @@ StageArgs stage_args(const pf_handle* h, int stage) {
   a.tiles_p = h->tiles_p;
   a.tiles_z = h->tiles_z;
   a.vec = h->vec;
+  a.stream_nt = h->stream_nt;
   for (int v = 0; v < 2; ++v) {
     a.y[0][v] = h->y[0][v];
     a.y[1][v] = h->y[1][v];
@@ -349,28 +352,36 @@ int autotune(pf_handle* h) {
     *out = tot;
     return PF_OK;
   };
-  // (1) planes per column of the single-stage passes
+  // (1) planes per column of the single-stage passes, and (unless the caller
+  // fixed it) four-cell or one-cell kernels
   const int zcands[] = {1, 2, 4, 8, 16, 32};
-  int best = h->z_chunk;
+  int best = h->z_chunk, best_vec = h->vec;
   float best_ms = 1e30f;
-  for (int zc : zcands) {
-    if (zc > h->P.n3 && zc != zcands[0]) continue;
-    if (set_tiles(h, zc)) continue;
-    float ms;
-    rc = timed([&]() -> hipError_t {
-      for (int st = 1; st <= 5; ++st) {
-        StageArgs a = stage_args(h, st);
-        hipError_t e = pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream);
-        if (e != hipSuccess) return e;
+  const bool try_both = !h->vec_fixed && h->P.n1 % 4 == 0 && !simple_kernels_only(h->P, h->smooth);
+  for (int vec = 1; vec >= 0; --vec) {
+    if (!try_both && vec != h->vec) continue;
+    h->vec = vec;
+    for (int zc : zcands) {
+      if (zc > h->P.n3 && zc != zcands[0]) continue;
+      if (set_tiles(h, zc)) continue;
+      float ms;
+      rc = timed([&]() -> hipError_t {
+        for (int st = 1; st <= 5; ++st) {
+          StageArgs a = stage_args(h, st);
+          hipError_t e = pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      }, &ms);
+      if (rc) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = zc;
+        best_vec = vec;
       }
-      return hipSuccess;
-    }, &ms);
-    if (rc) return rc;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = zc;
     }
   }
+  h->vec = best_vec;
   rc = set_tiles(h, best);
   if (rc) return rc;
   // (2) tile shape and planes per column of the paired passes
@@ -451,6 +462,10 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
   h->ncell = (long long)params->n1 * params->n2 * params->n3;
   h->esize = params->precision == PF_FP64 ? 8 : 4;
   h->nvar = params->model == PF_MODEL_COUPLED ? 2 : 1;
+  // six fields per unknown; beyond twice the 256 MB last-level cache the
+  // streamed fields bypass the caches (measured: faster at 256^3, slower on
+  // cache-resident grids)
+  h->stream_nt = (double)h->ncell * h->esize * 6 * h->nvar > 512.0e6 ? 1 : 0;
   h->vec = (params->n1 % 4 == 0 && !simple_kernels_only(*params, G ? 1 : 0)) ? 1 : 0;
   h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
 
@@ -672,6 +687,7 @@ int pf_set_vector(pf_handle* h, int32_t enable) {
   if (enable && simple_kernels_only(h->P, h->smooth))
     return fail(h, PF_EINVAL, "four-cell kernels implement the SigmaP1-P AC and coupled models only");
   h->vec = enable ? 1 : 0;
+  h->vec_fixed = 1;
   return set_tiles(h, h->z_chunk);
 }
 
@@ -810,30 +826,35 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
     int rc = autotune(h);
     if (rc) return rc;
   }
-  // Each kernel is launched reps times back to back between two events, so
-  // the mean excludes the host launch latency.  The control block is set to
-  // a live attempt but the controller's bookkeeping of the state is not
-  // advanced: y[cur] is never written by a stage kernel, so the state, t and
-  // dt are unchanged (the stage buffers are scratch until the next S1).
+  // The passes of one attempt run in schedule order, an event between each
+  // two, repeated reps times (after one warm-up attempt), so every pass reads
+  // what its predecessor has just written, as in a run.  The control block is
+  // set to a live attempt but the controller does not run: y[cur] is never
+  // written by a stage kernel, so the state, t and dt are unchanged (the stage
+  // buffers are scratch until the next S1).
   DevCtl& c = *h->hctl;
   init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
   int rc = push_ctl(h);
   if (rc) return rc;
-  hipEvent_t e0, e1;
-  PF_HIP(h, hipEventCreate(&e0));
-  PF_HIP(h, hipEventCreate(&e1));
-  for (int i = 0; i < 6; ++i) ms[i] = 0.0;
   const int np = num_passes(h);
-  for (int i = 0; i < np; ++i) {
-    // passes run in schedule order, so each one reads its predecessor's output
-    PF_HIP(h, issue_pass(h, i, h->stream));  // warm-up
-    PF_HIP(h, hipEventRecord(e0, h->stream));
-    for (int r = 0; r < reps; ++r) PF_HIP(h, issue_pass(h, i, h->stream));
-    PF_HIP(h, hipEventRecord(e1, h->stream));
-    PF_HIP(h, hipEventSynchronize(e1));
-    float x = 0;
-    PF_HIP(h, hipEventElapsedTime(&x, e0, e1));
-    ms[i] = (double)x / reps;
+  hipEvent_t ev[6];
+  for (int i = 0; i <= np; ++i) PF_HIP(h, hipEventCreate(&ev[i]));
+  hipEvent_t& e0 = ev[0];
+  hipEvent_t& e1 = ev[1];
+  for (int i = 0; i < 6; ++i) ms[i] = 0.0;
+  for (int r = 0; r <= reps; ++r) {
+    PF_HIP(h, hipEventRecord(ev[0], h->stream));
+    for (int i = 0; i < np; ++i) {
+      PF_HIP(h, issue_pass(h, i, h->stream));
+      PF_HIP(h, hipEventRecord(ev[i + 1], h->stream));
+    }
+    PF_HIP(h, hipEventSynchronize(ev[np]));
+    if (r == 0) continue;  // warm-up
+    for (int i = 0; i < np; ++i) {
+      float x = 0;
+      PF_HIP(h, hipEventElapsedTime(&x, ev[i], ev[i + 1]));
+      ms[i] += (double)x / reps;
+    }
   }
   // controller, on a scratch copy of the control block
   DevCtl cc = c;
@@ -847,8 +868,7 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
   float x = 0;
   PF_HIP(h, hipEventElapsedTime(&x, e0, e1));
   ms[5] = (double)x / reps;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (int i = 0; i <= np; ++i) (void)hipEventDestroy(ev[i]);
   return PF_OK;
 }
 
@@ -1039,6 +1059,7 @@ int pf_get_config(const pf_handle* h, int32_t* out) {
   out[5] = pf::kPairTiles[tsi][1];
   out[6] = h->pair_zc;
   out[7] = h->npair;
+  out[8] = h->vec;
   return PF_OK;
 }
 

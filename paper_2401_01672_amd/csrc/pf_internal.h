@@ -31,7 +31,7 @@ struct DevCtl {
   double tol, safety, dt_min, dt_max, eq_tol;
   double eps;        // last error norm
   double maxk1;      // last max over water cells of |k1_phi|
-  double sum_phi, enthalpy, ice;  // diagnostics of the state at the last step start
+  double sum_phi, enthalpy, ice;  // unused (0): runs take them from a diagnostics pass
   double dt_used;    // step of the last attempt
   long long n_acc, n_rej, max_steps;
   int cur;           // which of the two state buffers holds y
@@ -95,6 +95,7 @@ struct StageArgs {
   int ignore_done;       // standalone RHS: ignore ctl
   int c_from_out;        // S5: C is read from the y_new slot (paired schedule)
   int vec;               // 1: four x1-cells per thread (needs n1 % 4 == 0)
+  int stream_nt;         // 1: non-temporal loads/stores of the streamed fields
   double t_fixed;        // standalone RHS time
 };
 
@@ -129,7 +130,7 @@ constexpr int kSchedFive = 0;    // S1..S5, one pass each
 constexpr int kSchedPaired = 1;  // (S1+S2), (S3+S4), S5
 
 // Partial-reduction slots per workgroup.
-constexpr int kPartS1 = 4;  // max |k1_phi| (water), sum phi (water), enthalpy sum, ice count
+constexpr int kPartS1 = 4;  // max |k1_phi| (water); slots 1..3 unused (0)
 constexpr int kPartS5 = 1;  // max |E|
 
 }  // namespace pf

@@ -28,7 +28,8 @@
 //   S4: k4 = F(t + dt/2, Y4);    Y5 = y + dt (k1/2 - 3 k3/2 + 2 k4),
 //                                P  = y + dt (k1 + 4 k4)/6,  C = dt (2 k1 - 9 k3 + 8 k4)/30
 //   S5: k5 = F(t + dt, Y5);      y_new = P + dt k5/6,        E = C - dt k5/30
-// S1 also reduces the diagnostics of y; S5 reduces max |E| in FP64.
+// S1 also reduces max over water cells of |k1_phi| (the equilibrium measure);
+// S5 reduces max |E| in FP64.
 #include <float.h>
 #include <hip/hip_cooperative_groups.h>
 #include <math.h>
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
   }
   const R rdt = R(dt);
 
-  double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
+  double red0 = 0.0;
   if (active) {
     const int i1 = p % m.n1;
     const int i2 = p / m.n1;
@@ -461,24 +462,11 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
           k1T[n] = kt;
           oT[n] = tc + rdt * (R(1.0 / 3.0) * kt);
         }
+        // equilibrium measure: max over water cells of |k1_phi| (the Temp
+        // model has no phase-field equation and reports 0)
         const bool water = !(code & kGlassBit);
-        double dpc = (double)pc;
-        double thc_d = kCoupled ? (double)tc : -m.dT;
-        if (MODEL == PF_MODEL_TEMP) {
-          thc_d = (double)pc;
-          const R iw = SMOOTH ? fmax(R(0), R(1) - R(m.zeta) * Gc) : (water ? R(1) : R(m.iw_glass));
-          dpc = (double)temp_phi(m, pc, iw);
-        }
-        const double Gd = (double)Gc;
-        const double rc = SMOOTH ? Gd * m.rcG + (1.0 - Gd) * (m.rcL + dpc * m.drc)
-                                 : (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
-        if (water) {
-          // no phase-field equation in the Temp model: no equilibrium measure
-          if (MODEL != PF_MODEL_TEMP) red0 = dmax_nf(red0, fabs((double)kp));
-          red1 += dpc;
-          red3 += (dpc > 0.5) ? 1.0 : 0.0;
-        }
-        red2 += rc * thc_d - m.Lv * dpc;
+        if (water && MODEL != PF_MODEL_TEMP) red0 = dmax_nf(red0, fabs((double)kp));
+        (void)Gc;
       } else if (STAGE == 2) {
         const R k1p = k1P[n];
         oP[n] = pc + rdt * (R(1.0 / 6.0) * (kp - k1p));
@@ -531,15 +519,17 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
     }
   }
   if (STAGE == 1) {
-    double v[4] = {red0, red1, red2, red3};
-    const int ops[4] = {1, 0, 0, 0};
-    block_reduce<4>(v, ops, smem);
+    // the sums of the state (phi, enthalpy, ice) are not needed per step:
+    // runs report them from a diagnostics pass over the final state
+    double v[1] = {red0};
+    const int ops[1] = {1};
+    block_reduce<1>(v, ops, smem);
     if (threadIdx.x == 0) {
       double* o = a.part + (size_t)blockIdx.x * kPartS1;
       o[0] = v[0];
-      o[1] = v[1];
-      o[2] = v[2];
-      o[3] = v[3];
+      o[1] = 0.0;
+      o[2] = 0.0;
+      o[3] = 0.0;
     }
   } else if (STAGE == 5) {
     double v[1] = {red0};
@@ -655,7 +645,7 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
 // steps_per_launch attempts and returns; every workgroup leaves the loop at
 // the same point (the exit test reads the control blocks after a barrier).
 
-template <typename R, int MODEL, int STAGE>
+template <typename R, int MODEL, int STAGE, bool NT = false>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile, const int slot,
                                             double* smem);
 
@@ -924,14 +914,67 @@ __device__ __forceinline__ Quad<R> ldq(const R* base, uint32_t idx) {
   return q;
 }
 
+// Streaming forms: every output of a pass, and every input read only at the
+// cell itself (not a stencil neighbour), is touched once per pass; on grids
+// far larger than the caches they are loaded and stored non-temporally and
+// leave the L2 to the stencil rows that neighbouring workgroups re-read (on
+// cache-resident grids the plain forms are faster).
 template <typename R>
-__device__ __forceinline__ void stq(R* base, uint32_t idx, const Quad<R>& q) {
+__device__ __forceinline__ Quad<R> ldq_nt(const R* base, uint32_t idx) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  Quad<R> q;
+  if constexpr (sizeof(R) == 4) {
+    const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4*>(base + idx));
+    q.v[0] = t.x;
+    q.v[1] = t.y;
+    q.v[2] = t.z;
+    q.v[3] = t.w;
+  } else {
+    const d2 t0 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(base + idx));
+    const d2 t1 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(base + idx + 2));
+    q.v[0] = t0.x;
+    q.v[1] = t0.y;
+    q.v[2] = t1.x;
+    q.v[3] = t1.y;
+  }
+  return q;
+}
+
+template <typename R>
+__device__ __forceinline__ void stq_plain(R* base, uint32_t idx, const Quad<R>& q) {
   if constexpr (sizeof(R) == 4) {
     *reinterpret_cast<float4*>(base + idx) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
   } else {
     *reinterpret_cast<double2*>(base + idx) = make_double2(q.v[0], q.v[1]);
     *reinterpret_cast<double2*>(base + idx + 2) = make_double2(q.v[2], q.v[3]);
   }
+}
+
+template <typename R>
+__device__ __forceinline__ void stq_nt(R* base, uint32_t idx, const Quad<R>& q) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  if constexpr (sizeof(R) == 4) {
+    const f4 t = {q.v[0], q.v[1], q.v[2], q.v[3]};
+    __builtin_nontemporal_store(t, reinterpret_cast<f4*>(base + idx));
+  } else {
+    const d2 t0 = {q.v[0], q.v[1]}, t1 = {q.v[2], q.v[3]};
+    __builtin_nontemporal_store(t0, reinterpret_cast<d2*>(base + idx));
+    __builtin_nontemporal_store(t1, reinterpret_cast<d2*>(base + idx + 2));
+  }
+}
+
+template <bool NT, typename R>
+__device__ __forceinline__ Quad<R> ldq_s(const R* base, uint32_t idx) {
+  if constexpr (NT) return ldq_nt(base, idx);
+  else return ldq(base, idx);
+}
+
+template <bool NT, typename R>
+__device__ __forceinline__ void stq_s(R* base, uint32_t idx, const Quad<R>& q) {
+  if constexpr (NT) stq_nt(base, idx, q);
+  else stq_plain(base, idx, q);
 }
 
 template <typename R>
@@ -943,7 +986,7 @@ __device__ __forceinline__ R shfl_down1(R v) {
   return __shfl_down(v, 1, 64);
 }
 
-template <typename R, int MODEL, int STAGE>
+template <typename R, int MODEL, int STAGE, bool NT>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
                                             const int slot, double* smem) {
   const ModelConst& m = a.mc;
@@ -987,7 +1030,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   }
   const R rdt = R(dt);
 
-  double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
+  double red0 = 0.0;
   // the quad's position (n1 % 4 == 0: all four cells share i2)
   const uint32_t i1 = active ? p % (uint32_t)m.n1 : 0u;
   const uint32_t i2 = active ? p / (uint32_t)m.n1 : 0u;
@@ -1063,45 +1106,34 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
                                 inb, dirf, thD, kp, kt);
         kq[0].v[k] = kp;
         kq[1].v[k] = kt;
-        if (STAGE == 1) {
-          const bool water = !(code & kGlassBit);
-          const double dpc = (double)cc[0].v[k];
-          const double thc_d = kCoupled ? (double)cc[1].v[k] : -m.dT;
-          const double rc = (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
-          if (water) {
-            red0 = dmax_nf(red0, fabs((double)kp));
-            red1 += dpc;
-            red3 += (dpc > 0.5) ? 1.0 : 0.0;
-          }
-          red2 += rc * thc_d - m.Lv * dpc;
-        }
+        if (STAGE == 1 && !(code & kGlassBit)) red0 = dmax_nf(red0, fabs((double)kp));
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const Quad<R>& kk = kq[v];
         Quad<R> o;
         if (STAGE == 0) {
-          stq(out[v], n, kk);
+          stq_s<NT>(out[v], n, kk);
         } else if (STAGE == 1) {
-          stq(k1[v], n, kk);
+          stq_s<NT>(k1[v], n, kk);
 #pragma unroll
           for (int k = 0; k < 4; ++k) o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 3.0) * kk.v[k]);
-          stq(out[v], n, o);
+          stq_s<NT>(out[v], n, o);
         } else if (STAGE == 2) {
-          const Quad<R> q1 = ldq(k1[v], n);
+          const Quad<R> q1 = ldq_s<NT>(k1[v], n);
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 6.0) * (kk.v[k] - q1.v[k]));
-          stq(out[v], n, o);
+          stq_s<NT>(out[v], n, o);
         } else if (STAGE == 3) {
-          const Quad<R> q1 = ldq(k1[v], n), y0 = ldq(yv[v], n);
-          stq(k3[v], n, kk);
+          const Quad<R> q1 = ldq_s<NT>(k1[v], n), y0 = ldq_s<NT>(yv[v], n);
+          stq_s<NT>(k3[v], n, kk);
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             o.v[k] = y0.v[k] + rdt * (R(0.125) * (q1.v[k] + R(3) * kk.v[k]));
-          stq(out[v], n, o);
+          stq_s<NT>(out[v], n, o);
         } else if (STAGE == 4) {
-          const Quad<R> q1 = ldq(k1[v], n), q3 = ldq(k3[v], n), y0 = ldq(yv[v], n);
+          const Quad<R> q1 = ldq_s<NT>(k1[v], n), q3 = ldq_s<NT>(k3[v], n), y0 = ldq_s<NT>(yv[v], n);
           Quad<R> P, Cc;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
@@ -1109,18 +1141,18 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
             P.v[k] = y0.v[k] + rdt * (R(1.0 / 6.0) * (q1.v[k] + R(4) * kk.v[k]));
             Cc.v[k] = rdt * (R(1.0 / 30.0) * (R(2) * q1.v[k] - R(9) * q3.v[k] + R(8) * kk.v[k]));
           }
-          stq(out[v], n, o);
-          stq(k1[v], n, P);
-          stq(k3[v], n, Cc);
+          stq_s<NT>(out[v], n, o);
+          stq_s<NT>(k1[v], n, P);
+          stq_s<NT>(k3[v], n, Cc);
         } else if (STAGE == 5) {
-          const Quad<R> P = ldq(k1[v], n), Cc = ldq(k3[v], n);
+          const Quad<R> P = ldq_s<NT>(k1[v], n), Cc = ldq_s<NT>(k3[v], n);
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             o.v[k] = P.v[k] + rdt * (R(1.0 / 6.0) * kk.v[k]);
             const double e = (double)Cc.v[k] - dt * ((1.0 / 30.0) * (double)kk.v[k]);
             red0 = dmax_nf(red0, fabs(e));
           }
-          stq(out[v], n, o);
+          stq_s<NT>(out[v], n, o);
         }
       }
 #pragma unroll
@@ -1131,11 +1163,13 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     }
   }
   if (STAGE == 1) {
-    double v[4] = {red0, red1, red2, red3};
-    const int ops[4] = {1, 0, 0, 0};
-    block_reduce<4>(v, ops, smem);
+    // the sums of the state (phi, enthalpy, ice) are not needed per step:
+    // runs report them from a diagnostics pass over the final state
+    double v[1] = {red0};
+    const int ops[1] = {1};
+    block_reduce<1>(v, ops, smem);
     if (threadIdx.x == 0)
-      for (int i = 0; i < 4; ++i) a.part[(size_t)slot * kPartS1 + i] = v[i];
+      for (int i = 0; i < 4; ++i) a.part[(size_t)slot * kPartS1 + i] = i == 0 ? v[0] : 0.0;
     __syncthreads();  // smem is reused by the next tile of a persistent block
   } else if (STAGE == 5) {
     double v[1] = {red0};
@@ -1146,10 +1180,10 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   }
 }
 
-template <typename R, int MODEL, int STAGE>
+template <typename R, int MODEL, int STAGE, bool NT = false>
 __global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
-  stage4_tile<R, MODEL, STAGE>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem);
+  stage4_tile<R, MODEL, STAGE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1261,7 +1295,7 @@ __global__ __launch_bounds__(TX* TY) void pair_kernel(PairArgs a) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) c_k[v] = c_y[v] = c_k1[v] = p_k[v] = p_y[v] = p_k1[v] = R(0);
 
-  double red0 = 0.0, red1 = 0.0, red2 = 0.0, red3 = 0.0;
+  double red0 = 0.0;
 
   auto load_plane = [&](int p) {
     const int s = ((p % 3) + 3) % 3;
@@ -1349,19 +1383,10 @@ __global__ __launch_bounds__(TX* TY) void pair_kernel(PairArgs a) {
         if (mine) {
           c_code = code;
           if (FIRST == 1 && j >= z0 && j < z1) {
-            // k1 to HBM and the diagnostics of the state (own planes only)
+            // k1 to HBM and the equilibrium measure (own planes only)
 #pragma unroll
             for (int v = 0; v < NV; ++v) k1g[v][n] = kk[v];
-            const bool water = !(code & kGlassBit);
-            const double dpc = (double)ctr[0];
-            const double thc_d = kCoupled ? (double)ctr[1] : -m.dT;
-            const double rc = (code & kGlassBit) ? m.rcG : m.rcL + dpc * m.drc;
-            if (water) {
-              red0 = dmax_nf(red0, fabs((double)kp));
-              red1 += dpc;
-              red3 += (dpc > 0.5) ? 1.0 : 0.0;
-            }
-            red2 += rc * thc_d - m.Lv * dpc;
+            if (!(code & kGlassBit)) red0 = dmax_nf(red0, fabs((double)kp));
           }
         }
       }
@@ -1421,7 +1446,7 @@ __global__ __launch_bounds__(TX* TY) void pair_kernel(PairArgs a) {
     // wavefront xor trees, then the waves in order (fixed order: bitwise
     // reproducible)
     constexpr int NW = NT / 64;
-    double v[4] = {red0, red1, red2, red3};
+    double v[4] = {red0, 0.0, 0.0, 0.0};  // per-step sums of the state are not needed
     const int ops[4] = {1, 0, 0, 0};
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -1495,15 +1520,23 @@ static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
   if (a.mc.reaction == PF_REACT_GRADP || a.mc.smooth) return launch_simple_t<R, MODEL>(stage, a, s);
   if (a.vec) {
+#define PF_S4(S)                                                                       \
+  do {                                                                                 \
+    if (a.stream_nt)                                                                   \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true>), grid, block, 0, s, a);    \
+    else                                                                               \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false>), grid, block, 0, s, a);   \
+  } while (0)
     switch (stage) {
-      case 0: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 0>), grid, block, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 1>), grid, block, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 2>), grid, block, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 3>), grid, block, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 4>), grid, block, 0, s, a); break;
-      case 5: hipLaunchKernelGGL((stage4_kernel<R, MODEL, 5>), grid, block, 0, s, a); break;
+      case 0: PF_S4(0); break;
+      case 1: PF_S4(1); break;
+      case 2: PF_S4(2); break;
+      case 3: PF_S4(3); break;
+      case 4: PF_S4(4); break;
+      case 5: PF_S4(5); break;
       default: return hipErrorInvalidValue;
     }
+#undef PF_S4
     return hipGetLastError();
   }
   switch (stage) {
