@@ -279,7 +279,7 @@ def run_gpu(args, wl):
     for i in range(npass):
         gbs = sb[i] * ncell / (ms[i] * 1e-3) / 1e9
         kl = PASS_KERNELS[sched][i]
-        if wl.get("kernel") == "stage_kernel":
+        if not cfg.get("four_cell", True):
             kl = kl.replace("stage4_kernel", "stage_kernel")
         per_pass.append(dict(pass_=PASS_NAMES[sched][i], kernel=kl,
                              ms=round(ms[i], 5), bytes_per_cell=sb[i], gbs=round(gbs, 1)))

@@ -367,3 +367,36 @@ def test_rerun_is_bitwise_deterministic():
         s.close()
     assert np.array_equal(outs[0][0], outs[1][0])
     assert outs[0][1:] == outs[1][1:]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degenerate_geometries(precision):
+    """All glass: nothing evolves, no water cells, equilibrium at once.
+    All water with phi = 0: a stationary state of the phase equation
+    (phi = 0 is a fixed point of the reaction term).  Coupled, uniform theta
+    with insulated faces: stationary as well."""
+    shape = (12, 8, 16)
+    dt = np.float64 if precision == "fp64" else np.float32
+    p, _, _, _ = rand_problem(shape, "ac", 3)
+    s = pf.Solver(p, np.ones(shape, np.uint8), precision, dict(tol=1e-6))
+    s.set_state(np.zeros(shape, dt))
+    s.set_time(0.0, 1e-3)
+    st = s.integrate(max_steps=10, eq_tol=1e-6)
+    assert st["status"] == pf.PF_EQUILIBRIUM and st["steps_accepted"] == 0
+    assert st["pore_count"] == 0 and st["ice_count"] == 0 and st["uwc"] == 0.0
+    s.close()
+    s = pf.Solver(p, np.zeros(shape, np.uint8), precision, dict(tol=1e-6))
+    s.set_state(np.zeros(shape, dt))
+    s.set_time(0.0, 1e-3)
+    st = s.integrate(max_steps=10, eq_tol=1e-6)
+    assert st["status"] == pf.PF_EQUILIBRIUM and st["uwc"] == 1.0
+    s.close()
+    pc, mask, _, _ = rand_problem(shape, "coupled", 4)
+    s = pf.Solver(pc, mask, precision, dict(tol=0.0))
+    th = np.full(shape, 1.5, dt)
+    s.set_state(np.zeros(shape, dt), th)
+    s.set_time(0.0, 1e-3)
+    s.integrate(max_steps=5)
+    ph, th2 = s.get_state()
+    assert np.all(ph == 0) and np.array_equal(th2, th)
+    s.close()
