@@ -354,7 +354,7 @@ def main():
                     help="attempt budget per run of the warm-start workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
+        print(json.dumps(dict(error="the benchmark runs on one GPU only (the path is single-device); --gpus must be 1")))
         sys.exit(2)
     wl = WORKLOADS[args.workload]
     if args.workload.startswith("warmstart"):
