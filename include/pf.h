@@ -218,10 +218,14 @@ typedef struct {
   int32_t mode;           /* 1: persistent cooperative kernel: one launch
                                 per poll interval, grid barriers between
                                 stages;
-                             2 (default): one launch per stage over all
-                                instances, the poll interval's attempts
-                                captured once and replayed as a HIP graph  */
-  int32_t z_chunk;        /* planes per work item (0: 4)                   */
+                             2 (default): one launch per stage over the
+                                instances still running, the poll
+                                interval's attempts captured as a HIP graph
+                                and replayed; the work table and the graph
+                                are rebuilt when instances finish          */
+  int32_t z_chunk;        /* planes per work item (0: 4 while the running
+                             instances make at least 1024 items, halved
+                             down to 1 below that)                         */
   int32_t steps_per_poll; /* attempts between host checks (0: 32)          */
   int32_t pad;
 } pf_batch_options;

@@ -872,6 +872,16 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
   return PF_OK;
 }
 
+// Items of the batched sweep over the instances in act at z planes per item.
+static long long batch_items_at(pf_handle* const* inst, const std::vector<int>& act, int z) {
+  long long total = 0;
+  for (int i : act) {
+    int tp, tz;
+    total += pf::grid_blocks(inst[i]->mc, z < inst[i]->P.n3 ? z : inst[i]->P.n3, 1, &tp, &tz);
+  }
+  return total;
+}
+
 int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t max_steps,
                        double eq_tol, pf_run_stats* out, uintptr_t stream,
                        const pf_batch_options* opts) {
@@ -892,19 +902,18 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   }
   pf_handle* h0 = inst[0];
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : h0->own_stream;
-  // planes per work item (small: fine-grained load balance) and attempts
-  // between host checks of the control blocks
-  const int kBatchZ = (opts && opts->z_chunk) ? opts->z_chunk : 4;
+  // Planes per work item.  Fixed when given; otherwise 4 while the running
+  // instances make at least kMinItems items, halved (down to 1) when fewer
+  // remain, so that a few small instances still spread over the whole chip.
+  const int z_fixed = (opts && opts->z_chunk) ? opts->z_chunk : 0;
+  const int kBatchZ = 4;
+  const long long kMinItems = 1024;
   const int kStepsPerLaunch = (opts && opts->steps_per_poll) ? opts->steps_per_poll : 32;
-  std::vector<pf::BatchDesc> desc(n);
-  std::vector<int> item_inst;
-  int item0 = 0;
+  std::vector<int> act;
   for (int i = 0; i < n; ++i) {
     pf_handle* h = inst[i];
     PF_HIP(h, hipStreamSynchronize(h->stream));
     h->vec = 1;
-    int rc = set_tiles(h, kBatchZ);
-    if (rc) return rc;
     DevCtl& c = *h->hctl;
     init_ctl(h, c, t_end, max_steps, eq_tol);
     if (h->t >= t_end) {
@@ -915,81 +924,118 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       c.status = PF_MAXSTEPS;
     }
     PF_HIP(h, hipMemcpyAsync(h->ctl, h->hctl, sizeof(DevCtl), hipMemcpyHostToDevice, s));
-    pf::BatchDesc& d = desc[i];
-    memset(&d, 0, sizeof(d));
-    for (int st = 1; st <= 5; ++st) d.st[st - 1] = stage_args(h, st);
-    d.p1 = h->part1;
-    d.p5 = h->part5;
-    d.ntiles = h->nparts;
-    d.item0 = item0;
-    d.h3 = h->mc.h3;
-    for (int k = 0; k < h->nparts; ++k) item_inst.push_back(i);
-    item0 += h->nparts;
+    if (!c.done) act.push_back(i);
   }
-  const int nitems = item0;
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  const long long max_items = batch_items_at(inst, all, z_fixed ? z_fixed : 1);
+  if (max_items > (1LL << 30)) return fail(h0, PF_EINVAL, "batch: too many work items");
+  std::vector<pf::BatchDesc> desc(n);
+  memset(desc.data(), 0, sizeof(pf::BatchDesc) * n);
+  std::vector<int2> items;
   pf::BatchDesc* ddesc = nullptr;
-  int* ditem = nullptr;
+  int2* ditems = nullptr;
+  int* dact = nullptr;
   unsigned* dbar = nullptr;  // [0] arrivals, [1] generation, [2] barrier-overrun flag
   if (hipMalloc(&ddesc, sizeof(pf::BatchDesc) * n) != hipSuccess ||
-      hipMalloc(&ditem, sizeof(int) * nitems) != hipSuccess ||
+      hipMalloc(&ditems, sizeof(int2) * (size_t)(max_items > 0 ? max_items : 1)) != hipSuccess ||
+      hipMalloc(&dact, sizeof(int) * n) != hipSuccess ||
       hipMalloc(&dbar, 4 * sizeof(unsigned)) != hipSuccess) {
     (void)hipFree(ddesc);
-    (void)hipFree(ditem);
+    (void)hipFree(ditems);
+    (void)hipFree(dact);
     return fail(h0, PF_ENOMEM, "batch: descriptor allocation failed");
   }
+  hipGraphExec_t gexec = nullptr;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
     (void)hipFree(ddesc);
-    (void)hipFree(ditem);
+    (void)hipFree(ditems);
+    (void)hipFree(dact);
     (void)hipFree(dbar);
   };
   unsigned hbar[4] = {0, 0, 0, 0};
-  if (hipMemcpyAsync(ddesc, desc.data(), sizeof(pf::BatchDesc) * n, hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipMemcpyAsync(ditem, item_inst.data(), sizeof(int) * nitems, hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipMemcpyAsync(dbar, hbar, sizeof(hbar), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess) {
+  if (hipMemcpyAsync(dbar, hbar, sizeof(hbar), hipMemcpyHostToDevice, s) != hipSuccess) {
     cleanup();
-    return fail(h0, PF_EHIP, "batch: descriptor upload failed");
+    return fail(h0, PF_EHIP, "batch: barrier upload failed");
   }
-  int grid = pf::batch_max_blocks(h0->P.precision, h0->P.model);
-  if (grid < 1) {
-    cleanup();
-    return fail(h0, PF_EHIP, "batch: occupancy query failed");
-  }
-  if (grid > nitems) grid = nitems;
-  hipGraphExec_t gexec = nullptr;
-  if (mode == 2) {
-    // capture kStepsPerLaunch attempts of all instances once, replay below
+  // Tiles, descriptors and items of the running instances (act); the
+  // multi-launch form also captures kStepsPerLaunch attempts over them.
+  auto build = [&]() -> int {
+    int z = z_fixed ? z_fixed : kBatchZ;
+    if (!z_fixed)
+      while (z > 1 && batch_items_at(inst, act, z) < kMinItems) z >>= 1;
+    items.clear();
+    for (int i : act) {
+      pf_handle* h = inst[i];
+      int rc = set_tiles(h, z);
+      if (rc) return rc;
+      pf::BatchDesc& d = desc[i];
+      for (int st = 1; st <= 5; ++st) d.st[st - 1] = stage_args(h, st);
+      d.p1 = h->part1;
+      d.p5 = h->part5;
+      d.ntiles = h->nparts;
+      d.h3 = h->mc.h3;
+      for (int k = 0; k < h->nparts; ++k) items.push_back(make_int2(i, k));
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    if (hipMemcpyAsync(ddesc, desc.data(), sizeof(pf::BatchDesc) * n, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(ditems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipMemcpyAsync(dact, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(h0, PF_EHIP, "batch: descriptor upload failed");
+    if (mode != 2) return PF_OK;
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
-      e = pf::launch_batch_step(h0->P.precision, h0->P.model, ddesc, ditem, nitems, n, s);
+      e = pf::launch_batch_step(h0->P.precision, h0->P.model, ddesc, ditems, (int)items.size(),
+                                dact, (int)act.size(), s);
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e == hipSuccess && e2 == hipSuccess) {
       e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
     }
     if (e != hipSuccess || e2 != hipSuccess) {
-      cleanup();
+      gexec = nullptr;
       return fail(h0, PF_EHIP, "batch: graph capture failed");
     }
+    return PF_OK;
+  };
+  int grid = 0;
+  if (!act.empty()) {
+    // the persistent form keeps every instance in its table (finished ones
+    // are skipped inside the kernel)
+    if (mode == 1) act = all;
+    int rc = build();
+    if (rc) {
+      cleanup();
+      return rc;
+    }
+    if (mode == 1) {
+      grid = pf::batch_max_blocks(h0->P.precision, h0->P.model);
+      if (grid < 1) {
+        cleanup();
+        return fail(h0, PF_EHIP, "batch: occupancy query failed");
+      }
+      if (grid > (int)items.size()) grid = (int)items.size();
+    }
   }
-  for (;;) {
-    bool any = false;
-    for (int i = 0; i < n; ++i) any |= !inst[i]->hctl->done;
-    if (!any) break;
-    hipError_t e = mode == 1 ? pf::launch_batch(h0->P.precision, h0->P.model, ddesc, ditem,
-                                                nitems, n, kStepsPerLaunch, grid, dbar,
-                                                dbar + 2, s)
+  while (!act.empty()) {
+    hipError_t e = mode == 1 ? pf::launch_batch(h0->P.precision, h0->P.model, ddesc,
+                                                ditems, (int)items.size(), n, kStepsPerLaunch,
+                                                grid, dbar, dbar + 2, s)
                              : hipGraphLaunch(gexec, s);
     if (e != hipSuccess) {
-      if (gexec) (void)hipGraphExecDestroy(gexec);
       cleanup();
       return fail(h0, PF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
-    for (int i = 0; i < n; ++i)
+    for (int i : act)
       if (hipMemcpyAsync(inst[i]->hctl, inst[i]->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s) !=
           hipSuccess) {
         cleanup();
@@ -1001,12 +1047,21 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       return fail(h0, PF_EHIP, "batch: synchronize failed");
     }
     if (hbar[2]) {
-      if (gexec) (void)hipGraphExecDestroy(gexec);
       cleanup();
       return fail(h0, PF_EHIP, "batch: a grid barrier wait overran its bound");
     }
+    std::vector<int> still;
+    for (int i : act)
+      if (!inst[i]->hctl->done) still.push_back(i);
+    if (still.size() == act.size()) continue;
+    act.swap(still);
+    if (act.empty() || mode == 1) continue;
+    int rc = build();  // fewer instances: smaller grids, maybe thinner tiles
+    if (rc) {
+      cleanup();
+      return rc;
+    }
   }
-  if (gexec) (void)hipGraphExecDestroy(gexec);
   cleanup();
   const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
   int ret = PF_OK;

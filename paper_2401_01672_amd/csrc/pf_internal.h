@@ -121,7 +121,6 @@ struct BatchDesc {
   const double* p1;     // S1 partials of the instance (ntiles x kPartS1)
   const double* p5;     // S5 partials (ntiles)
   int ntiles;           // work items (stage-pass tiles) of the instance
-  int item0;            // first global item index of the instance
   double h3;
 };
 
@@ -155,11 +154,13 @@ hipError_t launch_pair(int precision, int model, int first, int ts, const PairAr
 // batched sweep: cooperative persistent launch; grid_blocks <= batch_max_blocks()
 // bar: two zeroed unsigned counters (grid barrier); err: set to 1 when a
 // barrier wait overran its bound
-hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int* item_inst,
+// items[i] = (instance, tile); the controllers run for desc[0 .. ninst)
+hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int2* items,
                         int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
                         unsigned* err, hipStream_t s);
 int batch_max_blocks(int precision, int model);
-// batched sweep, multi-launch form: one attempt = 5 stage launches + 1 controller
-hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc,
-                             const int* item_inst, int nitems, int ninst, hipStream_t s);
+// batched sweep, multi-launch form: one attempt = 5 stage launches over the
+// nitems items + 1 controller launch over the ninst instances of inst_list
+hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
+                             int nitems, const int* inst_list, int ninst, hipStream_t s);
 }  // namespace pf

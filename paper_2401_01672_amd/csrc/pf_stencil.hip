@@ -636,14 +636,15 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
 // ---------------------------------------------------------------------------
 // Batched sweep: many independent grids (instances) advanced by one
 // persistent cooperative kernel.  Work items are (instance, tile) pairs of
-// the four-cell stage passes; all items of one stage are processed (strided
-// over the workgroups), then a grid-wide barrier, then the next stage; after
-// S5 one workgroup per instance runs that instance's controller on its own
-// control block (own t, dt, status), then a barrier.  Instances whose
-// control block says done are skipped, so finished instances cost nothing
-// and the remaining ones share the whole GPU.  A launch performs at most
-// steps_per_launch attempts and returns; every workgroup leaves the loop at
-// the same point (the exit test reads the control blocks after a barrier).
+// the four-cell stage passes (items[i].x = instance, .y = tile); all items of
+// one stage are processed (strided over the workgroups), then a grid-wide
+// barrier, then the next stage; after S5 one workgroup per instance runs that
+// instance's controller on its own control block (own t, dt, status), then a
+// barrier.  Instances whose control block says done are skipped, so finished
+// instances cost nothing and the remaining ones share the whole GPU.  A launch
+// performs at most steps_per_launch attempts and returns; every workgroup
+// leaves the loop at the same point (the exit test reads the control blocks
+// after a barrier).
 
 template <typename R, int MODEL, int STAGE, bool NT = false>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile, const int slot,
@@ -685,7 +686,7 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, un
 
 template <typename R, int MODEL>
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
-                                                       const int* item_inst, int nitems,
+                                                       const int2* items, int nitems,
                                                        int ninst, int steps_per_launch,
                                                        unsigned* bar, unsigned* err) {
   __shared__ double smem[8 * kWaves];
@@ -697,9 +698,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
 #pragma unroll 1
     for (int stage = 1; stage <= 5; ++stage) {
       for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const int inst = item_inst[item];
-        const BatchDesc& d = desc[inst];
-        const int tile = item - d.item0;
+        const int2 it = items[item];
+        const BatchDesc& d = desc[it.x];
+        const int tile = it.y;
         switch (stage) {
           case 1: stage4_tile<R, MODEL, 1>(d.st[0], tile, tile, smem); break;
           case 2: stage4_tile<R, MODEL, 2>(d.st[1], tile, tile, smem); break;
@@ -718,74 +719,77 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
   }
 }
 
-// Multi-launch form of the batched sweep: one launch per stage over all
-// (instance, tile) items (one item per workgroup, XCD-aware order), one
-// controller launch with one workgroup per instance; the host captures a run
-// of attempts into a HIP graph.  Same per-cell arithmetic as batch_kernel.
+// Multi-launch form of the batched sweep: one launch per stage over the
+// (instance, tile) items of the instances still running (one item per
+// workgroup, XCD-aware order), one controller launch with one workgroup per
+// listed instance; the host captures a run of attempts into a HIP graph and
+// rebuilds the item table (and the graph) when instances finish.  Same
+// per-cell arithmetic as batch_kernel.
 template <typename R, int MODEL, int STAGE>
 __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchDesc* desc,
-                                                             const int* item_inst) {
+                                                             const int2* items) {
   __shared__ double smem[8 * kWaves];
-  const int item = xcd_tile(blockIdx.x, gridDim.x);
-  const BatchDesc& d = desc[item_inst[item]];
-  const int tile = item - d.item0;
-  stage4_tile<R, MODEL, STAGE>(d.st[STAGE - 1], tile, tile, smem);
+  const int2 it = items[xcd_tile(blockIdx.x, gridDim.x)];
+  stage4_tile<R, MODEL, STAGE>(desc[it.x].st[STAGE - 1], it.y, it.y, smem);
 }
 
-__global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc) {
+__global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc,
+                                                        const int* inst_list) {
   __shared__ double smem[8 * kWaves];
-  const BatchDesc& d = desc[blockIdx.x];
+  const BatchDesc& d = desc[inst_list[blockIdx.x]];
   controller_body(d.st[0].ctl, d.p1, d.ntiles, d.p5, d.ntiles, d.h3, smem);
 }
 
 template <typename R, int MODEL>
-static hipError_t launch_batch_step_t(const BatchDesc* desc, const int* item_inst, int nitems,
-                                      int ninst, hipStream_t s) {
+static hipError_t launch_batch_step_t(const BatchDesc* desc, const int2* items, int nitems,
+                                      const int* inst_list, int ninst, hipStream_t s) {
   const dim3 g((unsigned)nitems), b(kBlock);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1>), g, b, 0, s, desc, item_inst);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2>), g, b, 0, s, desc, item_inst);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3>), g, b, 0, s, desc, item_inst);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4>), g, b, 0, s, desc, item_inst);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5>), g, b, 0, s, desc, item_inst);
-  hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1>), g, b, 0, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2>), g, b, 0, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3>), g, b, 0, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4>), g, b, 0, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5>), g, b, 0, s, desc, items);
+  hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc, inst_list);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc,
-                             const int* item_inst, int nitems, int ninst, hipStream_t s) {
+hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
+                             int nitems, const int* inst_list, int ninst, hipStream_t s) {
   if (precision == PF_FP64)
     return model == PF_MODEL_AC
-               ? launch_batch_step_t<double, PF_MODEL_AC>(desc, item_inst, nitems, ninst, s)
-               : launch_batch_step_t<double, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, s);
+               ? launch_batch_step_t<double, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst, s)
+               : launch_batch_step_t<double, PF_MODEL_COUPLED>(desc, items, nitems, inst_list,
+                                                              ninst, s);
   return model == PF_MODEL_AC
-             ? launch_batch_step_t<float, PF_MODEL_AC>(desc, item_inst, nitems, ninst, s)
-             : launch_batch_step_t<float, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, s);
+             ? launch_batch_step_t<float, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst, s)
+             : launch_batch_step_t<float, PF_MODEL_COUPLED>(desc, items, nitems, inst_list,
+                                                           ninst, s);
 }
 
 template <typename R, int MODEL>
-static hipError_t launch_batch_t(const BatchDesc* desc, const int* item_inst, int nitems,
+static hipError_t launch_batch_t(const BatchDesc* desc, const int2* items, int nitems,
                                  int ninst, int steps, int grid_blocks, unsigned* bar,
                                  unsigned* err, hipStream_t s) {
-  void* args[] = {(void*)&desc, (void*)&item_inst, (void*)&nitems, (void*)&ninst,
+  void* args[] = {(void*)&desc, (void*)&items, (void*)&nitems, (void*)&ninst,
                   (void*)&steps, (void*)&bar, (void*)&err};
   return hipLaunchCooperativeKernel((const void*)batch_kernel<R, MODEL>, dim3(grid_blocks),
                                     dim3(kBlock), args, 0, s);
 }
 
-hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int* item_inst,
+hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int2* items,
                         int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
                         unsigned* err, hipStream_t s) {
   if (precision == PF_FP64) {
     if (model == PF_MODEL_AC)
-      return launch_batch_t<double, PF_MODEL_AC>(desc, item_inst, nitems, ninst, steps,
+      return launch_batch_t<double, PF_MODEL_AC>(desc, items, nitems, ninst, steps,
                                                  grid_blocks, bar, err, s);
-    return launch_batch_t<double, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, steps,
+    return launch_batch_t<double, PF_MODEL_COUPLED>(desc, items, nitems, ninst, steps,
                                                     grid_blocks, bar, err, s);
   }
   if (model == PF_MODEL_AC)
-    return launch_batch_t<float, PF_MODEL_AC>(desc, item_inst, nitems, ninst, steps,
+    return launch_batch_t<float, PF_MODEL_AC>(desc, items, nitems, ninst, steps,
                                               grid_blocks, bar, err, s);
-  return launch_batch_t<float, PF_MODEL_COUPLED>(desc, item_inst, nitems, ninst, steps,
+  return launch_batch_t<float, PF_MODEL_COUPLED>(desc, items, nitems, ninst, steps,
                                                  grid_blocks, bar, err, s);
 }
 

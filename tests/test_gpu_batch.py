@@ -1,5 +1,6 @@
-"""Batched sweep (one persistent cooperative kernel for many instances)
-against per-instance runs and the FP64 oracle, through the C ABI."""
+"""Batched sweep (per-stage launches over all running instances, or one
+persistent cooperative kernel) against per-instance runs and the FP64
+oracle, through the C ABI."""
 import numpy as np
 import pytest
 
@@ -68,6 +69,38 @@ def test_batch_equals_individual_runs(precision, mode):
         assert np.array_equal(a, b), i
         assert st["ice_count"] == sb["ice_count"]
         assert sb["sum_phi"] == pytest.approx(st["sum_phi"], rel=1e-12)
+    for s in batch + single:
+        s.close()
+
+
+@pytest.mark.parametrize("mode", ["persistent", "graph"])
+def test_batch_staggered_finish_equals_individual_runs(mode):
+    """Instances that reach t_end after different numbers of attempts (each
+    starts at its own time): the graph form drops finished instances from its
+    work table and thins the tiles as the running set shrinks; every instance
+    must still end bitwise equal to its own single run."""
+    insts = small_instances(7, "fp32", seed0=2100)
+    t_end = 0.12
+    starts = [t_end * i / 8.0 for i in range(7)]
+    batch = make_solvers(insts, "fp32", 1e-3)
+    single = make_solvers(insts, "fp32", 1e-3)
+    for s, b, t0 in zip(single, batch, starts):
+        s.set_time(t0, 1e-3)
+        b.set_time(t0, 1e-3)
+    stats_b = pf.batch_integrate(batch, t_end=t_end, max_steps=5000, mode=mode, steps_per_poll=5)
+    counts = []
+    for i, s in enumerate(single):
+        st = s.integrate(t_end=t_end, max_steps=5000)
+        sb = stats_b[i]
+        assert st["status"] == sb["status"] == pf.PF_OK
+        assert (st["steps_accepted"], st["steps_rejected"]) == \
+            (sb["steps_accepted"], sb["steps_rejected"])
+        assert st["t"] == sb["t"] == t_end
+        a, _ = s.get_state()
+        b, _ = batch[i].get_state()
+        assert np.array_equal(a, b), i
+        counts.append(sb["steps_accepted"] + sb["steps_rejected"])
+    assert len(set(counts)) > 3, counts  # the instances did finish at different attempts
     for s in batch + single:
         s.close()
 
@@ -143,5 +176,7 @@ def test_sweep_instances_batch_to_equilibrium_small_subset():
         assert stats[i]["status"] == pf.PF_EQUILIBRIUM == st["status"]
         assert stats[i]["steps_accepted"] == st["steps_accepted"]
         assert stats[i]["ice_count"] == st["ice_count"]
+        assert stats[i]["t"] == st["t"]
+        assert np.array_equal(ss[i].get_state()[0], s.get_state()[0]), i
     for s in ss + single:
         s.close()
