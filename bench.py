@@ -29,11 +29,16 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per cell of each pass, per unknown: words read + written,
 # plus the 1-byte neighbourhood code.
-#  five-pass schedule: S1 r y, w Y2 k1 | S2 r Y2 k1, w Y3 | S3 r Y3 y k1, w Y4 k3
+#  five-pass schedule, four-cell kernels (Y2 and Y4 formed at the stencil
+#  points, never stored):
+#                      S1 r y, w k1 | S2 r y k1, w Y3 | S3 r Y3, w k3
+#                      | S4 r y k1 k3, w Y5 P C | S5 r Y5 P C, w y_new
+#  five-pass schedule, one-cell kernels (every stage value stored):
+#                      S1 r y, w Y2 k1 | S2 r Y2 k1, w Y3 | S3 r Y3 y k1, w Y4 k3
 #                      | S4 r Y4 y k1 k3, w Y5 P C | S5 r Y5 P C, w y_new
 #  paired schedule:    S1+S2 r y, w k1 Y3 | S3+S4 r Y3 y k1, w Y5 P C
 #                      | S5 r Y5 P C, w y_new
-PASS_WORDS = {"five": [3, 3, 5, 7, 4], "paired": [3, 6, 4]}
+PASS_WORDS = {"five": [2, 3, 2, 6, 4], "five_one_cell": [3, 3, 5, 7, 4], "paired": [3, 6, 4]}
 PASS_NAMES = {"five": ["S1", "S2", "S3", "S4", "S5"], "paired": ["S1+S2", "S3+S4", "S5"]}
 PASS_KERNELS = {"five": ["stage4_kernel<..,1>", "stage4_kernel<..,2>", "stage4_kernel<..,3>",
                          "stage4_kernel<..,4>", "stage4_kernel<..,5>"],
@@ -136,7 +141,7 @@ def run_sweep(args):
     attempts = max(x["steps_accepted"] + x["steps_rejected"] for x in st)
     for s in ss:
         s.close()
-    bpc = sum(PASS_WORDS["five"]) * 4 + 5  # AC model, FP32, five passes
+    bpc = sum(PASS_WORDS["five"]) * 4 + 5  # AC model, FP32, five four-cell passes
     achieved = bpc * ncell / (ms_step * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
@@ -271,7 +276,8 @@ def run_gpu(args, wl):
     sched = cfg["schedule"]
     esize = 8 if prec == "fp64" else 4
     nvar = 2 if model == "coupled" else 1
-    sb = pass_bytes(sched, nvar, esize)
+    sb = pass_bytes(sched if sched != "five" or cfg.get("four_cell", True) else "five_one_cell",
+                    nvar, esize)
     if case.G is not None:  # paper mode also reads the glass field in every pass
         sb = [b + esize for b in sb]
     npass = len(sb)

@@ -122,6 +122,16 @@ bool simple_kernels_only(const pf_params& P, int smooth) {
   return P.model == PF_MODEL_TEMP || P.reaction != PF_REACT_SIGMA || smooth;
 }
 
+// The four-cell kernels: n1 divisible by 4, the SigmaP1-P AC or coupled model
+// on the voxel mask, and a plane run with its neighbour rows within the LDS
+// budget.
+static bool four_cell_ok(const pf_params& P, int smooth) {
+  const int nvar = P.model == PF_MODEL_COUPLED ? 2 : 1;
+  const int esize = P.precision == PF_FP64 ? 8 : 4;
+  return P.n1 % 4 == 0 && !simple_kernels_only(P, smooth) &&
+         pf::stage4_lds_bytes(P.n1, nvar, esize) <= pf::kStage4MaxLds;
+}
+
 int validate(const pf_params* P, const uint8_t* mask) {
   if (!P || !mask) return fail(nullptr, PF_EINVAL, "params and mask must be non-NULL");
   if (P->n1 < 1 || P->n2 < 1 || P->n3 < 1)
@@ -174,13 +184,30 @@ StageArgs stage_args(const pf_handle* h, int stage) {
     a.out_y[1][v] = h->y[1][v];
     a.k1[v] = h->k1[v];
     a.k3[v] = h->k3[v];
-    switch (stage) {
-      case 1: a.in[v] = nullptr; a.out[v] = h->a[v]; break;
-      case 2: a.in[v] = h->a[v]; a.out[v] = h->b[v]; break;
-      case 3: a.in[v] = h->b[v]; a.out[v] = h->a[v]; break;
-      case 4: a.in[v] = h->a[v]; a.out[v] = h->b[v]; break;
-      case 5: a.in[v] = h->b[v]; a.out[v] = nullptr; break;
-      default: break;
+    if (h->vec) {
+      // Four-cell passes: S1 y -> k1; S2 (y, k1) -> Y3 in B; S3 Y3 -> k3;
+      // S4 (y, k1, k3) -> Y5 in A, P in the y_new slot, C in B; S5 (Y5, P,
+      // C) -> y_new over P.  Y2 and Y4 are formed at the stencil points.
+      switch (stage) {
+        case 1: a.in[v] = nullptr; a.out[v] = nullptr; break;
+        case 2: a.in[v] = nullptr; a.out[v] = h->b[v]; break;
+        case 3: a.in[v] = h->b[v]; a.out[v] = nullptr; break;
+        case 4: a.in[v] = nullptr; a.out[v] = h->a[v]; a.cbuf[v] = h->b[v]; break;
+        case 5: a.in[v] = h->a[v]; a.out[v] = nullptr; a.cbuf[v] = h->b[v]; break;
+        default: break;
+      }
+    } else {
+      // One-cell passes: S1 y -> k1, Y2 in A; S2 (Y2, k1) -> Y3 in B; S3
+      // (Y3, y, k1) -> k3, Y4 in A; S4 (Y4, y, k1, k3) -> Y5 in B, P over
+      // k1, C over k3; S5 (Y5, P, C) -> y_new.
+      switch (stage) {
+        case 1: a.in[v] = nullptr; a.out[v] = h->a[v]; break;
+        case 2: a.in[v] = h->a[v]; a.out[v] = h->b[v]; break;
+        case 3: a.in[v] = h->b[v]; a.out[v] = h->a[v]; break;
+        case 4: a.in[v] = h->a[v]; a.out[v] = h->b[v]; break;
+        case 5: a.in[v] = h->b[v]; a.out[v] = nullptr; break;
+        default: break;
+      }
     }
   }
   a.part = (stage == 1) ? h->part1 : (stage == 5 ? h->part5 : nullptr);
@@ -357,7 +384,7 @@ int autotune(pf_handle* h) {
   const int zcands[] = {1, 2, 4, 8, 16, 32};
   int best = h->z_chunk, best_vec = h->vec;
   float best_ms = 1e30f;
-  const bool try_both = !h->vec_fixed && h->P.n1 % 4 == 0 && !simple_kernels_only(h->P, h->smooth);
+  const bool try_both = !h->vec_fixed && four_cell_ok(h->P, h->smooth);
   for (int vec = 1; vec >= 0; --vec) {
     if (!try_both && vec != h->vec) continue;
     h->vec = vec;
@@ -466,7 +493,7 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
   // streamed fields bypass the caches (measured: faster at 256^3, slower on
   // cache-resident grids)
   h->stream_nt = (double)h->ncell * h->esize * 6 * h->nvar > 512.0e6 ? 1 : 0;
-  h->vec = (params->n1 % 4 == 0 && !simple_kernels_only(*params, G ? 1 : 0)) ? 1 : 0;
+  h->vec = four_cell_ok(*params, G ? 1 : 0) ? 1 : 0;
   h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
 
   auto bail = [&](int code, const std::string& msg) {
@@ -686,6 +713,8 @@ int pf_set_vector(pf_handle* h, int32_t enable) {
     return fail(h, PF_EINVAL, "four-cell kernels need n1 divisible by 4");
   if (enable && simple_kernels_only(h->P, h->smooth))
     return fail(h, PF_EINVAL, "four-cell kernels implement the SigmaP1-P AC and coupled models only");
+  if (enable && !four_cell_ok(h->P, h->smooth))
+    return fail(h, PF_EINVAL, "four-cell kernels: n1 too large for their LDS plane buffers");
   h->vec = enable ? 1 : 0;
   h->vec_fixed = 1;
   return set_tiles(h, h->z_chunk);
@@ -897,8 +926,10 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       return fail(nullptr, PF_EINVAL, "batch: all instances need the same model and precision");
     if (simple_kernels_only(inst[i]->P, inst[i]->smooth))
       return fail(nullptr, PF_EINVAL, "batch: the SigmaP1-P AC and coupled models only");
-    if (inst[i]->P.n1 % 4 != 0)
-      return fail(nullptr, PF_EINVAL, "batch: every instance needs n1 divisible by 4");
+    if (!four_cell_ok(inst[i]->P, inst[i]->smooth))
+      return fail(nullptr, PF_EINVAL,
+                  "batch: every instance needs n1 divisible by 4 and small enough for the "
+                  "four-cell kernels");
   }
   pf_handle* h0 = inst[0];
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : h0->own_stream;
@@ -927,7 +958,12 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     if (!c.done) act.push_back(i);
   }
   std::vector<int> all(n);
-  for (int i = 0; i < n; ++i) all[i] = i;
+  int n1max = 0;
+  for (int i = 0; i < n; ++i) {
+    all[i] = i;
+    n1max = inst[i]->P.n1 > n1max ? inst[i]->P.n1 : n1max;
+  }
+  const size_t lds = pf::stage4_lds_bytes(n1max, h0->nvar, h0->esize);
   const long long max_items = batch_items_at(inst, all, z_fixed ? z_fixed : 1);
   if (max_items > (1LL << 30)) return fail(h0, PF_EINVAL, "batch: too many work items");
   std::vector<pf::BatchDesc> desc(n);
@@ -995,7 +1031,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
       e = pf::launch_batch_step(h0->P.precision, h0->P.model, ddesc, ditems, (int)items.size(),
-                                dact, (int)act.size(), s);
+                                dact, (int)act.size(), lds, s);
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e == hipSuccess && e2 == hipSuccess) {
       e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
@@ -1018,7 +1054,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       return rc;
     }
     if (mode == 1) {
-      grid = pf::batch_max_blocks(h0->P.precision, h0->P.model);
+      grid = pf::batch_max_blocks(h0->P.precision, h0->P.model, lds);
       if (grid < 1) {
         cleanup();
         return fail(h0, PF_EHIP, "batch: occupancy query failed");
@@ -1029,7 +1065,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   while (!act.empty()) {
     hipError_t e = mode == 1 ? pf::launch_batch(h0->P.precision, h0->P.model, ddesc,
                                                 ditems, (int)items.size(), n, kStepsPerLaunch,
-                                                grid, dbar, dbar + 2, s)
+                                                grid, dbar, dbar + 2, lds, s)
                              : hipGraphLaunch(gexec, s);
     if (e != hipSuccess) {
       cleanup();

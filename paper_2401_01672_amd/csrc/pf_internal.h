@@ -15,6 +15,13 @@ namespace pf {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
+// Dynamic LDS of the four-cell stage kernels: two plane buffers of
+// kBlock + 2 n1/4 quads per unknown (the run and the rows on either side).
+inline size_t stage4_lds_bytes(int n1, int nvar, int esize) {
+  return 2u * (size_t)nvar * (size_t)(kBlock + 2 * (n1 / 4)) * 4u * (size_t)esize;
+}
+constexpr size_t kStage4MaxLds = 65536;
+
 // Per-cell neighbourhood code (one byte, static): bit f (f = 0..5 for faces
 // x1-,x1+,x2-,x2+,x3-,x3+) is set when the neighbour through face f exists
 // and is water; bit 6 is set when the cell itself is glass.
@@ -87,8 +94,9 @@ struct StageArgs {
   const void* y[2][2];// both state buffers
   void* k1[2];
   void* k3[2];
-  void* out[2];       // next stage input, or y_new (S5: written to y[1-cur])
-  void* out_y[2][2];  // S5 destination candidates
+  void* out[2];       // stored stage value written by the pass
+  void* out_y[2][2];  // both state buffers as destinations (S5: y_new)
+  void* cbuf[2];      // four-cell passes: error combination C (S4 -> S5)
   ModelConst mc;
   int z_chunk;
   int tiles_p, tiles_z;  // workgroup grid: plane tiles x z chunks
@@ -154,13 +162,15 @@ hipError_t launch_pair(int precision, int model, int first, int ts, const PairAr
 // batched sweep: cooperative persistent launch; grid_blocks <= batch_max_blocks()
 // bar: two zeroed unsigned counters (grid barrier); err: set to 1 when a
 // barrier wait overran its bound
-// items[i] = (instance, tile); the controllers run for desc[0 .. ninst)
+// items[i] = (instance, tile); the controllers run for desc[0 .. ninst);
+// lds = stage4_lds_bytes of the widest instance
 hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int2* items,
                         int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
-                        unsigned* err, hipStream_t s);
-int batch_max_blocks(int precision, int model);
+                        unsigned* err, size_t lds, hipStream_t s);
+int batch_max_blocks(int precision, int model, size_t lds);
 // batched sweep, multi-launch form: one attempt = 5 stage launches over the
 // nitems items + 1 controller launch over the ninst instances of inst_list
 hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
-                             int nitems, const int* inst_list, int ninst, hipStream_t s);
+                             int nitems, const int* inst_list, int ninst, size_t lds,
+                             hipStream_t s);
 }  // namespace pf

@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
 
 template <typename R, int MODEL, int STAGE, bool NT = false>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile, const int slot,
-                                            double* smem);
+                                            double* smem, void* lds);
 
 // Grid-wide barrier: bar[0] counts arrivals, bar[1] is the generation.  The
 // last workgroup to arrive resets the count and advances the generation
@@ -690,6 +690,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
                                                        int ninst, int steps_per_launch,
                                                        unsigned* bar, unsigned* err) {
   __shared__ double smem[8 * kWaves];
+  extern __shared__ __align__(16) unsigned char pf_stage_lds[];
   for (int it = 0; it < steps_per_launch; ++it) {
     // exit when every instance is done (same answer in every workgroup)
     int active = 0;
@@ -702,11 +703,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
         const BatchDesc& d = desc[it.x];
         const int tile = it.y;
         switch (stage) {
-          case 1: stage4_tile<R, MODEL, 1>(d.st[0], tile, tile, smem); break;
-          case 2: stage4_tile<R, MODEL, 2>(d.st[1], tile, tile, smem); break;
-          case 3: stage4_tile<R, MODEL, 3>(d.st[2], tile, tile, smem); break;
-          case 4: stage4_tile<R, MODEL, 4>(d.st[3], tile, tile, smem); break;
-          default: stage4_tile<R, MODEL, 5>(d.st[4], tile, tile, smem); break;
+          case 1: stage4_tile<R, MODEL, 1>(d.st[0], tile, tile, smem, pf_stage_lds); break;
+          case 2: stage4_tile<R, MODEL, 2>(d.st[1], tile, tile, smem, pf_stage_lds); break;
+          case 3: stage4_tile<R, MODEL, 3>(d.st[2], tile, tile, smem, pf_stage_lds); break;
+          case 4: stage4_tile<R, MODEL, 4>(d.st[3], tile, tile, smem, pf_stage_lds); break;
+          default: stage4_tile<R, MODEL, 5>(d.st[4], tile, tile, smem, pf_stage_lds); break;
         }
       }
       grid_barrier(bar, gridDim.x, err);
@@ -729,8 +730,9 @@ template <typename R, int MODEL, int STAGE>
 __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchDesc* desc,
                                                              const int2* items) {
   __shared__ double smem[8 * kWaves];
+  extern __shared__ __align__(16) unsigned char pf_stage_lds[];
   const int2 it = items[xcd_tile(blockIdx.x, gridDim.x)];
-  stage4_tile<R, MODEL, STAGE>(desc[it.x].st[STAGE - 1], it.y, it.y, smem);
+  stage4_tile<R, MODEL, STAGE>(desc[it.x].st[STAGE - 1], it.y, it.y, smem, pf_stage_lds);
 }
 
 __global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc,
@@ -742,68 +744,72 @@ __global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc,
 
 template <typename R, int MODEL>
 static hipError_t launch_batch_step_t(const BatchDesc* desc, const int2* items, int nitems,
-                                      const int* inst_list, int ninst, hipStream_t s) {
+                                      const int* inst_list, int ninst, size_t lds,
+                                      hipStream_t s) {
   const dim3 g((unsigned)nitems), b(kBlock);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1>), g, b, 0, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2>), g, b, 0, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3>), g, b, 0, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4>), g, b, 0, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5>), g, b, 0, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5>), g, b, lds, s, desc, items);
   hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc, inst_list);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
-                             int nitems, const int* inst_list, int ninst, hipStream_t s) {
+                             int nitems, const int* inst_list, int ninst, size_t lds,
+                             hipStream_t s) {
   if (precision == PF_FP64)
     return model == PF_MODEL_AC
-               ? launch_batch_step_t<double, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst, s)
+               ? launch_batch_step_t<double, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst,
+                                                         lds, s)
                : launch_batch_step_t<double, PF_MODEL_COUPLED>(desc, items, nitems, inst_list,
-                                                              ninst, s);
+                                                              ninst, lds, s);
   return model == PF_MODEL_AC
-             ? launch_batch_step_t<float, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst, s)
+             ? launch_batch_step_t<float, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst,
+                                                      lds, s)
              : launch_batch_step_t<float, PF_MODEL_COUPLED>(desc, items, nitems, inst_list,
-                                                           ninst, s);
+                                                           ninst, lds, s);
 }
 
 template <typename R, int MODEL>
 static hipError_t launch_batch_t(const BatchDesc* desc, const int2* items, int nitems,
                                  int ninst, int steps, int grid_blocks, unsigned* bar,
-                                 unsigned* err, hipStream_t s) {
+                                 unsigned* err, size_t lds, hipStream_t s) {
   void* args[] = {(void*)&desc, (void*)&items, (void*)&nitems, (void*)&ninst,
                   (void*)&steps, (void*)&bar, (void*)&err};
   return hipLaunchCooperativeKernel((const void*)batch_kernel<R, MODEL>, dim3(grid_blocks),
-                                    dim3(kBlock), args, 0, s);
+                                    dim3(kBlock), args, (unsigned)lds, s);
 }
 
 hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const int2* items,
                         int nitems, int ninst, int steps, int grid_blocks, unsigned* bar,
-                        unsigned* err, hipStream_t s) {
+                        unsigned* err, size_t lds, hipStream_t s) {
   if (precision == PF_FP64) {
     if (model == PF_MODEL_AC)
       return launch_batch_t<double, PF_MODEL_AC>(desc, items, nitems, ninst, steps,
-                                                 grid_blocks, bar, err, s);
+                                                 grid_blocks, bar, err, lds, s);
     return launch_batch_t<double, PF_MODEL_COUPLED>(desc, items, nitems, ninst, steps,
-                                                    grid_blocks, bar, err, s);
+                                                    grid_blocks, bar, err, lds, s);
   }
   if (model == PF_MODEL_AC)
     return launch_batch_t<float, PF_MODEL_AC>(desc, items, nitems, ninst, steps,
-                                              grid_blocks, bar, err, s);
+                                              grid_blocks, bar, err, lds, s);
   return launch_batch_t<float, PF_MODEL_COUPLED>(desc, items, nitems, ninst, steps,
-                                                 grid_blocks, bar, err, s);
+                                                 grid_blocks, bar, err, lds, s);
 }
 
-int batch_max_blocks(int precision, int model) {
+int batch_max_blocks(int precision, int model, size_t lds) {
   int per_cu = 0;
   hipError_t e;
   if (precision == PF_FP64)
     e = model == PF_MODEL_AC
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<double, PF_MODEL_AC>, kBlock, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<double, PF_MODEL_COUPLED>, kBlock, 0);
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<double, PF_MODEL_AC>, kBlock, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<double, PF_MODEL_COUPLED>, kBlock, lds);
   else
     e = model == PF_MODEL_AC
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<float, PF_MODEL_AC>, kBlock, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<float, PF_MODEL_COUPLED>, kBlock, 0);
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<float, PF_MODEL_AC>, kBlock, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<float, PF_MODEL_COUPLED>, kBlock, lds);
   if (e != hipSuccess || per_cu < 1) return 0;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -981,6 +987,25 @@ __device__ __forceinline__ void stq_s(R* base, uint32_t idx, const Quad<R>& q) {
   else stq_plain(base, idx, q);
 }
 
+// Stage value formed from the state and stored derivatives at a quad:
+// Y2 = y + dt k1/3 (S2) or Y4 = y + dt (k1 + 3 k3)/8 (S4); the same
+// expressions, operation for operation, as in the one-cell kernel.
+template <int STAGE, typename R>
+__device__ __forceinline__ Quad<R> stage_value(const R* y, const R* q1, const R* q3, R rdt,
+                                               uint32_t i) {
+  Quad<R> a = ldq(y, i);
+  const Quad<R> b = ldq(q1, i);
+  if constexpr (STAGE == 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.v[k] = a.v[k] + rdt * (R(1.0 / 3.0) * b.v[k]);
+  } else {
+    const Quad<R> c = ldq(q3, i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.v[k] = a.v[k] + rdt * (R(0.125) * (b.v[k] + R(3) * c.v[k]));
+  }
+  return a;
+}
+
 template <typename R>
 __device__ __forceinline__ R shfl_up1(R v) {
   return __shfl_up(v, 1, 64);
@@ -992,7 +1017,7 @@ __device__ __forceinline__ R shfl_down1(R v) {
 
 template <typename R, int MODEL, int STAGE, bool NT>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
-                                            const int slot, double* smem) {
+                                            const int slot, double* smem, void* lds_raw) {
   const ModelConst& m = a.mc;
   double t0 = a.t_fixed, dt = 0.0;
   int cur = 0;
@@ -1022,40 +1047,81 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   R* k3[2] = {static_cast<R*>(a.k3[0]), static_cast<R*>(a.k3[1])};
   R* out[2] = {static_cast<R*>(STAGE == 5 ? a.out_y[1 - cur][0] : a.out[0]),
                static_cast<R*>(STAGE == 5 ? a.out_y[1 - cur][1] : a.out[1])};
+  R* ynew[2] = {static_cast<R*>(a.out_y[1 - cur][0]), static_cast<R*>(a.out_y[1 - cur][1])};
+  R* cb[2] = {static_cast<R*>(a.cbuf[0]), static_cast<R*>(a.cbuf[1])};
   if (STAGE == 1) {
     in[0] = yv[0];
     in[1] = yv[1];
   }
-  if (STAGE == 5 && a.c_from_out) {  // paired schedule: P in K3, C in the y_new slot
-    k1[0] = k3[0];
-    k1[1] = k3[1];
-    k3[0] = out[0];
-    k3[1] = out[1];
+  if (STAGE == 5) {  // where S4 left P and C
+    if (a.c_from_out) {  // paired schedule: P in K3, C in the y_new slot
+      k1[0] = k3[0];
+      k1[1] = k3[1];
+      k3[0] = out[0];
+      k3[1] = out[1];
+    } else {  // P in the y_new slot (overwritten in place), C in cbuf
+      k1[0] = out[0];
+      k1[1] = out[1];
+      k3[0] = cb[0];
+      k3[1] = cb[1];
+    }
   }
   const R rdt = R(dt);
+  // Stencil input quad at cell index i of variable v.  S2 and S4 form their
+  // stage value from the state and the stored derivatives (Y2 = y + dt k1/3,
+  // Y4 = y + dt (k1 + 3 k3)/8; the same expressions as the one-cell kernel);
+  // raw (when given) receives the loaded k1 quad (S2 needs it at the cell).
+  auto ldin = [&](int v, uint32_t i, Quad<R>* raw) -> Quad<R> {
+    if constexpr (STAGE == 2 || STAGE == 4) {
+      const Quad<R> y0 = ldq(yv[v], i), q1 = ldq(k1[v], i);
+      Quad<R> q3, o;
+      if constexpr (STAGE == 4) q3 = ldq(k3[v], i);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if constexpr (STAGE == 2) o.v[k] = y0.v[k] + rdt * (R(1.0 / 3.0) * q1.v[k]);
+        else o.v[k] = y0.v[k] + rdt * (R(0.125) * (q1.v[k] + R(3) * q3.v[k]));
+      }
+      if (raw) raw[1] = q1;
+      return o;
+    } else {
+      return ldq(in[v], i);
+    }
+  };
 
   double red0 = 0.0;
+  // The workgroup's quads are the run [q0, q0 + kBlock) of the plane's quads
+  // (Q per x1-row).  Per plane, the stencil input of the run and of the Q
+  // quads on either side (the rows below and above) is staged in LDS, double
+  // buffered: [v][W] quads with W = kBlock + 2 Q, run at slot Q + t.  The x3
+  // neighbours come from a register window, x1 neighbours inside a wavefront
+  // from lane shuffles.
+  const uint32_t Q = (uint32_t)m.n1 >> 2, nq = plane >> 2, W = kBlock + 2u * Q;
+  const uint32_t t = threadIdx.x, q0 = (uint32_t)tp * kBlock;
+  Quad<R>* lds = static_cast<Quad<R>*>(lds_raw);
   // the quad's position (n1 % 4 == 0: all four cells share i2)
   const uint32_t i1 = active ? p % (uint32_t)m.n1 : 0u;
   const uint32_t i2 = active ? p / (uint32_t)m.n1 : 0u;
   const bool xm_in = i1 > 0, xp_in = i1 + 4 < (uint32_t)m.n1;
   const bool ym_in = i2 > 0, yp_in = i2 + 1 < (uint32_t)m.n2;
-  // lanes whose x-neighbour quad lives in another wavefront (or is inactive)
+  // lanes whose x-neighbour quad lives in another wavefront (read from LDS)
   const bool xm_remote = xm_in && (lane == 0);
   const bool xp_remote = xp_in && (lane == 63 || p + 4 >= plane);
   const unsigned dirf = (unsigned)m.dirichlet_faces;
 
+  // z window of the stencil input, and k1 at the cell (S2)
   Quad<R> cm[2], cc[2], cp[2];
+  Quad<R> rc[2][2], rp[2][2];
   uint32_t n = p + plane * (uint32_t)z0;
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      cc[v] = ldq(in[v], n);
-      cm[v] = z0 > 0 ? ldq(in[v], n - plane) : cc[v];
+      cc[v] = ldin(v, n, rc[v]);
+      cm[v] = z0 > 0 ? ldin(v, n - plane, nullptr) : cc[v];
     }
   }
   for (int z = z0; z < z1; ++z, n += plane) {
     const bool zp_in = z < m.n3 - 1;
+    Quad<R>* L = lds + (size_t)((z - z0) & 1) * NV * W;
     Quad<R> ym[2], yp[2];
     R xl[2], xr[2];
     uint32_t codes = 0;
@@ -1063,21 +1129,35 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       codes = *reinterpret_cast<const uint32_t*>(a.code + n);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        cp[v] = zp_in ? ldq(in[v], n + plane) : cc[v];
-        ym[v] = ym_in ? ldq(in[v], n - (uint32_t)m.n1) : cc[v];
-        yp[v] = yp_in ? ldq(in[v], n + (uint32_t)m.n1) : cc[v];
+        cp[v] = zp_in ? ldin(v, n + plane, rp[v]) : cc[v];
+        L[v * W + Q + t] = cc[v];
       }
     }
-    // x neighbours of the end cells: adjacent lanes, or memory across waves
+    // the rows below and above the run, in this plane
+    const uint32_t zoff = plane * (uint32_t)z;
+    for (uint32_t h = t; h < 2u * Q; h += kBlock) {
+      const long long hq = h < Q ? (long long)q0 - (long long)Q + h : (long long)(q0 + kBlock + h - Q);
+      if (hq >= 0 && hq < (long long)nq) {
+        const uint32_t sl = h < Q ? h : h + kBlock;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) L[v * W + sl] = ldin(v, zoff + (uint32_t)hq * 4u, nullptr);
+      }
+    }
+    __syncthreads();
+    // x neighbours of the end cells: adjacent lanes, or LDS across waves
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       xl[v] = shfl_up1(cc[v].v[3]);
       xr[v] = shfl_down1(cc[v].v[0]);
-      if (active && xm_remote) xl[v] = in[v][n - 1];
-      if (active && xp_remote) xr[v] = in[v][n + 4];
+      if (active && xm_remote) xl[v] = L[v * W + Q + t - 1].v[3];
+      if (active && xp_remote) xr[v] = L[v * W + Q + t + 1].v[0];
       // a boundary face carries the cell's own value
       if (!xm_in) xl[v] = cc[v].v[0];
       if (!xp_in) xr[v] = cc[v].v[3];
+      ym[v] = cc[v];
+      yp[v] = cc[v];
+      if (active && ym_in) ym[v] = L[v * W + t];
+      if (active && yp_in) yp[v] = L[v * W + 2u * Q + t];
     }
     if (active) {
       const unsigned inb_c = (ym_in ? 4u : 0u) | (yp_in ? 8u : 0u) | (z > 0 ? 16u : 0u) |
@@ -1120,24 +1200,17 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
           stq_s<NT>(out[v], n, kk);
         } else if (STAGE == 1) {
           stq_s<NT>(k1[v], n, kk);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 3.0) * kk.v[k]);
-          stq_s<NT>(out[v], n, o);
         } else if (STAGE == 2) {
-          const Quad<R> q1 = ldq_s<NT>(k1[v], n);
+          const Quad<R>& q1 = rc[v][1];
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 6.0) * (kk.v[k] - q1.v[k]));
           stq_s<NT>(out[v], n, o);
         } else if (STAGE == 3) {
-          const Quad<R> q1 = ldq_s<NT>(k1[v], n), y0 = ldq_s<NT>(yv[v], n);
           stq_s<NT>(k3[v], n, kk);
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            o.v[k] = y0.v[k] + rdt * (R(0.125) * (q1.v[k] + R(3) * kk.v[k]));
-          stq_s<NT>(out[v], n, o);
         } else if (STAGE == 4) {
-          const Quad<R> q1 = ldq_s<NT>(k1[v], n), q3 = ldq_s<NT>(k3[v], n), y0 = ldq_s<NT>(yv[v], n);
+          // the cell's y, k1, k3 were loaded one plane earlier: cache hits
+          const Quad<R> y0 = ldq(yv[v], n), q1 = ldq(k1[v], n), q3 = ldq(k3[v], n);
           Quad<R> P, Cc;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
@@ -1146,8 +1219,8 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
             Cc.v[k] = rdt * (R(1.0 / 30.0) * (R(2) * q1.v[k] - R(9) * q3.v[k] + R(8) * kk.v[k]));
           }
           stq_s<NT>(out[v], n, o);
-          stq_s<NT>(k1[v], n, P);
-          stq_s<NT>(k3[v], n, Cc);
+          stq_s<NT>(ynew[v], n, P);
+          stq_s<NT>(cb[v], n, Cc);
         } else if (STAGE == 5) {
           const Quad<R> P = ldq_s<NT>(k1[v], n), Cc = ldq_s<NT>(k3[v], n);
 #pragma unroll
@@ -1163,9 +1236,12 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       for (int v = 0; v < NV; ++v) {
         cm[v] = cc[v];
         cc[v] = cp[v];
+        if constexpr (STAGE == 2) rc[v][1] = rp[v][1];
       }
     }
   }
+  // the plane buffers are reused by the next tile of a persistent block
+  __syncthreads();
   if (STAGE == 1) {
     // the sums of the state (phi, enthalpy, ice) are not needed per step:
     // runs report them from a diagnostics pass over the final state
@@ -1187,7 +1263,9 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
 template <typename R, int MODEL, int STAGE, bool NT = false>
 __global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
-  stage4_tile<R, MODEL, STAGE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem);
+  extern __shared__ __align__(16) unsigned char pf_stage_lds[];
+  stage4_tile<R, MODEL, STAGE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem,
+                                   pf_stage_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1524,12 +1602,14 @@ static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
   if (a.mc.reaction == PF_REACT_GRADP || a.mc.smooth) return launch_simple_t<R, MODEL>(stage, a, s);
   if (a.vec) {
+    const size_t lds = stage4_lds_bytes(a.mc.n1, MODEL == PF_MODEL_COUPLED ? 2 : 1, sizeof(R));
+    if (lds > kStage4MaxLds) return hipErrorInvalidValue;
 #define PF_S4(S)                                                                       \
   do {                                                                                 \
     if (a.stream_nt)                                                                   \
-      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true>), grid, block, 0, s, a);    \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true>), grid, block, lds, s, a);  \
     else                                                                               \
-      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false>), grid, block, 0, s, a);   \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false>), grid, block, lds, s, a); \
   } while (0)
     switch (stage) {
       case 0: PF_S4(0); break;
