@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per cell of each pass, per unknown: words read + written,
 # plus the 1-byte neighbourhood code.
-#  five-pass schedule, four-cell kernels (Y2 and Y4 formed at the stencil
+#  five-pass schedule, vector kernels (Y2 and Y4 formed at the stencil
 #  points, never stored):
 #                      S1 r y, w k1 | S2 r y k1, w Y3 | S3 r Y3, w k3
 #                      | S4 r y k1 k3, w Y5 P C | S5 r Y5 P C, w y_new
@@ -141,7 +141,7 @@ def run_sweep(args):
     attempts = max(x["steps_accepted"] + x["steps_rejected"] for x in st)
     for s in ss:
         s.close()
-    bpc = sum(PASS_WORDS["five"]) * 4 + 5  # AC model, FP32, five four-cell passes
+    bpc = sum(PASS_WORDS["five"]) * 4 + 5  # AC model, FP32, five vector passes
     achieved = bpc * ncell / (ms_step * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
@@ -276,7 +276,7 @@ def run_gpu(args, wl):
     sched = cfg["schedule"]
     esize = 8 if prec == "fp64" else 4
     nvar = 2 if model == "coupled" else 1
-    sb = pass_bytes(sched if sched != "five" or cfg.get("four_cell", True) else "five_one_cell",
+    sb = pass_bytes(sched if sched != "five" or cfg.get("vector", True) else "five_one_cell",
                     nvar, esize)
     if case.G is not None:  # paper mode also reads the glass field in every pass
         sb = [b + esize for b in sb]
@@ -285,7 +285,7 @@ def run_gpu(args, wl):
     for i in range(npass):
         gbs = sb[i] * ncell / (ms[i] * 1e-3) / 1e9
         kl = PASS_KERNELS[sched][i]
-        if not cfg.get("four_cell", True):
+        if not cfg.get("vector", True):
             kl = kl.replace("stage4_kernel", "stage_kernel")
         per_pass.append(dict(pass_=PASS_NAMES[sched][i], kernel=kl,
                              ms=round(ms[i], 5), bytes_per_cell=sb[i], gbs=round(gbs, 1)))

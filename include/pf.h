@@ -152,7 +152,7 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out);
  * I_W(G) = max(0, 1 - zeta G) masks the update), and lambda and rho c are
  * blended with each cell's G (eq. material-properties-blending-formula).
  * Water cells for the diagnostics and the equilibrium test: G < 1/2.  Runs
- * on the one-cell stage kernels (no four-cell, paired or batched variants).
+ * on the one-cell stage kernels (no vector, paired or batched variants).
  * Errors: as pf_create, PF_EINVAL for G outside [0, 1]. */
 int pf_create_field(const pf_params* params, const double* G, pf_handle** out);
 
@@ -204,7 +204,7 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
                  pf_run_stats* stats);
 
 /* Batched sweep: integrate n independent instances (same model and
- * precision, each with n1 divisible by 4, each with its own geometry,
+ * precision, each with n1 divisible by 4 (FP32) or 2 (FP64), each with its own geometry,
  * constants, state, t and dt) together: every stage pass processes the tiles
  * of all unfinished instances in one launch (or one persistent cooperative
  * kernel runs all passes of a poll interval, see pf_batch_options), then each
@@ -256,8 +256,14 @@ int pf_set_tile(pf_handle* h, int32_t z_chunk);
  * Both give the same arithmetic per cell.  Re-runs the tile autotuner. */
 int pf_set_schedule(pf_handle* h, int32_t schedule);
 
-/* Single-stage passes with four consecutive x1-cells per thread (default when
- * n1 % 4 == 0; PF_EINVAL otherwise) or one cell per thread.  Same results. */
+/* Single-stage passes on vector kernels, one 16-byte vector of consecutive
+ * x1-cells per thread (4 FP32 or 2 FP64 cells; n1 must be divisible by that
+ * width and the SigmaP1-P AC or coupled model on a voxel mask is required,
+ * PF_EINVAL otherwise), or on one-cell kernels.  The two forms store
+ * different intermediate stage values (the vector passes form Y2 and Y4 at
+ * the stencil points from y, k1 and k3; the one-cell passes store them) and
+ * give the same results.  The default is the vector form where it applies;
+ * the autotuner times both unless this call fixed one. */
 int pf_set_vector(pf_handle* h, int32_t enable);
 
 /* Tile of the paired passes: tile_index 0: 64x4, 1: 64x8, 2: 32x8 cells of
@@ -267,7 +273,7 @@ int pf_set_pair_tile(pf_handle* h, int32_t tile_index, int32_t z_chunk);
 
 /* Current configuration, out[0..8] = {schedule, passes per attempt,
  * single-stage z_chunk, single-stage workgroups, pair tile x, pair tile y,
- * pair z_chunk, pair workgroups, four-cell kernels (1) or one-cell (0)}
+ * pair z_chunk, pair workgroups, vector kernels (1) or one-cell (0)}
  * (after the autotuner, if it has run; it times both kernel forms unless
  * pf_set_vector fixed one). */
 int pf_get_config(const pf_handle* h, int32_t* out);

@@ -328,7 +328,7 @@ class Solver:
         v = list(out)
         return dict(schedule={0: "five", 1: "paired"}[v[0]], passes=v[1], z_chunk=v[2],
                     workgroups=v[3], pair_tile=(v[4], v[5]), pair_z_chunk=v[6],
-                    pair_workgroups=v[7], four_cell=bool(v[8]))
+                    pair_workgroups=v[7], vector=bool(v[8]))
 
     def time_kernels(self, reps: int = 10):
         out = (C.c_double * 6)()

@@ -46,7 +46,7 @@ struct pf_handle {
   DevCtl* ctl = nullptr;   // device
   DevCtl* hctl = nullptr;  // pinned host mirror
   int sched = pf::kSchedFive;
-  int vec = 0;  // four-cells-per-thread stage kernels (n1 % 4 == 0)
+  int vec = 0;  // vector stage kernels (one 16-byte vector of x1-cells per thread)
   int vec_fixed = 0;  // set by pf_set_vector: the autotuner keeps vec
   int stream_nt = 0;  // non-temporal streams: working set far above the caches
   int z_chunk = 16;  // single-stage passes
@@ -116,19 +116,19 @@ void fill_model_const(const pf_params& P, ModelConst& m) {
   m.inv_h = 1.0 / P.h;
 }
 
-// the four-cell, paired and batched kernels implement the SigmaP1-P phase
+// the vector, paired and batched kernels implement the SigmaP1-P phase
 // equation of the AC and coupled models only
 bool simple_kernels_only(const pf_params& P, int smooth) {
   return P.model == PF_MODEL_TEMP || P.reaction != PF_REACT_SIGMA || smooth;
 }
 
-// The four-cell kernels: n1 divisible by 4, the SigmaP1-P AC or coupled model
-// on the voxel mask, and a plane run with its neighbour rows within the LDS
-// budget.
-static bool four_cell_ok(const pf_params& P, int smooth) {
+// The vector kernels: n1 divisible by the vector width (4 FP32 or 2 FP64
+// cells), the SigmaP1-P AC or coupled model on the voxel mask, and a plane
+// run with its neighbour rows within the LDS budget.
+static bool vector_ok(const pf_params& P, int smooth) {
   const int nvar = P.model == PF_MODEL_COUPLED ? 2 : 1;
   const int esize = P.precision == PF_FP64 ? 8 : 4;
-  return P.n1 % 4 == 0 && !simple_kernels_only(P, smooth) &&
+  return P.n1 % pf::vec_cells(esize) == 0 && !simple_kernels_only(P, smooth) &&
          pf::stage4_lds_bytes(P.n1, nvar, esize) <= pf::kStage4MaxLds;
 }
 
@@ -185,7 +185,7 @@ StageArgs stage_args(const pf_handle* h, int stage) {
     a.k1[v] = h->k1[v];
     a.k3[v] = h->k3[v];
     if (h->vec) {
-      // Four-cell passes: S1 y -> k1; S2 (y, k1) -> Y3 in B; S3 Y3 -> k3;
+      // Vector passes: S1 y -> k1; S2 (y, k1) -> Y3 in B; S3 Y3 -> k3;
       // S4 (y, k1, k3) -> Y5 in A, P in the y_new slot, C in B; S5 (Y5, P,
       // C) -> y_new over P.  Y2 and Y4 are formed at the stencil points.
       switch (stage) {
@@ -294,7 +294,7 @@ int set_tiles(pf_handle* h, int zc) {
   if (zc < 1) zc = 1;
   if (zc > h->P.n3) zc = h->P.n3;
   int tp, tz;
-  int nb = pf::grid_blocks(h->mc, zc, h->vec, &tp, &tz);
+  int nb = pf::grid_blocks(h->mc, zc, h->vec ? pf::vec_cells(h->esize) : 1, &tp, &tz);
   if (nb > h->max_parts) return fail(h, PF_EINVAL, "tile choice exceeds partial buffer");
   h->z_chunk = zc;
   h->tiles_p = tp;
@@ -380,11 +380,11 @@ int autotune(pf_handle* h) {
     return PF_OK;
   };
   // (1) planes per column of the single-stage passes, and (unless the caller
-  // fixed it) four-cell or one-cell kernels
+  // fixed it) vector or one-cell kernels
   const int zcands[] = {1, 2, 4, 8, 16, 32};
   int best = h->z_chunk, best_vec = h->vec;
   float best_ms = 1e30f;
-  const bool try_both = !h->vec_fixed && four_cell_ok(h->P, h->smooth);
+  const bool try_both = !h->vec_fixed && vector_ok(h->P, h->smooth);
   for (int vec = 1; vec >= 0; --vec) {
     if (!try_both && vec != h->vec) continue;
     h->vec = vec;
@@ -493,7 +493,7 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
   // streamed fields bypass the caches (measured: faster at 256^3, slower on
   // cache-resident grids)
   h->stream_nt = (double)h->ncell * h->esize * 6 * h->nvar > 512.0e6 ? 1 : 0;
-  h->vec = four_cell_ok(*params, G ? 1 : 0) ? 1 : 0;
+  h->vec = vector_ok(*params, G ? 1 : 0) ? 1 : 0;
   h->dt = params->dt_max > 0 ? params->dt_max : 1e-3;
 
   auto bail = [&](int code, const std::string& msg) {
@@ -507,7 +507,7 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
 
   // maximum number of workgroups over all tile choices (z_chunk >= 1)
   int tp, tz;
-  h->max_parts = pf::grid_blocks(h->mc, 1, 0, &tp, &tz);  // scalar grid bounds the vector one
+  h->max_parts = pf::grid_blocks(h->mc, 1, 1, &tp, &tz);  // one-cell grid bounds the vector one
   for (int ts = 0; ts < 3; ++ts) {
     int tx, ty, tzz;
     const int nb = pf::pair_blocks(h->mc, ts, 4, &tx, &ty, &tzz);
@@ -678,7 +678,7 @@ int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dph
     a.ignore_done = 1;
     a.t_fixed = t;
     a.vec = 0;
-    pf::grid_blocks(h->mc, h->z_chunk, 0, &a.tiles_p, &a.tiles_z);
+    pf::grid_blocks(h->mc, h->z_chunk, 1, &a.tiles_p, &a.tiles_z);
     a.in[0] = theta;
     a.in[1] = nullptr;
     a.out[0] = dtheta;
@@ -696,12 +696,12 @@ int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dph
   a.in[1] = theta;
   a.out[0] = dphi;
   a.out[1] = dtheta;
-  // caller buffers: the four-cell kernel needs 16-byte aligned fields
+  // caller buffers: the vector kernels need 16-byte aligned fields
   auto aligned = [](const void* q) { return ((uintptr_t)q & 15u) == 0; };
   if (a.vec && !(aligned(phi) && aligned(dphi) && (h->nvar == 1 || (aligned(theta) &&
                                                                     aligned(dtheta))))) {
     a.vec = 0;
-    pf::grid_blocks(h->mc, h->z_chunk, 0, &a.tiles_p, &a.tiles_z);
+    pf::grid_blocks(h->mc, h->z_chunk, 1, &a.tiles_p, &a.tiles_z);
   }
   PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, h->stream));
   return PF_OK;
@@ -709,12 +709,12 @@ int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dph
 
 int pf_set_vector(pf_handle* h, int32_t enable) {
   if (!h) return PF_EINVAL;
-  if (enable && h->P.n1 % 4 != 0)
-    return fail(h, PF_EINVAL, "four-cell kernels need n1 divisible by 4");
+  if (enable && h->P.n1 % pf::vec_cells(h->esize) != 0)
+    return fail(h, PF_EINVAL, "vector kernels need n1 divisible by 4 (FP32) or 2 (FP64)");
   if (enable && simple_kernels_only(h->P, h->smooth))
-    return fail(h, PF_EINVAL, "four-cell kernels implement the SigmaP1-P AC and coupled models only");
-  if (enable && !four_cell_ok(h->P, h->smooth))
-    return fail(h, PF_EINVAL, "four-cell kernels: n1 too large for their LDS plane buffers");
+    return fail(h, PF_EINVAL, "vector kernels implement the SigmaP1-P AC and coupled models only");
+  if (enable && !vector_ok(h->P, h->smooth))
+    return fail(h, PF_EINVAL, "vector kernels: n1 too large for their LDS plane buffers");
   h->vec = enable ? 1 : 0;
   h->vec_fixed = 1;
   return set_tiles(h, h->z_chunk);
@@ -906,7 +906,8 @@ static long long batch_items_at(pf_handle* const* inst, const std::vector<int>& 
   long long total = 0;
   for (int i : act) {
     int tp, tz;
-    total += pf::grid_blocks(inst[i]->mc, z < inst[i]->P.n3 ? z : inst[i]->P.n3, 1, &tp, &tz);
+    total += pf::grid_blocks(inst[i]->mc, z < inst[i]->P.n3 ? z : inst[i]->P.n3,
+                             pf::vec_cells(inst[i]->esize), &tp, &tz);
   }
   return total;
 }
@@ -926,10 +927,10 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       return fail(nullptr, PF_EINVAL, "batch: all instances need the same model and precision");
     if (simple_kernels_only(inst[i]->P, inst[i]->smooth))
       return fail(nullptr, PF_EINVAL, "batch: the SigmaP1-P AC and coupled models only");
-    if (!four_cell_ok(inst[i]->P, inst[i]->smooth))
+    if (!vector_ok(inst[i]->P, inst[i]->smooth))
       return fail(nullptr, PF_EINVAL,
-                  "batch: every instance needs n1 divisible by 4 and small enough for the "
-                  "four-cell kernels");
+                  "batch: every instance needs n1 divisible by 4 (FP32) or 2 (FP64) and "
+                  "small enough for the vector kernels");
   }
   pf_handle* h0 = inst[0];
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : h0->own_stream;

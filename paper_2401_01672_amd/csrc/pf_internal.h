@@ -15,10 +15,12 @@ namespace pf {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
-// Dynamic LDS of the four-cell stage kernels: two plane buffers of
-// kBlock + 2 n1/4 quads per unknown (the run and the rows on either side).
+// The vector stage kernels give each thread one 16-byte vector of cells.
+constexpr int vec_cells(int esize) { return 16 / esize; }
+// Their dynamic LDS: two plane buffers of kBlock + 2 n1/vec_cells vectors
+// per unknown (the workgroup's run and the rows on either side).
 inline size_t stage4_lds_bytes(int n1, int nvar, int esize) {
-  return 2u * (size_t)nvar * (size_t)(kBlock + 2 * (n1 / 4)) * 4u * (size_t)esize;
+  return 2u * (size_t)nvar * (size_t)(kBlock + 2 * (n1 / vec_cells(esize))) * 16u;
 }
 constexpr size_t kStage4MaxLds = 65536;
 
@@ -96,7 +98,7 @@ struct StageArgs {
   void* k3[2];
   void* out[2];       // stored stage value written by the pass
   void* out_y[2][2];  // both state buffers as destinations (S5: y_new)
-  void* cbuf[2];      // four-cell passes: error combination C (S4 -> S5)
+  void* cbuf[2];      // vector passes: error combination C (S4 -> S5)
   ModelConst mc;
   int z_chunk;
   int tiles_p, tiles_z;  // workgroup grid: plane tiles x z chunks
@@ -153,7 +155,8 @@ hipError_t launch_controller(DevCtl* ctl, const double* part1, int np1, const do
 hipError_t launch_diag(int precision, int model, const uint8_t* code, const void* G,
                        const void* phi, const void* th, const ModelConst& m, long long n,
                        double* part, int nparts, double* out4, hipStream_t s);
-int grid_blocks(const ModelConst& mc, int z_chunk, int vec, int* tiles_p, int* tiles_z);
+// workgroups of a stage pass with `cells` x1-cells per thread (1 or vec_cells)
+int grid_blocks(const ModelConst& mc, int z_chunk, int cells, int* tiles_p, int* tiles_z);
 // paired kernels: tile shape index ts selects (TX, TY) from kPairTiles
 constexpr int kPairTiles[3][2] = {{64, 4}, {64, 8}, {32, 8}};
 int pair_blocks(const ModelConst& mc, int ts, int z_chunk, int* tx, int* ty, int* tz);

@@ -636,7 +636,7 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
 // ---------------------------------------------------------------------------
 // Batched sweep: many independent grids (instances) advanced by one
 // persistent cooperative kernel.  Work items are (instance, tile) pairs of
-// the four-cell stage passes (items[i].x = instance, .y = tile); all items of
+// the vector stage passes (items[i].x = instance, .y = tile); all items of
 // one stage are processed (strided over the workgroups), then a grid-wide
 // barrier, then the next stage; after S5 one workgroup per instance runs that
 // instance's controller on its own control block (own t, dt, status), then a
@@ -891,17 +891,18 @@ __global__ void build_code_kernel(const uint8_t* mask, uint8_t* code, int n1, in
 }
 
 // ---------------------------------------------------------------------------
-// Vectorised stage kernel: each thread owns four consecutive x1-cells (one
-// 16-byte FP32 load per field and plane, two for FP64), so address
-// arithmetic and load issue are shared by four cells.  The x1 neighbours of
-// the four cells come from the thread's own registers and from the adjacent
-// lanes (shuffles); only a lane whose neighbour sits in another wavefront
-// loads it.  Needs n1 % 4 == 0 (each quad lies in one x1 row).  Same
-// arithmetic per cell as stage_kernel.
+// Vector stage kernel: each thread owns one 16-byte vector of consecutive
+// x1-cells (four FP32 or two FP64 cells: one load per field and plane), so
+// address arithmetic and load issue are shared by its cells.  The x1
+// neighbours come from the thread's own registers and from the adjacent lanes
+// (shuffles), the x2 neighbours from LDS.  Needs n1 divisible by the vector
+// width (each vector lies in one x1 row).  Same arithmetic per cell as
+// stage_kernel.
 
 template <typename R>
-struct Quad {
-  R v[4];
+struct Quad {  // one 16-byte vector: four FP32 or two FP64 cells
+  static constexpr int N = 16 / (int)sizeof(R);
+  R v[N];
 };
 
 template <typename R>
@@ -914,12 +915,9 @@ __device__ __forceinline__ Quad<R> ldq(const R* base, uint32_t idx) {
     q.v[2] = t.z;
     q.v[3] = t.w;
   } else {
-    const double2 t0 = *reinterpret_cast<const double2*>(base + idx);
-    const double2 t1 = *reinterpret_cast<const double2*>(base + idx + 2);
-    q.v[0] = t0.x;
-    q.v[1] = t0.y;
-    q.v[2] = t1.x;
-    q.v[3] = t1.y;
+    const double2 t = *reinterpret_cast<const double2*>(base + idx);
+    q.v[0] = t.x;
+    q.v[1] = t.y;
   }
   return q;
 }
@@ -941,12 +939,9 @@ __device__ __forceinline__ Quad<R> ldq_nt(const R* base, uint32_t idx) {
     q.v[2] = t.z;
     q.v[3] = t.w;
   } else {
-    const d2 t0 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(base + idx));
-    const d2 t1 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(base + idx + 2));
-    q.v[0] = t0.x;
-    q.v[1] = t0.y;
-    q.v[2] = t1.x;
-    q.v[3] = t1.y;
+    const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(base + idx));
+    q.v[0] = t.x;
+    q.v[1] = t.y;
   }
   return q;
 }
@@ -957,7 +952,6 @@ __device__ __forceinline__ void stq_plain(R* base, uint32_t idx, const Quad<R>& 
     *reinterpret_cast<float4*>(base + idx) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
   } else {
     *reinterpret_cast<double2*>(base + idx) = make_double2(q.v[0], q.v[1]);
-    *reinterpret_cast<double2*>(base + idx + 2) = make_double2(q.v[2], q.v[3]);
   }
 }
 
@@ -969,9 +963,8 @@ __device__ __forceinline__ void stq_nt(R* base, uint32_t idx, const Quad<R>& q) 
     const f4 t = {q.v[0], q.v[1], q.v[2], q.v[3]};
     __builtin_nontemporal_store(t, reinterpret_cast<f4*>(base + idx));
   } else {
-    const d2 t0 = {q.v[0], q.v[1]}, t1 = {q.v[2], q.v[3]};
-    __builtin_nontemporal_store(t0, reinterpret_cast<d2*>(base + idx));
-    __builtin_nontemporal_store(t1, reinterpret_cast<d2*>(base + idx + 2));
+    const d2 t = {q.v[0], q.v[1]};
+    __builtin_nontemporal_store(t, reinterpret_cast<d2*>(base + idx));
   }
 }
 
@@ -985,25 +978,6 @@ template <bool NT, typename R>
 __device__ __forceinline__ void stq_s(R* base, uint32_t idx, const Quad<R>& q) {
   if constexpr (NT) stq_nt(base, idx, q);
   else stq_plain(base, idx, q);
-}
-
-// Stage value formed from the state and stored derivatives at a quad:
-// Y2 = y + dt k1/3 (S2) or Y4 = y + dt (k1 + 3 k3)/8 (S4); the same
-// expressions, operation for operation, as in the one-cell kernel.
-template <int STAGE, typename R>
-__device__ __forceinline__ Quad<R> stage_value(const R* y, const R* q1, const R* q3, R rdt,
-                                               uint32_t i) {
-  Quad<R> a = ldq(y, i);
-  const Quad<R> b = ldq(q1, i);
-  if constexpr (STAGE == 2) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) a.v[k] = a.v[k] + rdt * (R(1.0 / 3.0) * b.v[k]);
-  } else {
-    const Quad<R> c = ldq(q3, i);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) a.v[k] = a.v[k] + rdt * (R(0.125) * (b.v[k] + R(3) * c.v[k]));
-  }
-  return a;
 }
 
 template <typename R>
@@ -1035,7 +1009,8 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
 
   const int tp = tile % a.tiles_p, tz = tile / a.tiles_p;
   const uint32_t plane = (uint32_t)m.n1 * (uint32_t)m.n2;
-  const uint32_t p = ((uint32_t)tp * kBlock + threadIdx.x) * 4u;
+  constexpr int VW = Quad<R>::N;  // cells per thread
+  const uint32_t p = ((uint32_t)tp * kBlock + threadIdx.x) * (uint32_t)VW;
   const bool active = p < plane;
   const int z0 = tz * a.z_chunk;
   const int z1 = min(z0 + a.z_chunk, m.n3);
@@ -1077,7 +1052,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       Quad<R> q3, o;
       if constexpr (STAGE == 4) q3 = ldq(k3[v], i);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < VW; ++k) {
         if constexpr (STAGE == 2) o.v[k] = y0.v[k] + rdt * (R(1.0 / 3.0) * q1.v[k]);
         else o.v[k] = y0.v[k] + rdt * (R(0.125) * (q1.v[k] + R(3) * q3.v[k]));
       }
@@ -1095,17 +1070,17 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   // buffered: [v][W] quads with W = kBlock + 2 Q, run at slot Q + t.  The x3
   // neighbours come from a register window, x1 neighbours inside a wavefront
   // from lane shuffles.
-  const uint32_t Q = (uint32_t)m.n1 >> 2, nq = plane >> 2, W = kBlock + 2u * Q;
+  const uint32_t Q = (uint32_t)m.n1 / VW, nq = plane / VW, W = kBlock + 2u * Q;
   const uint32_t t = threadIdx.x, q0 = (uint32_t)tp * kBlock;
   Quad<R>* lds = static_cast<Quad<R>*>(lds_raw);
-  // the quad's position (n1 % 4 == 0: all four cells share i2)
+  // the vector's position (n1 % VW == 0: its cells share i2)
   const uint32_t i1 = active ? p % (uint32_t)m.n1 : 0u;
   const uint32_t i2 = active ? p / (uint32_t)m.n1 : 0u;
-  const bool xm_in = i1 > 0, xp_in = i1 + 4 < (uint32_t)m.n1;
+  const bool xm_in = i1 > 0, xp_in = i1 + VW < (uint32_t)m.n1;
   const bool ym_in = i2 > 0, yp_in = i2 + 1 < (uint32_t)m.n2;
   // lanes whose x-neighbour quad lives in another wavefront (read from LDS)
   const bool xm_remote = xm_in && (lane == 0);
-  const bool xp_remote = xp_in && (lane == 63 || p + 4 >= plane);
+  const bool xp_remote = xp_in && (lane == 63 || p + VW >= plane);
   const unsigned dirf = (unsigned)m.dirichlet_faces;
 
   // z window of the stencil input, and k1 at the cell (S2)
@@ -1126,7 +1101,8 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     R xl[2], xr[2];
     uint32_t codes = 0;
     if (active) {
-      codes = *reinterpret_cast<const uint32_t*>(a.code + n);
+      if constexpr (VW == 4) codes = *reinterpret_cast<const uint32_t*>(a.code + n);
+      else codes = *reinterpret_cast<const uint16_t*>(a.code + n);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         cp[v] = zp_in ? ldin(v, n + plane, rp[v]) : cc[v];
@@ -1140,20 +1116,21 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       if (hq >= 0 && hq < (long long)nq) {
         const uint32_t sl = h < Q ? h : h + kBlock;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) L[v * W + sl] = ldin(v, zoff + (uint32_t)hq * 4u, nullptr);
+        for (int v = 0; v < NV; ++v)
+          L[v * W + sl] = ldin(v, zoff + (uint32_t)hq * (uint32_t)VW, nullptr);
       }
     }
     __syncthreads();
     // x neighbours of the end cells: adjacent lanes, or LDS across waves
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      xl[v] = shfl_up1(cc[v].v[3]);
+      xl[v] = shfl_up1(cc[v].v[VW - 1]);
       xr[v] = shfl_down1(cc[v].v[0]);
-      if (active && xm_remote) xl[v] = L[v * W + Q + t - 1].v[3];
+      if (active && xm_remote) xl[v] = L[v * W + Q + t - 1].v[VW - 1];
       if (active && xp_remote) xr[v] = L[v * W + Q + t + 1].v[0];
       // a boundary face carries the cell's own value
       if (!xm_in) xl[v] = cc[v].v[0];
-      if (!xp_in) xr[v] = cc[v].v[3];
+      if (!xp_in) xr[v] = cc[v].v[VW - 1];
       ym[v] = cc[v];
       yp[v] = cc[v];
       if (active && ym_in) ym[v] = L[v * W + t];
@@ -1164,19 +1141,20 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
                              (zp_in ? 32u : 0u);
       Quad<R> kq[2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const unsigned inb = inb_c | ((k > 0 || xm_in) ? 1u : 0u) | ((k < 3 || xp_in) ? 2u : 0u);
+      for (int k = 0; k < VW; ++k) {
+        const unsigned inb =
+            inb_c | ((k > 0 || xm_in) ? 1u : 0u) | ((k < VW - 1 || xp_in) ? 2u : 0u);
         const unsigned code = (codes >> (8 * k)) & 0xffu;
         R phn[6], thn[6];
         phn[0] = k > 0 ? cc[0].v[k - 1] : xl[0];
-        phn[1] = k < 3 ? cc[0].v[k + 1] : xr[0];
+        phn[1] = k < VW - 1 ? cc[0].v[k + 1] : xr[0];
         phn[2] = ym[0].v[k];
         phn[3] = yp[0].v[k];
         phn[4] = cm[0].v[k];
         phn[5] = cp[0].v[k];
         if (kCoupled) {
           thn[0] = k > 0 ? cc[1].v[k - 1] : xl[1];
-          thn[1] = k < 3 ? cc[1].v[k + 1] : xr[1];
+          thn[1] = k < VW - 1 ? cc[1].v[k + 1] : xr[1];
           thn[2] = ym[1].v[k];
           thn[3] = yp[1].v[k];
           thn[4] = cm[1].v[k];
@@ -1203,7 +1181,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         } else if (STAGE == 2) {
           const Quad<R>& q1 = rc[v][1];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
+          for (int k = 0; k < VW; ++k)
             o.v[k] = cc[v].v[k] + rdt * (R(1.0 / 6.0) * (kk.v[k] - q1.v[k]));
           stq_s<NT>(out[v], n, o);
         } else if (STAGE == 3) {
@@ -1213,7 +1191,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
           const Quad<R> y0 = ldq(yv[v], n), q1 = ldq(k1[v], n), q3 = ldq(k3[v], n);
           Quad<R> P, Cc;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < VW; ++k) {
             o.v[k] = y0.v[k] + rdt * (R(0.5) * q1.v[k] - R(1.5) * q3.v[k] + R(2) * kk.v[k]);
             P.v[k] = y0.v[k] + rdt * (R(1.0 / 6.0) * (q1.v[k] + R(4) * kk.v[k]));
             Cc.v[k] = rdt * (R(1.0 / 30.0) * (R(2) * q1.v[k] - R(9) * q3.v[k] + R(8) * kk.v[k]));
@@ -1224,7 +1202,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         } else if (STAGE == 5) {
           const Quad<R> P = ldq_s<NT>(k1[v], n), Cc = ldq_s<NT>(k3[v], n);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < VW; ++k) {
             o.v[k] = P.v[k] + rdt * (R(1.0 / 6.0) * kk.v[k]);
             const double e = (double)Cc.v[k] - dt * ((1.0 / 30.0) * (double)kk.v[k]);
             red0 = dmax_nf(red0, fabs(e));
@@ -1553,9 +1531,9 @@ __global__ __launch_bounds__(TX* TY) void pair_kernel(PairArgs a) {
 // ---------------------------------------------------------------------------
 // Host launchers
 
-int grid_blocks(const ModelConst& mc, int z_chunk, int vec, int* tiles_p, int* tiles_z) {
+int grid_blocks(const ModelConst& mc, int z_chunk, int cells, int* tiles_p, int* tiles_z) {
   const long long plane = (long long)mc.n1 * mc.n2;
-  const long long per = vec ? 4LL * kBlock : kBlock;
+  const long long per = (long long)cells * kBlock;
   *tiles_p = (int)((plane + per - 1) / per);
   *tiles_z = (mc.n3 + z_chunk - 1) / z_chunk;
   return (*tiles_p) * (*tiles_z);

@@ -17,12 +17,14 @@ import paper_2401_01672_amd as pf  # noqa: E402
 
 
 def small_instances(k, precision="fp32", fixed_dt=None, seed0=500):
-    """k micro-scale instances of uneven sizes (n1 divisible by 4), each with
-    its own supercooling and surface-tension scale."""
+    """k micro-scale instances of uneven sizes (n1 divisible by the vector
+    width: 4 in FP32, 2 in FP64), each with its own supercooling and
+    surface-tension scale."""
     rng = np.random.default_rng(seed0)
     out = []
+    widths = [8, 12, 16, 20, 24] if precision == "fp32" else [6, 10, 16, 18, 22]
     for i in range(k):
-        n1 = int(rng.choice([8, 12, 16, 20, 24]))
+        n1 = int(rng.choice(widths))
         n2 = int(rng.integers(5, 19))
         n3 = int(rng.integers(4, 23))
         c = pi.sweep_instance(seed0 + i, edge=48)

@@ -106,14 +106,17 @@ def test_every_pair_tile_matches_oracle(ts, zc):
     assert rel(ph, ph_o) <= 1e-12 and rel(th, T_o - T_STAR) <= 1e-12
 
 
-VEC_SHAPES = [(7, 5, 260), (9, 3, 12), (4, 6, 20), (3, 2, 4), (1, 1, 8), (13, 33, 64)]
+# n1 = 260 (65 FP32 / 130 FP64 vectors per row: rows straddle wavefronts);
+# n1 = 6 and 130: FP64 vectors only (n1 not divisible by 4)
+VEC_SHAPES = [(7, 5, 260), (9, 3, 12), (4, 6, 20), (3, 2, 4), (1, 1, 8), (13, 33, 64),
+              (5, 7, 6), (3, 4, 130)]
 
 
 @pytest.mark.parametrize("model", ["ac", "coupled"])
 @pytest.mark.parametrize("shape", VEC_SHAPES)
-def test_four_cell_kernels_match_oracle(model, shape):
-    """n1 % 4 == 0 selects the four-cells-per-thread stage kernels; rows of
-    65 quads (n1 = 260) straddle wavefronts and exercise the remote loads."""
+def test_vector_kernels_match_oracle(model, shape):
+    """FP64 runs on the vector stage kernels (two cells per thread) where n1
+    is even; rows longer than a wavefront exercise the LDS neighbour reads."""
     for trial, faces in enumerate((0, 63, 1 | 2)):
         p, mask, phi, T = rand_problem(shape, model, 70 + trial, faces=faces, bc_kind=trial % 3)
         P = oracle.make_params(p)
@@ -134,7 +137,7 @@ def test_four_cell_kernels_match_oracle(model, shape):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_four_cell_equals_one_cell(precision):
+def test_vector_equals_one_cell(precision):
     p, mask, phi, T = rand_problem((21, 19, 260), "coupled", 12, faces=1 << 4, bc_kind=1)
     outs = []
     for vec in (True, False):
