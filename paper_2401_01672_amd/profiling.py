@@ -116,7 +116,17 @@ def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_
         if not fk or not wk:
             continue
         f_kib, w_kib = fk[len(fk) // 2], wk[len(wk) // 2]  # median dispatch
+        run_cmd = (f"python3 -m paper_2401_01672_amd.profiling run --workload {workload}"
+                   + (f" --schedule {schedule}" if schedule != "five" else ""))
         rec = dict(workload=workload, schedule=schedule, kernel=f"{schedule}_pass{p}",
+                   commands=[
+                       "cd /tmp && export TMPDIR=/tmp && cd /root/repo",
+                       f"rocprofv3 --pmc FETCH_SIZE -d {fetch_dir} -o run --output-format csv "
+                       f"-- {run_cmd}",
+                       f"rocprofv3 --pmc WRITE_SIZE -d {write_dir} -o run --output-format csv "
+                       f"-- {run_cmd}",
+                       f"python3 -m paper_2401_01672_amd.profiling summarize --workload {workload}"
+                       f" --fetch {fetch_dir} --write {write_dir}"],
                    source_hash=sh, dispatches=len(fk),
                    fetch_kib_per_dispatch=f_kib, write_kib_per_dispatch=w_kib,
                    fetch_scale=fr, write_scale=wr,
