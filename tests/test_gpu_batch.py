@@ -182,3 +182,31 @@ def test_sweep_instances_batch_to_equilibrium_small_subset():
         assert np.array_equal(ss[i].get_state()[0], s.get_state()[0]), i
     for s in ss + single:
         s.close()
+
+
+def test_sweep_fp32_batch_matches_fp64_runs():
+    """Four 48^3 instances of the sweep generator: the FP32 batch run to
+    equilibrium against FP64 single runs to equilibrium.  The FP32 trajectory
+    differs by rounding, so the comparison is on what the run is for: both
+    reach equilibrium and give the same unfrozen water content (eq.
+    UWC-formula) to within 1e-3 of the water cells."""
+    cases = [pi.sweep_instance(4000 + i) for i in (5, 9, 17, 27)]
+    ss = []
+    for c in cases:
+        s = pf.Solver(c.params, c.mask, "fp32", c.run)
+        s.set_state(c.phi0.astype(np.float32))
+        s.set_time(0.0, c.run["dt0"])
+        ss.append(s)
+    stats = pf.batch_integrate(ss, max_steps=400000, eq_tol=1e-6)
+    for c, st32 in zip(cases, stats):
+        s64 = pf.Solver(c.params, c.mask, "fp64", c.run)
+        s64.set_state(c.phi0)
+        s64.set_time(0.0, c.run["dt0"])
+        st64 = s64.integrate(max_steps=400000, eq_tol=1e-6)
+        s64.close()
+        assert st32["status"] == st64["status"] == pf.PF_EQUILIBRIUM
+        assert st32["pore_count"] == st64["pore_count"]
+        d_uwc = abs(st32["ice_count"] - st64["ice_count"]) / st64["pore_count"]
+        assert d_uwc <= 1e-3, (c.name, st32["ice_count"], st64["ice_count"])
+    for s in ss:
+        s.close()
