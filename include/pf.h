@@ -271,11 +271,13 @@ int pf_set_vector(pf_handle* h, int32_t enable);
  * autotuner off. */
 int pf_set_pair_tile(pf_handle* h, int32_t tile_index, int32_t z_chunk);
 
-/* Current configuration, out[0..8] = {schedule, passes per attempt,
+/* Current configuration, out[0..13] = {schedule, passes per attempt,
  * single-stage z_chunk, single-stage workgroups, pair tile x, pair tile y,
- * pair z_chunk, pair workgroups, vector kernels (1) or one-cell (0)}
- * (after the autotuner, if it has run; it times both kernel forms unless
- * pf_set_vector fixed one). */
+ * pair z_chunk, pair workgroups, vector kernels (1) or one-cell (0),
+ * z_chunk of S1, S2, S3, S4, S5} (after the autotuner, if it has run: it
+ * times both kernel forms unless pf_set_vector fixed one, and picks the
+ * planes per workgroup column of each stage pass separately; the
+ * single-stage z_chunk is then S4's).  out must hold 14 values. */
 int pf_get_config(const pf_handle* h, int32_t* out);
 
 /* Time each kernel of one attempt from the current state and step: the

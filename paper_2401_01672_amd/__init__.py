@@ -323,12 +323,12 @@ class Solver:
         self._check(lib().pf_set_pair_tile(self.h, int(tile_index), int(z_chunk)))
 
     def get_config(self) -> Dict:
-        out = (C.c_int32 * 9)()
+        out = (C.c_int32 * 14)()
         self._check(lib().pf_get_config(self.h, out))
         v = list(out)
         return dict(schedule={0: "five", 1: "paired"}[v[0]], passes=v[1], z_chunk=v[2],
                     workgroups=v[3], pair_tile=(v[4], v[5]), pair_z_chunk=v[6],
-                    pair_workgroups=v[7], vector=bool(v[8]))
+                    pair_workgroups=v[7], vector=bool(v[8]), stage_z_chunk=v[9:14])
 
     def time_kernels(self, reps: int = 10):
         out = (C.c_double * 6)()

@@ -49,8 +49,10 @@ struct pf_handle {
   int vec = 0;  // vector stage kernels (one 16-byte vector of x1-cells per thread)
   int vec_fixed = 0;  // set by pf_set_vector: the autotuner keeps vec
   int stream_nt = 0;  // non-temporal streams: working set far above the caches
-  int z_chunk = 16;  // single-stage passes
+  int z_chunk = 16;  // single-stage passes (the RHS pass, batches, uniform choice)
   int tiles_p = 0, tiles_z = 0, nparts = 0, max_parts = 0;
+  // per stage pass S1..S5 (index 1..5): planes per workgroup column and grid
+  int st_z[6] = {0}, st_tp[6] = {0}, st_tz[6] = {0}, st_np[6] = {0};
   int pair_ts = 1, pair_zc = 16;  // paired passes: tile shape index, planes per column
   int ptx = 0, pty = 0, ptz = 0, npair = 0;
   int autotune_pending = 1;
@@ -172,9 +174,10 @@ StageArgs stage_args(const pf_handle* h, int stage) {
   a.G = h->G;
   a.ctl = h->ctl;
   a.mc = h->mc;
-  a.z_chunk = h->z_chunk;
-  a.tiles_p = h->tiles_p;
-  a.tiles_z = h->tiles_z;
+  const bool own = stage >= 1 && stage <= 5;
+  a.z_chunk = own ? h->st_z[stage] : h->z_chunk;
+  a.tiles_p = own ? h->st_tp[stage] : h->tiles_p;
+  a.tiles_z = own ? h->st_tz[stage] : h->tiles_z;
   a.vec = h->vec;
   a.stream_nt = h->stream_nt;
   for (int v = 0; v < 2; ++v) {
@@ -270,8 +273,8 @@ hipError_t issue_pass(const pf_handle* h, int i, hipStream_t s) {
 int num_passes(const pf_handle* h) { return h->sched == pf::kSchedFive ? 5 : 3; }
 
 hipError_t launch_ctl(const pf_handle* h, DevCtl* ctl, hipStream_t s) {
-  const int np1 = h->sched == pf::kSchedFive ? h->nparts : h->npair;
-  return pf::launch_controller(ctl, h->part1, np1, h->part5, h->nparts, h->mc.h3, s);
+  const int np1 = h->sched == pf::kSchedFive ? h->st_np[1] : h->npair;
+  return pf::launch_controller(ctl, h->part1, np1, h->part5, h->st_np[5], h->mc.h3, s);
 }
 
 hipError_t issue_step(const pf_handle* h, hipStream_t s) {
@@ -300,6 +303,27 @@ int set_tiles(pf_handle* h, int zc) {
   h->tiles_p = tp;
   h->tiles_z = tz;
   h->nparts = nb;
+  for (int st = 1; st <= 5; ++st) {
+    h->st_z[st] = zc;
+    h->st_tp[st] = tp;
+    h->st_tz[st] = tz;
+    h->st_np[st] = nb;
+  }
+  drop_graph(h);
+  return PF_OK;
+}
+
+// Planes per workgroup column of one stage pass (1..5) alone.
+int set_stage_tiles(pf_handle* h, int st, int zc) {
+  if (zc < 1) zc = 1;
+  if (zc > h->P.n3) zc = h->P.n3;
+  int tp, tz;
+  int nb = pf::grid_blocks(h->mc, zc, h->vec ? pf::vec_cells(h->esize) : 1, &tp, &tz);
+  if (nb > h->max_parts) return fail(h, PF_EINVAL, "tile choice exceeds partial buffer");
+  h->st_z[st] = zc;
+  h->st_tp[st] = tp;
+  h->st_tz[st] = tz;
+  h->st_np[st] = nb;
   drop_graph(h);
   return PF_OK;
 }
@@ -379,38 +403,68 @@ int autotune(pf_handle* h) {
     *out = tot;
     return PF_OK;
   };
-  // (1) planes per column of the single-stage passes, and (unless the caller
-  // fixed it) vector or one-cell kernels
+  // (1) planes per column of each single-stage pass, and (unless the caller
+  // fixed it) vector or one-cell kernels.  For every candidate depth the five
+  // passes run in attempt order with an event between each two (each reads
+  // what its predecessor wrote, as in a run); each pass keeps its fastest
+  // depth (median of three timed repetitions after a warm-up), and the kernel
+  // form with the smaller sum of per-pass minima wins.
   const int zcands[] = {1, 2, 4, 8, 16, 32};
-  int best = h->z_chunk, best_vec = h->vec;
-  float best_ms = 1e30f;
+  int best_vec = h->vec, best_z[6] = {0, h->z_chunk, h->z_chunk, h->z_chunk, h->z_chunk,
+                                      h->z_chunk};
+  float best_total = 1e30f;
   const bool try_both = !h->vec_fixed && vector_ok(h->P, h->smooth);
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) PF_HIP(h, hipEventCreate(&ev[i]));
   for (int vec = 1; vec >= 0; --vec) {
     if (!try_both && vec != h->vec) continue;
     h->vec = vec;
+    float bst[6];
+    int bz[6] = {0, 0, 0, 0, 0, 0};
+    for (int st = 0; st < 6; ++st) bst[st] = 1e30f;
     for (int zc : zcands) {
       if (zc > h->P.n3 && zc != zcands[0]) continue;
       if (set_tiles(h, zc)) continue;
-      float ms;
-      rc = timed([&]() -> hipError_t {
+      float reps[3][6];
+      for (int rep = 0; rep < 4; ++rep) {
+        PF_HIP(h, hipEventRecord(ev[0], h->stream));
         for (int st = 1; st <= 5; ++st) {
           StageArgs a = stage_args(h, st);
-          hipError_t e = pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream);
-          if (e != hipSuccess) return e;
+          PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, st, a, h->stream));
+          PF_HIP(h, hipEventRecord(ev[st], h->stream));
         }
-        return hipSuccess;
-      }, &ms);
-      if (rc) return rc;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = zc;
-        best_vec = vec;
+        PF_HIP(h, hipEventSynchronize(ev[5]));
+        if (rep == 0) continue;
+        for (int st = 1; st <= 5; ++st)
+          PF_HIP(h, hipEventElapsedTime(&reps[rep - 1][st], ev[st - 1], ev[st]));
+      }
+      for (int st = 1; st <= 5; ++st) {
+        float a0 = reps[0][st], a1 = reps[1][st], a2 = reps[2][st];
+        const float med = a0 > a1 ? (a1 > a2 ? a1 : (a0 > a2 ? a2 : a0))
+                                  : (a0 > a2 ? a0 : (a1 > a2 ? a2 : a1));
+        if (med < bst[st]) {
+          bst[st] = med;
+          bz[st] = zc;
+        }
       }
     }
+    float total = 0.0f;
+    for (int st = 1; st <= 5; ++st) total += bst[st];
+    if (total < best_total) {
+      best_total = total;
+      best_vec = vec;
+      for (int st = 1; st <= 5; ++st) best_z[st] = bz[st];
+    }
   }
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   h->vec = best_vec;
-  rc = set_tiles(h, best);
+  rc = set_tiles(h, best_z[4]);  // the RHS pass and the reported depth follow S4
   if (rc) return rc;
+  for (int st = 1; st <= 5; ++st) {
+    rc = set_stage_tiles(h, st, best_z[st]);
+    if (rc) return rc;
+  }
+  float best_ms = 1e30f;
   // (2) tile shape and planes per column of the paired passes
   if (h->sched == pf::kSchedPaired) {
     const int pz[] = {8, 16, 32, 64};
@@ -1152,6 +1206,7 @@ int pf_get_config(const pf_handle* h, int32_t* out) {
   out[6] = h->pair_zc;
   out[7] = h->npair;
   out[8] = h->vec;
+  for (int st = 1; st <= 5; ++st) out[8 + st] = h->st_z[st];
   return PF_OK;
 }
 

@@ -1042,10 +1042,12 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     }
   }
   const R rdt = R(dt);
-  // Stencil input quad at cell index i of variable v.  S2 and S4 form their
+  // Stencil input vector at cell index i of variable v.  S2 and S4 form their
   // stage value from the state and the stored derivatives (Y2 = y + dt k1/3,
   // Y4 = y + dt (k1 + 3 k3)/8; the same expressions as the one-cell kernel);
-  // raw (when given) receives the loaded k1 quad (S2 needs it at the cell).
+  // raw (when given) receives the loaded k1 (S2) or y, k1, k3 (S4), which the
+  // pass needs again at the cell one plane later (kept in registers: a reload
+  // misses the L2 on large grids).
   auto ldin = [&](int v, uint32_t i, Quad<R>* raw) -> Quad<R> {
     if constexpr (STAGE == 2 || STAGE == 4) {
       const Quad<R> y0 = ldq(yv[v], i), q1 = ldq(k1[v], i);
@@ -1056,7 +1058,13 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         if constexpr (STAGE == 2) o.v[k] = y0.v[k] + rdt * (R(1.0 / 3.0) * q1.v[k]);
         else o.v[k] = y0.v[k] + rdt * (R(0.125) * (q1.v[k] + R(3) * q3.v[k]));
       }
-      if (raw) raw[1] = q1;
+      if (raw) {
+        raw[1] = q1;
+        if constexpr (STAGE == 4) {
+          raw[0] = y0;
+          raw[2] = q3;
+        }
+      }
       return o;
     } else {
       return ldq(in[v], i);
@@ -1083,9 +1091,9 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   const bool xp_remote = xp_in && (lane == 63 || p + VW >= plane);
   const unsigned dirf = (unsigned)m.dirichlet_faces;
 
-  // z window of the stencil input, and k1 at the cell (S2)
+  // z window of the stencil input, and the cell's own k1 (S2) or y, k1, k3 (S4)
   Quad<R> cm[2], cc[2], cp[2];
-  Quad<R> rc[2][2], rp[2][2];
+  Quad<R> rc[2][3], rp[2][3];
   uint32_t n = p + plane * (uint32_t)z0;
   if (active) {
 #pragma unroll
@@ -1187,8 +1195,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         } else if (STAGE == 3) {
           stq_s<NT>(k3[v], n, kk);
         } else if (STAGE == 4) {
-          // the cell's y, k1, k3 were loaded one plane earlier: cache hits
-          const Quad<R> y0 = ldq(yv[v], n), q1 = ldq(k1[v], n), q3 = ldq(k3[v], n);
+          const Quad<R>&y0 = rc[v][0], &q1 = rc[v][1], &q3 = rc[v][2];
           Quad<R> P, Cc;
 #pragma unroll
           for (int k = 0; k < VW; ++k) {
@@ -1215,6 +1222,10 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         cm[v] = cc[v];
         cc[v] = cp[v];
         if constexpr (STAGE == 2) rc[v][1] = rp[v][1];
+        if constexpr (STAGE == 4) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) rc[v][r] = rp[v][r];
+        }
       }
     }
   }

@@ -152,3 +152,29 @@ def test_vector_equals_one_cell(precision):
         s.close()
     tol = 1e-13 if precision == "fp64" else 2e-6
     assert rel(outs[0][0], outs[1][0]) <= tol and rel(outs[0][1], outs[1][1]) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuned_stage_depths_do_not_change_results(precision):
+    """The autotuner picks the planes per workgroup column of each stage pass
+    separately; an adaptive run on its choice is bitwise equal to a run with
+    one depth fixed for all passes (the per-cell arithmetic does not depend on
+    the tiling, and the step-control reductions are maxima)."""
+    p, mask, phi, T = rand_problem((40, 24, 36), "coupled", 31, faces=1 << 4, bc_kind=1)
+    npdt = np.float64 if precision == "fp64" else np.float32
+    outs = []
+    for fixed in (None, 3):
+        s = pf.Solver(p, mask, precision, dict(tol=1e-6))
+        if fixed:
+            s.set_tile(fixed)
+        s.set_state(phi.astype(npdt), (T - T_STAR).astype(npdt))
+        s.set_time(0.0, 1e-3)
+        st = s.integrate(max_steps=40)
+        cfg = s.get_config()
+        outs.append((s.get_state(), st["steps_accepted"], st["steps_rejected"], cfg))
+        s.close()
+    (a, na, ra, cfg_a), (b, nb, rb, cfg_b) = outs
+    assert all(1 <= z <= 40 for z in cfg_a["stage_z_chunk"]), cfg_a
+    assert cfg_b["stage_z_chunk"] == [3] * 5, cfg_b
+    assert (na, ra) == (nb, rb)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
