@@ -490,7 +490,7 @@ __global__ __launch_bounds__(256) void count_water_kernel(const uint8_t* glass, 
   red[threadIdx.x] = c;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
   for (int c = 0; c < 16; ++c) red[2 + c][threadIdx.x] = dz * hv[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
+    if ((int)threadIdx.x < w)
       for (int j = 0; j < kHeadParts; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
     __syncthreads();
   }

@@ -127,7 +127,7 @@ int ufail(pf_unet* n, int code, const std::string& msg) {
   } while (0)
 
 void free_grid(pf_unet* n) {
-  if (n->slab) hipFree(n->slab);
+  if (n->slab) (void)hipFree(n->slab);
   n->slab = nullptr;
   n->n1 = n->n2 = n->n3 = 0;
   n->train = 0;
@@ -496,15 +496,16 @@ int pf_unet_create(uint64_t seed, pf_unet** out) {
 
 void pf_unet_destroy(pf_unet* n) {
   if (!n) return;
-  if (n->stream) hipStreamSynchronize(n->stream);
-  else hipDeviceSynchronize();
+  // teardown: errors here have no caller to report to
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  else (void)hipDeviceSynchronize();
   free_grid(n);
-  if (n->params) hipFree(n->params);
-  if (n->grad) hipFree(n->grad);
-  if (n->adam_m) hipFree(n->adam_m);
-  if (n->adam_v) hipFree(n->adam_v);
-  if (n->wslab) hipFree(n->wslab);
-  if (n->hostbuf) hipHostFree(n->hostbuf);
+  if (n->params) (void)hipFree(n->params);
+  if (n->grad) (void)hipFree(n->grad);
+  if (n->adam_m) (void)hipFree(n->adam_m);
+  if (n->adam_v) (void)hipFree(n->adam_v);
+  if (n->wslab) (void)hipFree(n->wslab);
+  if (n->hostbuf) (void)hipHostFree(n->hostbuf);
   delete n;
 }
 
@@ -641,11 +642,14 @@ int pf_unet_time_layers(pf_unet* n, int32_t n1, int32_t n2, int32_t n3, int32_t 
       break;
     }
     float t = 0.0f;
-    hipEventElapsedTime(&t, e0, e1);
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      rc = ufail(n, PF_EHIP, "event elapsed time");
+      break;
+    }
     ms[i] = (double)t / reps;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return rc;
 }
 
@@ -698,7 +702,7 @@ int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b
   a.variant = 1;
   if (rc == PF_OK && pfu::launch_conv_fwd(a, s) != hipSuccess) rc = PF_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;
-  hipFree(wf);
+  (void)hipFree(wf);
   return rc;
 }
 
@@ -720,7 +724,7 @@ int pf_conv3_bf16_backward(const uint16_t* x, int32_t cin, const float* w, const
   if (hipMalloc(&part, npart * sizeof(float)) != hipSuccess) return PF_ENOMEM;
   if (hipMalloc(&wbuf, ((size_t)cout * kpad + (size_t)cin * kpad_t) * sizeof(uint16_t)) !=
       hipSuccess) {
-    hipFree(part);
+    (void)hipFree(part);
     return PF_ENOMEM;
   }
   int rc = PF_OK;
@@ -763,8 +767,8 @@ int pf_conv3_bf16_backward(const uint16_t* x, int32_t cin, const float* w, const
     if (rc == PF_OK && pfu::launch_conv_fwd(a, s) != hipSuccess) rc = PF_EHIP;
   }
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;
-  hipFree(part);
-  hipFree(wbuf);
+  (void)hipFree(part);
+  (void)hipFree(wbuf);
   return rc;
 }
 
