@@ -315,8 +315,9 @@ def run_gpu(args, wl):
 
 def cpu_baseline(wl, sample_steps: int):
     """The FP64 oracle (as it stands) on the same grid for a bounded number of
-    adaptive attempts, timed on this host's cores."""
-    import numpy as np
+    adaptive attempts, timed on this host's cores (all of them, and one: the
+    single-thread rate from a tenth of the sample goes into the detail)."""
+    import ctypes
 
     import oracle
     import pf_inputs as pi
@@ -324,19 +325,35 @@ def cpu_baseline(wl, sample_steps: int):
     case = getattr(pi, wl["case"])(**wl.get("case_args", {}))
     params = dict(case.params, **wl.get("override", {}))
     P = oracle.make_params(params)
-    ctl = oracle.make_ctl(tol=case.run["tol"])
     T0 = case.T0
     phi0 = None if params.get("model") == "temp" else case.phi0
-    t0 = time.perf_counter()
     G = case.mask if case.G is None else case.G
-    _, _, st = oracle.integrate(P, G, ctl, 0.0, case.run["dt0"], phi0, T0,
-                                max_steps=sample_steps)
-    wall = time.perf_counter() - t0
-    n = st["steps_accepted"] + st["steps_rejected"]
-    return dict(value=round(case.ncells * n / wall / 1e9, 5), unit="GCUPS",
-                cores=oracle.num_threads(), kind="oracle",
-                sample=f"{n} adaptive RKM attempts of the same {case.shape[::-1]} grid in "
-                       f"FP64 ({wall:.1f} s)")
+
+    def timed(steps):
+        ctl = oracle.make_ctl(tol=case.run["tol"])
+        t0 = time.perf_counter()
+        _, _, st = oracle.integrate(P, G, ctl, 0.0, case.run["dt0"], phi0, T0, max_steps=steps)
+        wall = time.perf_counter() - t0
+        n = st["steps_accepted"] + st["steps_rejected"]
+        return n, wall, case.ncells * n / wall / 1e9
+
+    cores = oracle.num_threads()
+    n, wall, rate = timed(sample_steps)
+    out = dict(value=round(rate, 5), unit="GCUPS", cores=cores, kind="oracle",
+               sample=f"{n} adaptive RKM attempts of the same {case.shape[::-1]} grid in "
+                      f"FP64 ({wall:.1f} s)")
+    if cores > 1:
+        try:  # the oracle's OpenMP runtime, already loaded by the oracle library
+            gomp = ctypes.CDLL("libgomp.so.1")
+        except OSError:
+            gomp = None
+        if gomp is not None:
+            gomp.omp_set_num_threads(1)
+            n1, wall1, rate1 = timed(max(1, sample_steps // 10))
+            gomp.omp_set_num_threads(cores)
+            out["single_thread"] = dict(value=round(rate1, 6), attempts=n1,
+                                        wall_s=round(wall1, 2))
+    return out
 
 
 def main():
