@@ -258,8 +258,8 @@ int pf_set_schedule(pf_handle* h, int32_t schedule);
 
 /* Single-stage passes on vector kernels, one 16-byte vector of consecutive
  * x1-cells per thread (4 FP32 or 2 FP64 cells; n1 must be divisible by that
- * width and the SigmaP1-P AC or coupled model on a voxel mask is required,
- * PF_EINVAL otherwise), or on one-cell kernels.  The two forms store
+ * width and the glass must be a voxel mask, PF_EINVAL otherwise; every model
+ * and reaction), or on one-cell kernels.  The two forms store
  * different intermediate stage values (the vector passes form Y2 and Y4 at
  * the stencil points from y, k1 and k3; the one-cell passes store them) and
  * give the same results.  The default is the vector form where it applies;

@@ -118,19 +118,19 @@ void fill_model_const(const pf_params& P, ModelConst& m) {
   m.inv_h = 1.0 / P.h;
 }
 
-// the vector, paired and batched kernels implement the SigmaP1-P phase
-// equation of the AC and coupled models only
+// the paired and batched kernels implement the SigmaP1-P phase equation of
+// the AC and coupled models on a voxel mask only
 bool simple_kernels_only(const pf_params& P, int smooth) {
   return P.model == PF_MODEL_TEMP || P.reaction != PF_REACT_SIGMA || smooth;
 }
 
 // The vector kernels: n1 divisible by the vector width (4 FP32 or 2 FP64
-// cells), the SigmaP1-P AC or coupled model on the voxel mask, and a plane
-// run with its neighbour rows within the LDS budget.
+// cells), a voxel mask (no smooth glass field), and a plane run with its
+// neighbour rows within the LDS budget.  Every model and reaction.
 static bool vector_ok(const pf_params& P, int smooth) {
   const int nvar = P.model == PF_MODEL_COUPLED ? 2 : 1;
   const int esize = P.precision == PF_FP64 ? 8 : 4;
-  return P.n1 % pf::vec_cells(esize) == 0 && !simple_kernels_only(P, smooth) &&
+  return P.n1 % pf::vec_cells(esize) == 0 && !smooth &&
          pf::stage4_lds_bytes(P.n1, nvar, esize) <= pf::kStage4MaxLds;
 }
 
@@ -765,8 +765,8 @@ int pf_set_vector(pf_handle* h, int32_t enable) {
   if (!h) return PF_EINVAL;
   if (enable && h->P.n1 % pf::vec_cells(h->esize) != 0)
     return fail(h, PF_EINVAL, "vector kernels need n1 divisible by 4 (FP32) or 2 (FP64)");
-  if (enable && simple_kernels_only(h->P, h->smooth))
-    return fail(h, PF_EINVAL, "vector kernels implement the SigmaP1-P AC and coupled models only");
+  if (enable && h->smooth)
+    return fail(h, PF_EINVAL, "vector kernels need a voxel mask (no smooth glass field)");
   if (enable && !vector_ok(h->P, h->smooth))
     return fail(h, PF_EINVAL, "vector kernels: n1 too large for their LDS plane buffers");
   h->vec = enable ? 1 : 0;

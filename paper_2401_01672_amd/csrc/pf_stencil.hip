@@ -646,7 +646,7 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
 // leaves the loop at the same point (the exit test reads the control blocks
 // after a barrier).
 
-template <typename R, int MODEL, int STAGE, bool NT = false>
+template <typename R, int MODEL, int STAGE, bool NT = false, int REACT = PF_REACT_SIGMA>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile, const int slot,
                                             double* smem, void* lds);
 
@@ -989,7 +989,7 @@ __device__ __forceinline__ R shfl_down1(R v) {
   return __shfl_down(v, 1, 64);
 }
 
-template <typename R, int MODEL, int STAGE, bool NT>
+template <typename R, int MODEL, int STAGE, bool NT, int REACT>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
                                             const int slot, double* smem, void* lds_raw) {
   const ModelConst& m = a.mc;
@@ -1172,11 +1172,14 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
           for (int f = 0; f < 6; ++f) thn[f] = R(0);
         }
         R kp, kt;
-        CellRHS<R, MODEL>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn, thn, code,
-                                inb, dirf, thD, kp, kt);
+        // Temp model: the single unknown (theta) travels in the first slot
+        CellRHS<R, MODEL, REACT>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn, thn,
+                                       code, inb, dirf, thD, kp, kt);
         kq[0].v[k] = kp;
         kq[1].v[k] = kt;
-        if (STAGE == 1 && !(code & kGlassBit)) red0 = dmax_nf(red0, fabs((double)kp));
+        // equilibrium measure (no phase-field equation in the Temp model)
+        if (STAGE == 1 && MODEL != PF_MODEL_TEMP && !(code & kGlassBit))
+          red0 = dmax_nf(red0, fabs((double)kp));
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1249,12 +1252,12 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   }
 }
 
-template <typename R, int MODEL, int STAGE, bool NT = false>
+template <typename R, int MODEL, int STAGE, bool NT = false, int REACT = PF_REACT_SIGMA>
 __global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
   extern __shared__ __align__(16) unsigned char pf_stage_lds[];
-  stage4_tile<R, MODEL, STAGE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem,
-                                   pf_stage_lds);
+  stage4_tile<R, MODEL, STAGE, NT, REACT>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem,
+                                          pf_stage_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1586,32 +1589,46 @@ static hipError_t launch_simple_t(int stage, const StageArgs& a, hipStream_t s) 
                      : launch_scalar_t<R, MODEL, PF_REACT_SIGMA, 0>(stage, a, s);
 }
 
+template <typename R, int MODEL, int REACT>
+static hipError_t launch_vector_t(int stage, const StageArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
+  const size_t lds = stage4_lds_bytes(a.mc.n1, MODEL == PF_MODEL_COUPLED ? 2 : 1, sizeof(R));
+  if (lds > kStage4MaxLds) return hipErrorInvalidValue;
+#define PF_S4(S)                                                                          \
+  do {                                                                                    \
+    if (a.stream_nt)                                                                      \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true, REACT>), grid, block, lds, s, a);  \
+    else                                                                                  \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false, REACT>), grid, block, lds, s, a); \
+  } while (0)
+  switch (stage) {
+    case 0: PF_S4(0); break;
+    case 1: PF_S4(1); break;
+    case 2: PF_S4(2); break;
+    case 3: PF_S4(3); break;
+    case 4: PF_S4(4); break;
+    case 5: PF_S4(5); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PF_S4
+  return hipGetLastError();
+}
+
 template <typename R, int MODEL>
 static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
-  if (a.mc.reaction == PF_REACT_GRADP || a.mc.smooth) return launch_simple_t<R, MODEL>(stage, a, s);
+  if (a.mc.smooth) return launch_simple_t<R, MODEL>(stage, a, s);
   if (a.vec) {
-    const size_t lds = stage4_lds_bytes(a.mc.n1, MODEL == PF_MODEL_COUPLED ? 2 : 1, sizeof(R));
-    if (lds > kStage4MaxLds) return hipErrorInvalidValue;
-#define PF_S4(S)                                                                       \
-  do {                                                                                 \
-    if (a.stream_nt)                                                                   \
-      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true>), grid, block, lds, s, a);  \
-    else                                                                               \
-      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false>), grid, block, lds, s, a); \
-  } while (0)
-    switch (stage) {
-      case 0: PF_S4(0); break;
-      case 1: PF_S4(1); break;
-      case 2: PF_S4(2); break;
-      case 3: PF_S4(3); break;
-      case 4: PF_S4(4); break;
-      case 5: PF_S4(5); break;
-      default: return hipErrorInvalidValue;
+    if constexpr (MODEL == PF_MODEL_TEMP) {
+      return launch_vector_t<R, MODEL, PF_REACT_SIGMA>(stage, a, s);
+    } else {
+      if (a.mc.reaction != PF_REACT_GRADP)
+        return launch_vector_t<R, MODEL, PF_REACT_SIGMA>(stage, a, s);
+      return launch_vector_t<R, MODEL, PF_REACT_GRADP>(stage, a, s);
     }
-#undef PF_S4
-    return hipGetLastError();
   }
+  if (a.mc.reaction == PF_REACT_GRADP || MODEL == PF_MODEL_TEMP)
+    return launch_simple_t<R, MODEL>(stage, a, s);
+  const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
   switch (stage) {
     case 0: hipLaunchKernelGGL((stage_kernel<R, MODEL, 0>), grid, block, 0, s, a); break;
     case 1: hipLaunchKernelGGL((stage_kernel<R, MODEL, 1>), grid, block, 0, s, a); break;
@@ -1665,16 +1682,15 @@ hipError_t launch_pair(int precision, int model, int first, int ts, const PairAr
 }
 
 hipError_t launch_stage(int precision, int model, int stage, const StageArgs& a, hipStream_t s) {
-  if (model == PF_MODEL_TEMP && (a.vec || a.mc.reaction != PF_REACT_SIGMA))
-    return hipErrorInvalidValue;
+  if (model == PF_MODEL_TEMP && a.mc.reaction != PF_REACT_SIGMA) return hipErrorInvalidValue;
   if (precision == PF_FP64) {
     if (model == PF_MODEL_AC) return launch_stage_t<double, PF_MODEL_AC>(stage, a, s);
     if (model == PF_MODEL_COUPLED) return launch_stage_t<double, PF_MODEL_COUPLED>(stage, a, s);
-    if (model == PF_MODEL_TEMP) return launch_simple_t<double, PF_MODEL_TEMP>(stage, a, s);
+    if (model == PF_MODEL_TEMP) return launch_stage_t<double, PF_MODEL_TEMP>(stage, a, s);
   } else {
     if (model == PF_MODEL_AC) return launch_stage_t<float, PF_MODEL_AC>(stage, a, s);
     if (model == PF_MODEL_COUPLED) return launch_stage_t<float, PF_MODEL_COUPLED>(stage, a, s);
-    if (model == PF_MODEL_TEMP) return launch_simple_t<float, PF_MODEL_TEMP>(stage, a, s);
+    if (model == PF_MODEL_TEMP) return launch_stage_t<float, PF_MODEL_TEMP>(stage, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -99,9 +99,11 @@ def test_rhs_fp32_matches_oracle(model, reaction):
         assert rel(gT, kT) <= 2e-5
 
 
-def run_gpu(p, mask, phi, T, dt, steps, tol=0.0, precision="fp64"):
+def run_gpu(p, mask, phi, T, dt, steps, tol=0.0, precision="fp64", vector=None):
     s = pf.Solver(p, mask, precision, dict(tol=tol))
     s.set_loop(7, True)
+    if vector is not None:
+        s.set_vector(vector)
     if p["model"] == "temp":
         s.set_state(None, T - T_STAR)
     elif p["model"] == "coupled":
@@ -116,9 +118,10 @@ def run_gpu(p, mask, phi, T, dt, steps, tol=0.0, precision="fp64"):
     return ph, th, st, d
 
 
+@pytest.mark.parametrize("vector", [True, False])
 @pytest.mark.parametrize("model,reaction,dt", [("ac", "gradp", 0.5), ("coupled", "gradp", 2e-3),
                                                ("temp", "sigma", 2e-3)])
-def test_fixed_steps_fp64_match_oracle(model, reaction, dt):
+def test_fixed_steps_fp64_match_oracle(model, reaction, dt, vector):
     p, mask, phi, T = problem((18, 21, 26), model, reaction, 21, faces=(1 << 4) | (1 << 3),
                               bc_kind=1)
     P = oracle.make_params(p)
@@ -126,7 +129,7 @@ def test_fixed_steps_fp64_match_oracle(model, reaction, dt):
     ph_o, T_o, ost = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt,
                                       None if model == "temp" else phi,
                                       None if model == "ac" else T, max_steps=steps)
-    ph, th, st, d = run_gpu(p, mask, phi, T, dt, steps)
+    ph, th, st, d = run_gpu(p, mask, phi, T, dt, steps, vector=vector)
     assert st["steps_accepted"] == steps and st["status"] == pf.PF_MAXSTEPS
     if model != "temp":
         assert rel(ph, ph_o) <= 1e-12
@@ -138,9 +141,10 @@ def test_fixed_steps_fp64_match_oracle(model, reaction, dt):
     assert abs(d["enthalpy"] - od["enthalpy"]) <= 1e-10 * abs(od["enthalpy"])
 
 
+@pytest.mark.parametrize("vector", [True, False])
 @pytest.mark.parametrize("model,reaction,dt", [("coupled", "gradp", 1e-3),
                                                ("temp", "sigma", 1e-3)])
-def test_adaptive_fp64_matches_oracle(model, reaction, dt):
+def test_adaptive_fp64_matches_oracle(model, reaction, dt, vector):
     p, mask, phi, T = problem((12, 14, 16), model, reaction, 5, faces=1 << 4, bc_kind=0)
     # start from a smooth state (a sharp random field makes the first error
     # estimates sit at the roundoff floor)
@@ -150,7 +154,7 @@ def test_adaptive_fp64_matches_oracle(model, reaction, dt):
     P = oracle.make_params(p)
     ph_o, T_o, ost = oracle.integrate(P, mask, oracle.make_ctl(tol=1e-6), 0.0, dt,
                                       None if model == "temp" else phi, T, max_steps=40)
-    ph, th, st, _ = run_gpu(p, mask, phi, T, dt, 40, tol=1e-6)
+    ph, th, st, _ = run_gpu(p, mask, phi, T, dt, 40, tol=1e-6, vector=vector)
     assert st["steps_accepted"] == ost["steps_accepted"]
     assert st["steps_rejected"] == ost["steps_rejected"]
     # The oracle carries T (~273 K) where the GPU carries theta = T - T*, so
@@ -166,10 +170,12 @@ def test_adaptive_fp64_matches_oracle(model, reaction, dt):
 
 
 def test_simple_kernels_only_errors():
+    """The Temp model and GradP run on the vector and one-cell kernels of the
+    five-pass schedule, not on the paired or batched kernels."""
     p, mask, phi, T = problem((8, 8, 8), "temp", "sigma", 1)
     s = pf.Solver(p, mask, "fp32")
-    with pytest.raises(pf.PFError):
-        s.set_vector(True)
+    s.set_vector(True)
+    s.set_vector(False)
     with pytest.raises(pf.PFError):
         s.set_schedule("paired")
     s.set_state(None, (T - T_STAR).astype(np.float32))
@@ -178,8 +184,9 @@ def test_simple_kernels_only_errors():
     s.close()
     p, mask, phi, T = problem((8, 8, 8), "ac", "gradp", 1)
     s = pf.Solver(p, mask, "fp64")
+    s.set_vector(True)
     with pytest.raises(pf.PFError):
-        s.set_vector(True)
+        s.set_schedule("paired")
     s.close()
     p["model"] = "temp"
     with pytest.raises(pf.PFError):  # GradP needs a phase-field equation
@@ -282,3 +289,29 @@ def test_smooth_glass_errors():
     bad[0, 0, 0] = 1.5
     with pytest.raises(pf.PFError):
         pf.Solver(p, None, "fp32", glass_field=bad)
+
+
+@pytest.mark.parametrize("model,reaction,dt", [("coupled", "gradp", 2e-3), ("temp", "sigma", 2e-3),
+                                               ("ac", "gradp", 0.5)])
+def test_vector_equals_one_cell_fp32(model, reaction, dt):
+    """FP32 fixed steps of the Temp model and GradP on both kernel forms: the
+    vector passes form Y2 and Y4 at the stencil points with the expressions
+    the one-cell passes store, so the states agree bitwise; both stay within
+    the FP32 bound of the oracle."""
+    p, mask, phi, T = problem((21, 17, 36), model, reaction, 41, faces=1 << 4, bc_kind=1)
+    phi = phi.astype(np.float32).astype(np.float64)
+    T = (T - T_STAR).astype(np.float32).astype(np.float64) + T_STAR
+    outs = [run_gpu(p, mask, phi.astype(np.float32), (T - T_STAR).astype(np.float32) + T_STAR,
+                    dt, 6, precision="fp32", vector=v)[:2] for v in (True, False)]
+    for a, b in zip(outs[0], outs[1]):
+        if a is not None:
+            assert np.array_equal(a, b)
+    P = oracle.make_params(p)
+    ph_o, T_o, _ = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt,
+                                    None if model == "temp" else phi,
+                                    None if model == "ac" else T, max_steps=6)
+    ph, th = outs[0]
+    if model != "temp":
+        assert rel(ph, ph_o) <= 1e-4
+    if model != "ac":
+        assert rel(th, T_o - T_STAR) <= 1e-4
