@@ -152,7 +152,7 @@ int pf_create(const pf_params* params, const uint8_t* mask, pf_handle** out);
  * I_W(G) = max(0, 1 - zeta G) masks the update), and lambda and rho c are
  * blended with each cell's G (eq. material-properties-blending-formula).
  * Water cells for the diagnostics and the equilibrium test: G < 1/2.  Runs
- * on the one-cell stage kernels (no vector, paired or batched variants).
+ * on the vector and one-cell stage kernels (no paired or batched variants).
  * Errors: as pf_create, PF_EINVAL for G outside [0, 1]. */
 int pf_create_field(const pf_params* params, const double* G, pf_handle** out);
 
@@ -258,8 +258,8 @@ int pf_set_schedule(pf_handle* h, int32_t schedule);
 
 /* Single-stage passes on vector kernels, one 16-byte vector of consecutive
  * x1-cells per thread (4 FP32 or 2 FP64 cells; n1 must be divisible by that
- * width and the glass must be a voxel mask, PF_EINVAL otherwise; every model
- * and reaction), or on one-cell kernels.  The two forms store
+ * width, PF_EINVAL otherwise; every model, reaction and glass
+ * representation), or on one-cell kernels.  The two forms store
  * different intermediate stage values (the vector passes form Y2 and Y4 at
  * the stencil points from y, k1 and k3; the one-cell passes store them) and
  * give the same results.  The default is the vector form where it applies;

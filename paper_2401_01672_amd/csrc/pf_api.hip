@@ -125,13 +125,14 @@ bool simple_kernels_only(const pf_params& P, int smooth) {
 }
 
 // The vector kernels: n1 divisible by the vector width (4 FP32 or 2 FP64
-// cells), a voxel mask (no smooth glass field), and a plane run with its
-// neighbour rows within the LDS budget.  Every model and reaction.
+// cells) and a plane run with its neighbour rows (of every unknown, and of
+// the glass field in paper mode) within the LDS budget.  Every model,
+// reaction and glass representation.
 static bool vector_ok(const pf_params& P, int smooth) {
   const int nvar = P.model == PF_MODEL_COUPLED ? 2 : 1;
   const int esize = P.precision == PF_FP64 ? 8 : 4;
-  return P.n1 % pf::vec_cells(esize) == 0 && !smooth &&
-         pf::stage4_lds_bytes(P.n1, nvar, esize) <= pf::kStage4MaxLds;
+  return P.n1 % pf::vec_cells(esize) == 0 &&
+         pf::stage4_lds_bytes(P.n1, nvar + (smooth ? 1 : 0), esize) <= pf::kStage4MaxLds;
 }
 
 int validate(const pf_params* P, const uint8_t* mask) {
@@ -765,8 +766,6 @@ int pf_set_vector(pf_handle* h, int32_t enable) {
   if (!h) return PF_EINVAL;
   if (enable && h->P.n1 % pf::vec_cells(h->esize) != 0)
     return fail(h, PF_EINVAL, "vector kernels need n1 divisible by 4 (FP32) or 2 (FP64)");
-  if (enable && h->smooth)
-    return fail(h, PF_EINVAL, "vector kernels need a voxel mask (no smooth glass field)");
   if (enable && !vector_ok(h->P, h->smooth))
     return fail(h, PF_EINVAL, "vector kernels: n1 too large for their LDS plane buffers");
   h->vec = enable ? 1 : 0;

@@ -646,7 +646,8 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
 // leaves the loop at the same point (the exit test reads the control blocks
 // after a barrier).
 
-template <typename R, int MODEL, int STAGE, bool NT = false, int REACT = PF_REACT_SIGMA>
+template <typename R, int MODEL, int STAGE, bool NT = false, int REACT = PF_REACT_SIGMA,
+          int SMOOTH = 0>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile, const int slot,
                                             double* smem, void* lds);
 
@@ -989,7 +990,7 @@ __device__ __forceinline__ R shfl_down1(R v) {
   return __shfl_down(v, 1, 64);
 }
 
-template <typename R, int MODEL, int STAGE, bool NT, int REACT>
+template <typename R, int MODEL, int STAGE, bool NT, int REACT, int SMOOTH>
 __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
                                             const int slot, double* smem, void* lds_raw) {
   const ModelConst& m = a.mc;
@@ -1006,6 +1007,10 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   const R thD = R(dirichlet_theta(m, t0 + cs * dt));
   constexpr bool kCoupled = MODEL == PF_MODEL_COUPLED;
   constexpr int NV = kCoupled ? 2 : 1;
+  // staged fields: the unknowns' stage values, and (paper mode) the glass
+  // field G in slot NV
+  constexpr int NL = NV + (SMOOTH ? 1 : 0);
+  const R* Gf = static_cast<const R*>(a.G);
 
   const int tp = tile % a.tiles_p, tz = tile / a.tiles_p;
   const uint32_t plane = (uint32_t)m.n1 * (uint32_t)m.n2;
@@ -1049,6 +1054,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   // pass needs again at the cell one plane later (kept in registers: a reload
   // misses the L2 on large grids).
   auto ldin = [&](int v, uint32_t i, Quad<R>* raw) -> Quad<R> {
+    if (SMOOTH && v == NV) return ldq(Gf, i);
     if constexpr (STAGE == 2 || STAGE == 4) {
       const Quad<R> y0 = ldq(yv[v], i), q1 = ldq(k1[v], i);
       Quad<R> q3, o;
@@ -1092,27 +1098,27 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   const unsigned dirf = (unsigned)m.dirichlet_faces;
 
   // z window of the stencil input, and the cell's own k1 (S2) or y, k1, k3 (S4)
-  Quad<R> cm[2], cc[2], cp[2];
-  Quad<R> rc[2][3], rp[2][3];
+  Quad<R> cm[3], cc[3], cp[3];
+  Quad<R> rc[3][3], rp[3][3];
   uint32_t n = p + plane * (uint32_t)z0;
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    for (int v = 0; v < NL; ++v) {
       cc[v] = ldin(v, n, rc[v]);
       cm[v] = z0 > 0 ? ldin(v, n - plane, nullptr) : cc[v];
     }
   }
   for (int z = z0; z < z1; ++z, n += plane) {
     const bool zp_in = z < m.n3 - 1;
-    Quad<R>* L = lds + (size_t)((z - z0) & 1) * NV * W;
-    Quad<R> ym[2], yp[2];
-    R xl[2], xr[2];
+    Quad<R>* L = lds + (size_t)((z - z0) & 1) * NL * W;
+    Quad<R> ym[3], yp[3];
+    R xl[3], xr[3];
     uint32_t codes = 0;
     if (active) {
       if constexpr (VW == 4) codes = *reinterpret_cast<const uint32_t*>(a.code + n);
       else codes = *reinterpret_cast<const uint16_t*>(a.code + n);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
+      for (int v = 0; v < NL; ++v) {
         cp[v] = zp_in ? ldin(v, n + plane, rp[v]) : cc[v];
         L[v * W + Q + t] = cc[v];
       }
@@ -1124,14 +1130,14 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       if (hq >= 0 && hq < (long long)nq) {
         const uint32_t sl = h < Q ? h : h + kBlock;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NL; ++v)
           L[v * W + sl] = ldin(v, zoff + (uint32_t)hq * (uint32_t)VW, nullptr);
       }
     }
     __syncthreads();
     // x neighbours of the end cells: adjacent lanes, or LDS across waves
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    for (int v = 0; v < NL; ++v) {
       xl[v] = shfl_up1(cc[v].v[VW - 1]);
       xr[v] = shfl_down1(cc[v].v[0]);
       if (active && xm_remote) xl[v] = L[v * W + Q + t - 1].v[VW - 1];
@@ -1172,9 +1178,27 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
           for (int f = 0; f < 6; ++f) thn[f] = R(0);
         }
         R kp, kt;
-        // Temp model: the single unknown (theta) travels in the first slot
-        CellRHS<R, MODEL, REACT>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn, thn,
-                                       code, inb, dirf, thD, kp, kt);
+        if constexpr (SMOOTH) {
+          const R Gc = cc[NV].v[k];
+          R Gn[6];
+          Gn[0] = k > 0 ? cc[NV].v[k - 1] : xl[NV];
+          Gn[1] = k < VW - 1 ? cc[NV].v[k + 1] : xr[NV];
+          Gn[2] = ym[NV].v[k];
+          Gn[3] = yp[NV].v[k];
+          Gn[4] = cm[NV].v[k];
+          Gn[5] = cp[NV].v[k];
+          // Temp model: the single unknown (theta) travels in the first slot
+          if (MODEL == PF_MODEL_TEMP)
+            CellRHSSmooth<R, MODEL, REACT>::eval(m, R(0), cc[0].v[k], thn, phn, Gc, Gn, inb,
+                                                 dirf, thD, kt, kp);
+          else
+            CellRHSSmooth<R, MODEL, REACT>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0),
+                                                 phn, thn, Gc, Gn, inb, dirf, thD, kp, kt);
+        } else {
+          // Temp model: the single unknown (theta) travels in the first slot
+          CellRHS<R, MODEL, REACT>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn, thn,
+                                         code, inb, dirf, thD, kp, kt);
+        }
         kq[0].v[k] = kp;
         kq[1].v[k] = kt;
         // equilibrium measure (no phase-field equation in the Temp model)
@@ -1221,7 +1245,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
+      for (int v = 0; v < NL; ++v) {
         cm[v] = cc[v];
         cc[v] = cp[v];
         if constexpr (STAGE == 2) rc[v][1] = rp[v][1];
@@ -1252,12 +1276,13 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   }
 }
 
-template <typename R, int MODEL, int STAGE, bool NT = false, int REACT = PF_REACT_SIGMA>
+template <typename R, int MODEL, int STAGE, bool NT = false, int REACT = PF_REACT_SIGMA,
+          int SMOOTH = 0>
 __global__ __launch_bounds__(kBlock) void stage4_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
   extern __shared__ __align__(16) unsigned char pf_stage_lds[];
-  stage4_tile<R, MODEL, STAGE, NT, REACT>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, smem,
-                                          pf_stage_lds);
+  stage4_tile<R, MODEL, STAGE, NT, REACT, SMOOTH>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x,
+                                                  smem, pf_stage_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1589,17 +1614,20 @@ static hipError_t launch_simple_t(int stage, const StageArgs& a, hipStream_t s) 
                      : launch_scalar_t<R, MODEL, PF_REACT_SIGMA, 0>(stage, a, s);
 }
 
-template <typename R, int MODEL, int REACT>
+template <typename R, int MODEL, int REACT, int SMOOTH>
 static hipError_t launch_vector_t(int stage, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
-  const size_t lds = stage4_lds_bytes(a.mc.n1, MODEL == PF_MODEL_COUPLED ? 2 : 1, sizeof(R));
-  if (lds > kStage4MaxLds) return hipErrorInvalidValue;
-#define PF_S4(S)                                                                          \
-  do {                                                                                    \
-    if (a.stream_nt)                                                                      \
-      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true, REACT>), grid, block, lds, s, a);  \
-    else                                                                                  \
-      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false, REACT>), grid, block, lds, s, a); \
+  const size_t lds =
+      stage4_lds_bytes(a.mc.n1, (MODEL == PF_MODEL_COUPLED ? 2 : 1) + SMOOTH, sizeof(R));
+  if (lds > kStage4MaxLds || (SMOOTH && !a.G)) return hipErrorInvalidValue;
+#define PF_S4(S)                                                                        \
+  do {                                                                                  \
+    if (a.stream_nt)                                                                    \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, true, REACT, SMOOTH>), grid, block,  \
+                         lds, s, a);                                                    \
+    else                                                                                \
+      hipLaunchKernelGGL((stage4_kernel<R, MODEL, S, false, REACT, SMOOTH>), grid, block, \
+                         lds, s, a);                                                    \
   } while (0)
   switch (stage) {
     case 0: PF_S4(0); break;
@@ -1614,19 +1642,23 @@ static hipError_t launch_vector_t(int stage, const StageArgs& a, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename R, int MODEL, int SMOOTH>
+static hipError_t launch_vector_m(int stage, const StageArgs& a, hipStream_t s) {
+  if constexpr (MODEL == PF_MODEL_TEMP) {
+    return launch_vector_t<R, MODEL, PF_REACT_SIGMA, SMOOTH>(stage, a, s);
+  } else {
+    if (a.mc.reaction != PF_REACT_GRADP)
+      return launch_vector_t<R, MODEL, PF_REACT_SIGMA, SMOOTH>(stage, a, s);
+    return launch_vector_t<R, MODEL, PF_REACT_GRADP, SMOOTH>(stage, a, s);
+  }
+}
+
 template <typename R, int MODEL>
 static hipError_t launch_stage_t(int stage, const StageArgs& a, hipStream_t s) {
-  if (a.mc.smooth) return launch_simple_t<R, MODEL>(stage, a, s);
-  if (a.vec) {
-    if constexpr (MODEL == PF_MODEL_TEMP) {
-      return launch_vector_t<R, MODEL, PF_REACT_SIGMA>(stage, a, s);
-    } else {
-      if (a.mc.reaction != PF_REACT_GRADP)
-        return launch_vector_t<R, MODEL, PF_REACT_SIGMA>(stage, a, s);
-      return launch_vector_t<R, MODEL, PF_REACT_GRADP>(stage, a, s);
-    }
-  }
-  if (a.mc.reaction == PF_REACT_GRADP || MODEL == PF_MODEL_TEMP)
+  if (a.vec)
+    return a.mc.smooth ? launch_vector_m<R, MODEL, 1>(stage, a, s)
+                       : launch_vector_m<R, MODEL, 0>(stage, a, s);
+  if (a.mc.smooth || a.mc.reaction == PF_REACT_GRADP || MODEL == PF_MODEL_TEMP)
     return launch_simple_t<R, MODEL>(stage, a, s);
   const dim3 grid((unsigned)(a.tiles_p * a.tiles_z)), block(kBlock);
   switch (stage) {

@@ -225,6 +225,8 @@ def gpu_rhs_smooth(p, G, t, phi, T, precision="fp64"):
 
 SMOOTH_VARIANTS = [("ac", "sigma"), ("coupled", "sigma"), ("ac", "gradp"), ("coupled", "gradp"),
                    ("temp", "sigma")]
+SMOOTH_STEP_VARIANTS = [("ac", "sigma", 0.5), ("coupled", "sigma", 2e-3),
+                        ("coupled", "gradp", 2e-3), ("temp", "sigma", 2e-3)]
 
 
 @pytest.mark.parametrize("model,reaction", SMOOTH_VARIANTS)
@@ -253,9 +255,11 @@ def test_smooth_rhs_fp32_matches_oracle(model, reaction):
         assert rel(gT, kT) <= 2e-5
 
 
-def test_paper_case_fixed_steps_fp64_matches_oracle():
+@pytest.mark.parametrize("vector", [True, False])
+def test_paper_case_fixed_steps_fp64_matches_oracle(vector):
     """The paper-mode vessel (smooth beads, glass cap, anchored nucleation
-    disk, cooled cap face) at N3 = 40, coupled model, 20 fixed steps."""
+    disk, cooled cap face) at N3 = 40, coupled model, 20 fixed steps, on both
+    kernel forms."""
     c = pi.case_paper(40, seed=5)
     p = dict(c.params)
     dt, steps = 5e-3, 20
@@ -263,6 +267,7 @@ def test_paper_case_fixed_steps_fp64_matches_oracle():
     ph_o, T_o, _ = oracle.integrate(P, c.G, oracle.make_ctl(tol=0.0), 0.0, dt, c.phi0, c.T0,
                                     max_steps=steps)
     s = pf.Solver(p, None, "fp64", dict(tol=0.0), glass_field=c.G)
+    s.set_vector(vector)
     s.set_state(c.phi0, c.T0 - T_STAR)
     s.set_time(0.0, dt)
     st = s.integrate(max_steps=steps)
@@ -277,10 +282,12 @@ def test_paper_case_fixed_steps_fp64_matches_oracle():
 
 
 def test_smooth_glass_errors():
-    p, G, phi, T = smooth_problem((8, 8, 8), "ac", "sigma", 3)
+    p, G, phi, T = smooth_problem((8, 8, 7), "ac", "sigma", 3)
     s = pf.Solver(p, None, "fp32", glass_field=G)
-    with pytest.raises(pf.PFError):
+    with pytest.raises(pf.PFError):  # n1 = 7: no vector kernels
         s.set_vector(True)
+    with pytest.raises(pf.PFError):
+        s.set_schedule("paired")
     s.set_state(phi.astype(np.float32))
     with pytest.raises(pf.PFError):
         pf.batch_integrate([s], max_steps=2)
@@ -315,3 +322,38 @@ def test_vector_equals_one_cell_fp32(model, reaction, dt):
         assert rel(ph, ph_o) <= 1e-4
     if model != "ac":
         assert rel(th, T_o - T_STAR) <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("model,reaction,dt", SMOOTH_STEP_VARIANTS)
+def test_smooth_vector_equals_one_cell(model, reaction, dt, precision):
+    """Paper mode (smooth glass field, staged in LDS beside the unknowns) on
+    both kernel forms: bitwise equal states after fixed steps, and the RHS of
+    the vector form against the oracle."""
+    p, G, phi, T = smooth_problem((13, 11, 36), model, reaction, 61, faces=1 << 5, bc_kind=2)
+    npdt = np.float64 if precision == "fp64" else np.float32
+    G = G.astype(npdt).astype(np.float64)
+    outs = []
+    for vec in (True, False):
+        s = pf.Solver(p, None, precision, dict(tol=0.0), glass_field=G)
+        s.set_vector(vec)
+        if model == "temp":
+            s.set_state(None, (T - T_STAR).astype(npdt))
+        elif model == "coupled":
+            s.set_state(phi.astype(npdt), (T - T_STAR).astype(npdt))
+        else:
+            s.set_state(phi.astype(npdt))
+        s.set_time(0.0, dt)
+        st = s.integrate(max_steps=5)
+        assert st["steps_accepted"] == 5
+        outs.append(s.get_state())
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        if a is not None:
+            assert np.array_equal(a, b)
+    if model != "temp" and precision == "fp64":
+        kp, kT = oracle_rhs(p, G, 0.5, phi, T)
+        gp, gT = gpu_rhs_smooth(p, G, 0.5, phi, T, "fp64")  # n1 = 36: vector RHS
+        assert rel(gp, kp) <= 1e-12
+        if model != "ac":
+            assert rel(gT, kT) <= 1e-12
