@@ -178,3 +178,24 @@ def test_autotuned_stage_depths_do_not_change_results(precision):
     assert cfg_b["stage_z_chunk"] == [3] * 5, cfg_b
     assert (na, ra) == (nb, rb)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("precision,n1", [("fp64", 800), ("fp32", 1604)])
+def test_rows_too_long_for_vector_lds(precision, n1):
+    """Rows whose vector plane buffers would exceed 64 KiB of LDS run on the
+    one-cell kernels: pf_set_vector(1) is refused, and the run still matches
+    the oracle."""
+    p, mask, phi, T = rand_problem((3, 2, n1), "coupled", 77, faces=1 << 4, bc_kind=1)
+    s = pf.Solver(p, mask, precision, dict(tol=0.0))
+    with pytest.raises(pf.PFError):
+        s.set_vector(True)
+    assert not s.get_config()["vector"]
+    s.close()
+    dt = 2e-3
+    ph, th, st, d, cfg = run(p, mask, phi, T, dt, 3, precision, "five")
+    assert not cfg["vector"]
+    P = oracle.make_params(p)
+    ph_o, T_o, _ = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt, phi, T,
+                                    max_steps=3)
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    assert rel(ph, ph_o) <= tol and rel(th, T_o - T_STAR) <= tol
