@@ -617,13 +617,52 @@ __global__ void reach_seed_kernel(const uint8_t* code, const void* phi, int fp64
 }
 
 // Sweep: a water cell joins when a face neighbour across a water-water face
-// has joined.  A workgroup loads a 16^3 block of reach flags
-// with a one-cell halo (and the block's cell codes) into LDS and iterates the
-// update inside the block until nothing changes, so a path through the
-// block is crossed in one launch; blocks exchange the front through the
-// halo on the next launch.  Every productive inner iteration marks at least
-// one of the block's 4096 cells, which bounds the loop.
+// has joined.  A workgroup loads a 16^3 block of reach flags with a one-cell
+// halo (and the block's cell codes) into LDS and closes the block: rounds of
+// three line passes, one per axis, in which each thread scans one line of 16
+// cells forward and backward and marks every cell of a run of open faces
+// that touches a joined cell (so a straight stretch of pore is crossed in one
+// pass, and a path is crossed in as many rounds as it turns), until a round
+// changes nothing.  Blocks exchange the front through the halo on the next
+// launch.  Every productive round marks at least one of the block's 4096
+// cells, which bounds the loop.
 constexpr int kRB = 16, kRH = kRB + 2;
+
+// one line of the block: cells h0 + i*hs (halo index) with codes c0 + i*cs;
+// bm / bp: the code bits of the faces towards -axis / +axis
+__device__ __forceinline__ bool reach_line(uint8_t* sr, const uint8_t* sc, int h0, int hs,
+                                           int c0, int cs, unsigned bm, unsigned bp) {
+  bool changed = false;
+  bool carry = sr[h0 - hs] != 0;  // the halo cell before the line
+  for (int i = 0; i < kRB; ++i) {
+    const unsigned c = sc[c0 + i * cs];
+    uint8_t& f = sr[h0 + i * hs];
+    if (c & 0x40u) {
+      carry = false;
+      continue;
+    }
+    if (!f && carry && (c & bm)) {
+      f = 1;
+      changed = true;
+    }
+    carry = f != 0;
+  }
+  carry = sr[h0 + kRB * hs] != 0;  // the halo cell after the line
+  for (int i = kRB - 1; i >= 0; --i) {
+    const unsigned c = sc[c0 + i * cs];
+    uint8_t& f = sr[h0 + i * hs];
+    if (c & 0x40u) {
+      carry = false;
+      continue;
+    }
+    if (!f && carry && (c & bp)) {
+      f = 1;
+      changed = true;
+    }
+    carry = f != 0;
+  }
+  return changed;
+}
 
 __global__ __launch_bounds__(256) void reach_block_kernel(const uint8_t* code, uint8_t* reach,
                                                           int n1, int n2, int n3, int bx, int by,
@@ -649,22 +688,24 @@ __global__ __launch_bounds__(256) void reach_block_kernel(const uint8_t* code, u
     sc[i] = (x < n1 && y < n2 && z < n3) ? code[z * pl + (long long)y * n1 + x] : (uint8_t)0x40u;
   }
   if (tid == 0) any = 0;
-  for (int iter = 0; iter <= kRB * kRB * kRB; ++iter) {
+  // thread -> the line through (u, w) of the two other axes
+  const int u = tid % kRB, w = tid / kRB;
+  for (int round = 0; round <= kRB * kRB * kRB; ++round) {
     if (tid == 0) flag = 0;
     __syncthreads();
-    for (int i = tid; i < kRB * kRB * kRB; i += 256) {
-      const unsigned c = sc[i];
-      const int lx = i % kRB, ly = (i / kRB) % kRB, lz = i / (kRB * kRB);
-      const int h = ((lz + 1) * kRH + (ly + 1)) * kRH + (lx + 1);
-      if ((c & 0x40u) || sr[h]) continue;
-      const bool hit = ((c & 1u) && sr[h - 1]) || ((c & 2u) && sr[h + 1]) ||
-                       ((c & 4u) && sr[h - kRH]) || ((c & 8u) && sr[h + kRH]) ||
-                       ((c & 16u) && sr[h - kRH * kRH]) || ((c & 32u) && sr[h + kRH * kRH]);
-      if (hit) {
-        sr[h] = 1;
-        flag = 1;
-      }
-    }
+    bool ch = false;
+    // x lines (y = u, z = w)
+    ch |= reach_line(sr, sc, ((w + 1) * kRH + (u + 1)) * kRH + 1, 1, (w * kRB + u) * kRB, 1,
+                     1u, 2u);
+    __syncthreads();
+    // y lines (x = u, z = w)
+    ch |= reach_line(sr, sc, ((w + 1) * kRH + 1) * kRH + (u + 1), kRH, w * kRB * kRB + u, kRB,
+                     4u, 8u);
+    __syncthreads();
+    // z lines (x = u, y = w)
+    ch |= reach_line(sr, sc, (kRH + (w + 1)) * kRH + (u + 1), kRH * kRH, w * kRB + u,
+                     kRB * kRB, 16u, 32u);
+    if (ch) flag = 1;
     __syncthreads();
     const int f = flag;
     __syncthreads();

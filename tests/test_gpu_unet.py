@@ -273,3 +273,39 @@ def test_full_size_convolution_sampled(edge):
             z - z0, yy - y0, x - x0]
         got = dev_to_f64(y[z, yy, x].contiguous())
         assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 27 * cin * 2.0 ** -24 * S)
+
+
+def test_nucleus_component_through_a_serpentine():
+    """A single one-cell-wide corridor that snakes along x, turns at the row
+    ends, climbs from row to row and from layer to layer (hundreds of turns,
+    crossing every reachability block many times), plus isolated water
+    pockets: the warm start keeps exactly the corridor."""
+    n = 40
+    mask = np.ones((n, n, n), dtype=np.uint8)
+    rows = [(z, y) for z in range(1, n - 1, 2) for y in range(1, n - 1, 2)]
+    for k, (z, y) in enumerate(rows):
+        mask[z, y, 1:n - 1] = 0
+        if k + 1 < len(rows):
+            z2, y2 = rows[k + 1]
+            x = n - 2 if k % 2 == 0 else 1  # turn at alternating ends
+            if z2 == z:
+                mask[z, y:y2 + 1, x] = 0
+            else:  # climb to the next layer
+                mask[z:z2 + 1, y, x] = 0
+                mask[z2, 1:y + 1, x] = 0
+    # pockets sealed off from the corridor
+    for (z, y, x) in ((0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5)):
+        mask[z, y, x] = 0
+    c = pi.warmstart_instance(20000, edge=48)
+    p = dict(c.params, n1=n, n2=n, n3=n)
+    phi0 = np.zeros((n, n, n), dtype=np.float32)
+    phi0[1, 1, 1:4] = 1.0  # the nucleus: the corridor's first cells
+    s = pf.Solver(p, mask, "fp32", c.run)
+    s.set_state(phi0)
+    net = pf.UNet(seed=2)
+    net.warmstart(s, 0.5, 1.0)
+    phi, _ = s.get_state()
+    keep = U.nucleus_component(mask, phi0)
+    assert keep.sum() == (mask == 0).sum() - 3  # the whole corridor, no pocket
+    assert np.all(phi[~keep] == 0) and np.all(phi[keep] > 0)
+    s.close()
