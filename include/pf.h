@@ -244,7 +244,11 @@ int pf_diagnostics(pf_handle* h, pf_run_stats* stats);
 int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph);
 
 /* Tile shape of the stencil kernels: z_chunk = planes per workgroup column
- * (>= 1); 0 = choose by the built-in autotuner on the next run. */
+ * (>= 1); 0 = choose by the built-in autotuner on the next run.  The
+ * autotuner runs on a handle's first run; its choice (kernel form and the
+ * depth of each pass) is kept for the rest of the process and reused by
+ * every handle with the same grid shape, precision, model, reaction, glass
+ * representation, streaming mode, schedule and device. */
 int pf_set_tile(pf_handle* h, int32_t z_chunk);
 
 /* Stencil schedule of one attempt:

@@ -11,8 +11,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <array>
 #include <chrono>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -379,8 +382,7 @@ int pull_ctl(pf_handle* h) {
 // Autotuner: time the five stage kernels for each candidate z_chunk on the
 // current state (no controller, so the state is untouched) and keep the
 // fastest.
-int autotune(pf_handle* h) {
-  h->autotune_pending = 0;
+int autotune_measure(pf_handle* h) {
   DevCtl& c = *h->hctl;
   init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
   if (!(c.dt_att > 0) || !(c.dt_att < INFINITY)) c.dt_att = 1e-12;
@@ -497,6 +499,53 @@ int autotune(pf_handle* h) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return PF_OK;
+}
+
+// The autotuner's choice depends on the grid's shape and on the kernel
+// variant, not on the state: handles of one signature on one device reuse
+// the first handle's measurement for the rest of the process.
+using TuneKey = std::array<int, 12>;
+struct TuneVal {
+  int vec;
+  int z[6];
+  int pair_ts, pair_zc;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+int autotune(pf_handle* h) {
+  h->autotune_pending = 0;
+  int dev = 0;
+  PF_HIP(h, hipGetDevice(&dev));
+  const TuneKey key = {dev, h->P.n1, h->P.n2, h->P.n3, h->P.precision, h->P.model,
+                       h->P.reaction, h->smooth, h->stream_nt, h->sched, h->vec_fixed,
+                       h->vec_fixed ? h->vec : -1};
+  TuneVal val;
+  bool hit = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      val = it->second;
+      hit = true;
+    }
+  }
+  if (!hit) {
+    int rc = autotune_measure(h);
+    if (rc) return rc;
+    val.vec = h->vec;
+    for (int st = 0; st <= 5; ++st) val.z[st] = st ? h->st_z[st] : h->z_chunk;
+    val.pair_ts = h->pair_ts;
+    val.pair_zc = h->pair_zc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.emplace(key, val);
+    return PF_OK;
+  }
+  h->vec = val.vec;
+  int rc = set_tiles(h, val.z[0]);
+  for (int st = 1; st <= 5 && !rc; ++st) rc = set_stage_tiles(h, st, val.z[st]);
+  if (!rc && h->sched == pf::kSchedPaired) rc = set_pair_tiles(h, val.pair_ts, val.pair_zc);
+  return rc;
 }
 
 }  // namespace

@@ -199,3 +199,21 @@ def test_rows_too_long_for_vector_lds(precision, n1):
                                     max_steps=3)
     tol = 1e-12 if precision == "fp64" else 1e-4
     assert rel(ph, ph_o) <= tol and rel(th, T_o - T_STAR) <= tol
+
+
+def test_autotune_choice_is_reused_by_equal_handles():
+    """A second handle of the same signature takes the first handle's
+    autotuned configuration (no second measurement) and computes the same
+    states."""
+    p, mask, phi, T = rand_problem((24, 20, 32), "coupled", 91, faces=1 << 4, bc_kind=1)
+    outs = []
+    for rep in range(2):
+        s = pf.Solver(p, mask, "fp32", dict(tol=1e-6))
+        s.set_state(phi.astype(np.float32), (T - T_STAR).astype(np.float32))
+        s.set_time(0.0, 1e-3)
+        st = s.integrate(max_steps=30)
+        outs.append((s.get_config(), s.get_state(), st["steps_accepted"]))
+        s.close()
+    assert outs[0][0] == outs[1][0]
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][1][0], outs[1][1][0])
