@@ -40,6 +40,8 @@ class Params(C.Structure):
         ("lam", C.c_double * 3), ("rhoc", C.c_double * 3), ("Lv", C.c_double),
         ("bc_T0", C.c_double), ("bc_T1", C.c_double),
         ("bc_t0", C.c_double), ("bc_t1", C.c_double),
+        ("rho_c_separate", C.c_int32), ("pad_", C.c_int32),
+        ("rho", C.c_double * 3), ("cs", C.c_double * 3), ("L", C.c_double),
     ]
 
 
@@ -128,6 +130,10 @@ def make_params(p: Dict, model: Optional[str] = None, reaction: str = "sigma") -
     P.gamma = float(p.get("gamma", 2.0))
     P.lam[:] = [float(v) for v in p["lam"]]
     P.rhoc[:] = [float(v) for v in p["rhoc"]]
+    P.rho_c_separate = int(p.get("rho_c_separate", 0))
+    P.rho[:] = [float(v) for v in p.get("rho", (1.0, 1.0, 1.0))]
+    P.cs[:] = [float(v) for v in p.get("cs", (1.0, 1.0, 1.0))]
+    P.L = float(p.get("L", 0.0))
     return P
 
 

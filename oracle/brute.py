@@ -69,6 +69,21 @@ def blend(G, phi, w):
     return G * w[2] + (1 - G) * (phi * w[1] + (1 - phi) * w[0])
 
 
+def heat_capacity(p, G, phi):
+    """rho c per cell: blended volumetric values, or (the paper's own form)
+    blended density times blended specific heat."""
+    if p.get("rho_c_separate", 0):
+        return blend(G, phi, p["rho"]) * blend(G, phi, p["cs"])
+    return blend(G, phi, p["rhoc"])
+
+
+def latent_heat(p, G, phi):
+    """rho L per cell: constant, or blended density times L."""
+    if p.get("rho_c_separate", 0):
+        return blend(G, phi, p["rho"]) * p["L"]
+    return p["Lv"] + 0 * phi
+
+
 def smoothstep(w, e0, e1):
     s = np.clip((w - e0) / (e1 - e0), 0.0, 1.0)
     out = s * s * (3 - 2 * s)
@@ -173,10 +188,11 @@ def rhs(p, G, t, phi, T=None):
             A[c, c] -= 2 * lam[c]
             src[c] += 2 * lam[c] * TD
     divq = (A @ Tc + src) / (p["h"] ** 2)
+    rc, lat = heat_capacity(p, Gf, ph), latent_heat(p, Gf, ph)
     if model == "temp":
-        kT = divq / (blend(Gf, ph, p["rhoc"]) - p["Lv"] * dph)
+        kT = divq / (rc - lat * dph)
         return (dph * kT).reshape(shape), kT.reshape(shape)
-    kT = (divq + p["Lv"] * kphi) / blend(Gf, ph, p["rhoc"])
+    kT = (divq + lat * kphi) / rc
     return kphi.reshape(shape), kT.reshape(shape)
 
 

@@ -71,6 +71,14 @@ typedef struct {
   double rhoc[3]; /* volumetric heat capacity: liquid, ice, glass */
   double Lv;      /* volumetric latent heat */
   double bc_T0, bc_T1, bc_t0, bc_t1;
+  /* the paper's own material model (Sec. 2.2): density and specific heat
+   * blended separately, rho c = blend(rho) blend(c), latent term
+   * blend(rho) L; otherwise rhoc and Lv above */
+  int32_t rho_c_separate;
+  int32_t pad_;
+  double rho[3];  /* density: liquid, ice, glass [kg m^-3] */
+  double cs[3];   /* specific heat: liquid, ice, glass [J kg^-1 K^-1] */
+  double L;       /* specific latent heat [J kg^-1] */
 } or_params;
 
 typedef struct {
@@ -109,6 +117,20 @@ double or_water_indicator(double G, double zeta) {
 /* Blending, eq. (material-properties-blending-formula); w = (L, I, G). */
 double or_blend(double G, double phi, const double w[3]) {
   return G * w[2] + (1.0 - G) * (phi * w[1] + (1.0 - phi) * w[0]);
+}
+
+/* Heat capacity per volume and latent heat per volume of a cell: the
+ * product of the blended density and specific heat, and the blended density
+ * times L (eq. heat-equation with rho and c blended by eq.
+ * material-properties-blending-formula), or the blended volumetric heat
+ * capacity and a constant volumetric latent heat. */
+static double or_rhoc(const or_params* p, double G, double phi) {
+  if (p->rho_c_separate) return or_blend(G, phi, p->rho) * or_blend(G, phi, p->cs);
+  return or_blend(G, phi, p->rhoc);
+}
+static double or_latent(const or_params* p, double G, double phi) {
+  if (p->rho_c_separate) return or_blend(G, phi, p->rho) * p->L;
+  return p->Lv;
 }
 
 /* Prescribed temperature of the Dirichlet faces, eq. (BC-temperature-cap):
@@ -244,16 +266,17 @@ void or_rhs(const or_params* p, const double* G, double t, const double* phi,
           } /* else eq. (BC-temperature-wall): insulated */
         }
         q /= h2;
-        const double rc = or_blend(Gc, phic, p->rhoc);
+        const double rc = or_rhoc(p, Gc, phic);
+        const double lat = or_latent(p, Gc, phic);
         if (p->model == OR_MODEL_COUPLED) {
           /* eq. (heat-equation): rho c dT/dt = div(lambda grad T) + rho L dphi/dt */
-          kT[n] = (q + p->Lv * kp) / rc;
+          kT[n] = (q + lat * kp) / rc;
           kphi[n] = kp;
         } else {
           /* eq. (combined-heat-xfer-phase-transition):
            * rho [c - L varphi'(T)] dT/dt = div(lambda grad T) */
           double dp = temp_dphi_dT(Gc, Tc, p);
-          double kt = q / (rc - p->Lv * dp);
+          double kt = q / (rc - lat * dp);
           kT[n] = kt;
           if (kphi) kphi[n] = dp * kt;
         }
@@ -426,7 +449,7 @@ int or_integrate(const or_params* p, const double* G, const or_ctl* c, double t_
  * out[0] = #{G < 1/2 and phi > 1/2}  (ice cells, eq. frozen-subdomain)
  * out[1] = #{G < 1/2}                (water-occupied cells, eq. water-occupied-subdomain)
  * out[2] = sum of phi over G < 1/2
- * out[3] = h^3 * sum over all cells of (rho c (T - T*) - Lv phi)  (enthalpy
+ * out[3] = h^3 * sum over all cells of (rho c (T - T*) - rho L phi)  (enthalpy
  *          relative to water at T*; T = T* - dT for the micro-scale model)
  */
 void or_diagnostics(const or_params* p, const double* G, const double* phi, const double* T,
@@ -441,7 +464,7 @@ void or_diagnostics(const or_params* p, const double* G, const double* phi, cons
       sphi += ph;
       if (ph > 0.5) ice += 1.0;
     }
-    H += or_blend(G[i], ph, p->rhoc) * (Tc - p->t_star) - p->Lv * ph;
+    H += or_rhoc(p, G[i], ph) * (Tc - p->t_star) - or_latent(p, G[i], ph) * ph;
   }
   out[0] = ice;
   out[1] = pore;

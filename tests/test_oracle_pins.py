@@ -552,3 +552,101 @@ def test_smooth_glass_limits():
     p1 = dict(p, phi_face_mask=1)
     kp1, _ = oracle.rhs(oracle.make_params(p1), np.zeros(shape), 0.0, phi)
     assert np.array_equal(kp0, kp1)
+
+
+# --------------------------------------------------------------------------
+# The paper's own material model: rho and c blended separately (eq.
+# material-properties-blending-formula applied to each of c, lambda, rho),
+# rho c = blend(rho) blend(c), latent term blend(rho) L (eq. heat-equation).
+
+def _tab1_params(model, shape, faces=0, bc_kind=0):
+    t1 = GOLD["table1"]
+    p = _tiny_params(model, shape, None, faces=faces, bc_kind=bc_kind)
+    p.update(rho_c_separate=1,
+             rho=(t1["rho"]["L"], t1["rho"]["I"], t1["rho"]["G"]),
+             cs=(t1["c"]["L"], t1["c"]["I"], t1["c"]["G"]),
+             lam=(t1["lambda"]["L"], t1["lambda"]["I"], t1["lambda"]["G"]),
+             L=t1["L"], gamma=2.0)
+    return p
+
+
+@pytest.mark.parametrize("model", ["coupled", "temp"])
+@pytest.mark.parametrize("smooth", [False, True])
+def test_separate_rho_c_matches_brute_force(model, smooth):
+    rng = np.random.default_rng(401 if model == "coupled" else 402)
+    shape = (4, 3, 5)
+    for trial in range(3):
+        p = _tab1_params(model, shape, faces=int(rng.integers(0, 64)), bc_kind=trial)
+        if smooth:
+            p["phi_face_mask"] = 0
+            G = rng.random(shape)
+            G[rng.random(shape) < 0.3] = 0.0
+        else:
+            G = (rng.random(shape) < 0.3).astype(float)
+        phi = rng.random(shape)
+        T = 273.15 + rng.normal(0, 1.0, shape)
+        P = oracle.make_params(p)
+        if model == "temp":
+            kp, kT = oracle.rhs(P, G, 0.7, None, T)
+        else:
+            kp, kT = oracle.rhs(P, G, 0.7, phi, T)
+        bp, bT = brute.rhs(p, G, 0.7, phi, T)
+        assert np.abs(kT - bT).max() <= 1e-12 * np.abs(bT).max()
+        assert np.abs(kp - bp).max() <= 1e-11 * max(np.abs(bp).max(), 1e-300)
+
+
+def test_separate_rho_c_with_unit_density_is_the_volumetric_form():
+    """rho = 1 everywhere and c = the volumetric values: the two material
+    models coincide (rho c and rho L reduce to rhoc and L)."""
+    rng = np.random.default_rng(403)
+    shape = (5, 4, 6)
+    p = _tiny_params("coupled", shape, rng, faces=1 << 4, bc_kind=1)
+    q = dict(p, rho_c_separate=1, rho=(1.0, 1.0, 1.0), cs=p["rhoc"], L=p["Lv"])
+    G = (rng.random(shape) < 0.3).astype(float)
+    phi, T = rng.random(shape), 273.15 + rng.normal(0, 2, shape)
+    a = oracle.rhs(oracle.make_params(p), G, 0.4, phi, T)
+    b = oracle.rhs(oracle.make_params(q), G, 0.4, phi, T)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("phi_value", [0.0, 0.5, 1.0])
+def test_separate_rho_c_conduction_rate_of_a_uniform_phase(phi_value):
+    """A uniform phase state (no phase change: phi constant, T > T* far from
+    the drive) with a cosine temperature mode: dT/dt = -(lambda/(rho c)) k^2-rate
+    of the discrete Neumann Laplacian, with rho c the product of the blended
+    density and specific heat -- at phi = 1/2 that is
+    (rho_L + rho_I)(c_L + c_I)/4, not the blend of the products."""
+    t1 = GOLD["table1"]
+    n1 = 12
+    shape = (1, 1, n1)
+    p = _tab1_params("coupled", shape)
+    p.update(b=0.0)  # no drive: the reaction term keeps phi = 0, 1/2, 1 stationary
+    G = np.zeros(shape)
+    phi = np.full(shape, phi_value)
+    k = 2
+    i = np.arange(n1)
+    mode = np.cos(k * np.pi * (i + 0.5) / n1).reshape(shape)
+    T = 290.0 + 0.1 * mode
+    kp, kT = oracle.rhs(oracle.make_params(p), G, 0.0, phi, T)
+    assert np.all(kp == 0.0)
+    rho = (1 - phi_value) * t1["rho"]["L"] + phi_value * t1["rho"]["I"]
+    c = (1 - phi_value) * t1["c"]["L"] + phi_value * t1["c"]["I"]
+    lam = (1 - phi_value) * t1["lambda"]["L"] + phi_value * t1["lambda"]["I"]
+    eig = -4.0 / p["h"]**2 * math.sin(k * math.pi / (2 * n1))**2
+    expect = lam / (rho * c) * eig * 0.1 * mode
+    assert np.abs(kT - expect).max() <= 1e-12 * np.abs(expect).max()
+
+
+def test_separate_rho_c_enthalpy_balance_insulated():
+    """Insulated box: sum of rho c k_T minus sum of rho L k_phi over the cells
+    is the sum of the face fluxes, zero."""
+    rng = np.random.default_rng(404)
+    shape = (6, 7, 5)
+    p = _tab1_params("coupled", shape, faces=0)
+    G = (rng.random(shape) < 0.35).astype(float)
+    phi, T = rng.random(shape), 273.15 + rng.normal(0, 2, shape)
+    kp, kT = oracle.rhs(oracle.make_params(p), G, 0.0, phi, T)
+    rc = brute.blend(G, phi, p["rho"]) * brute.blend(G, phi, p["cs"])
+    lat = brute.blend(G, phi, p["rho"]) * p["L"]
+    w = rc * kT - lat * kp
+    assert abs(w.sum()) <= 1e-12 * np.abs(rc * kT).sum()
