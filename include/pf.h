@@ -110,6 +110,18 @@ typedef struct {
   double tol;             /* error tolerance; <= 0: fixed steps                 */
   double safety;          /* step-size safety factor                            */
   double dt_min, dt_max;  /* step bounds [s]                                    */
+  /* Material model.  0: rho c blended as one volumetric quantity (rhoc) and a
+   * constant latent heat per volume (Lv).  1: the paper's own form (Sec. 2.2):
+   * density and specific heat blended separately by eq.
+   * material-properties-blending-formula, rho c = blend(rho) blend(c), and
+   * the latent term blend(rho) L in eq. heat-equation (and in eq.
+   * combined-heat-xfer-phase-transition for the Temp model); rhoc and Lv are
+   * then unused.  The enthalpy diagnostic uses the same per-cell values. */
+  int32_t rho_c_separate;
+  int32_t pad_;
+  double rho[3];          /* density: liquid, ice, glass [kg m^-3]              */
+  double cs[3];           /* specific heat: liquid, ice, glass [J kg^-1 K^-1]   */
+  double L;               /* specific latent heat [J kg^-1]                     */
 } pf_params;
 
 /* Result of one attempt. */

@@ -41,6 +41,8 @@ class PFParams(C.Structure):
         ("bc_t1", C.c_double),
         ("tol", C.c_double), ("safety", C.c_double), ("dt_min", C.c_double),
         ("dt_max", C.c_double),
+        ("rho_c_separate", C.c_int32), ("pad_", C.c_int32),
+        ("rho", C.c_double * 3), ("cs", C.c_double * 3), ("L", C.c_double),
     ]
 
 
@@ -161,6 +163,10 @@ def make_params(p: Dict, precision: str = "fp64", run: Optional[Dict] = None) ->
     P.safety = float(run.get("safety", 0.8))
     P.dt_min = float(run.get("dt_min", 1e-12))
     P.dt_max = float(run.get("dt_max", 1e30))
+    P.rho_c_separate = int(p.get("rho_c_separate", 0))
+    P.rho[:] = [float(v) for v in p.get("rho", (1.0, 1.0, 1.0))]
+    P.cs[:] = [float(v) for v in p.get("cs", (1.0, 1.0, 1.0))]
+    P.L = float(p.get("L", 0.0))
     return P
 
 

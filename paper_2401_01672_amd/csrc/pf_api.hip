@@ -108,6 +108,14 @@ void fill_model_const(const pf_params& P, ModelConst& m) {
   m.drc = P.rhoc[1] - P.rhoc[0];
   m.rcG = P.rhoc[2];
   m.Lv = P.Lv;
+  m.sep = P.rho_c_separate ? 1 : 0;
+  m.rhoL = P.rho[0];
+  m.drho = P.rho[1] - P.rho[0];
+  m.rhoG = P.rho[2];
+  m.csL = P.cs[0];
+  m.dcs = P.cs[1] - P.cs[0];
+  m.csG = P.cs[2];
+  m.Lm = P.L;
   m.bc_T0 = P.bc_T0 - P.t_star;
   m.bc_T1 = P.bc_T1 - P.t_star;
   m.bc_t0 = P.bc_t0;
@@ -156,9 +164,19 @@ int validate(const pf_params* P, const uint8_t* mask) {
   if (!(P->h > 0) || !(P->xi > 0) || !(P->alpha > 0))
     return fail(nullptr, PF_EINVAL, "h, xi and alpha must be positive");
   if (!(P->eps1 != P->eps0)) return fail(nullptr, PF_EINVAL, "eps1 must differ from eps0");
+  if (P->rho_c_separate != 0 && P->rho_c_separate != 1)
+    return fail(nullptr, PF_EINVAL, "rho_c_separate must be 0 or 1");
   if (P->model != PF_MODEL_AC) {
-    for (int i = 0; i < 3; ++i)
-      if (!(P->rhoc[i] > 0)) return fail(nullptr, PF_EINVAL, "rhoc must be positive");
+    for (int i = 0; i < 3; ++i) {
+      if (P->rho_c_separate) {
+        if (!(P->rho[i] > 0) || !(P->cs[i] > 0))
+          return fail(nullptr, PF_EINVAL, "rho and cs must be positive");
+      } else if (!(P->rhoc[i] > 0)) {
+        return fail(nullptr, PF_EINVAL, "rhoc must be positive");
+      }
+    }
+    if (P->rho_c_separate && !(P->L >= 0 && P->L < INFINITY))
+      return fail(nullptr, PF_EINVAL, "L must be finite and non-negative");
   }
   if (P->dirichlet_faces < 0 || P->dirichlet_faces > 63)
     return fail(nullptr, PF_EINVAL, "dirichlet_faces must be a 6-bit mask");

@@ -67,6 +67,12 @@ struct ModelConst {
   double lamL, dlam, lamG;   // lambda_L, lambda_I - lambda_L, lambda_G
   double rcL, drc, rcG;      // rho c likewise
   double Lv;
+  // the paper's material model (pf_params.rho_c_separate): rho and c
+  // blended separately, rho c = rho c of the blends, latent term rho L
+  int sep;
+  double rhoL, drho, rhoG;   // density
+  double csL, dcs, csG;      // specific heat
+  double Lm;                 // specific latent heat
   double bc_T0, bc_T1, bc_t0, bc_t1;  // Dirichlet schedule (theta units)
   double h3;        // h^3 for the enthalpy
   double gamma;     // Temp model

@@ -155,6 +155,24 @@ __device__ __forceinline__ R grad_norm(const ModelConst& m, R phic, const R (&ph
   return sqrt(g2);
 }
 
+// Heat capacity and latent heat per volume of a cell of the voxel mask:
+// blended volumetric rho c and a constant rho L, or (the paper's material
+// model) the product of the blended density and specific heat and the
+// blended density times L (eqs. heat-equation and
+// material-properties-blending-formula).
+template <typename R>
+__device__ __forceinline__ void heat_capacity_mask(const ModelConst& m, bool glass, R phic, R& rc,
+                                                   R& lat) {
+  if (m.sep) {
+    const R rho = glass ? R(m.rhoG) : R(m.rhoL) + phic * R(m.drho);
+    rc = rho * (glass ? R(m.csG) : R(m.csL) + phic * R(m.dcs));
+    lat = rho * R(m.Lm);
+  } else {
+    rc = glass ? R(m.rcG) : R(m.rcL) + phic * R(m.drc);
+    lat = R(m.Lv);
+  }
+}
+
 template <typename R, int MODEL, int REACT = PF_REACT_SIGMA>
 struct CellRHS {
   // phn/thn: neighbour values through faces 0..5.  Precondition: for a face
@@ -195,8 +213,9 @@ struct CellRHS {
       }
       const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
       if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
-      const R rc = glass ? R(m.rcG) : R(m.rcL) + phic * R(m.drc);
-      kth = div_fast(R(0.5) * R(m.cH) * qq + R(m.Lv) * kphi, rc);
+      R rc, lat;
+      heat_capacity_mask(m, glass, phic, rc, lat);
+      kth = div_fast(R(0.5) * R(m.cH) * qq + lat * kphi, rc);
     } else {
       kth = R(0);
     }
@@ -245,10 +264,11 @@ struct CellRHS<R, PF_MODEL_TEMP, REACT> {
     }
     const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
     if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
-    const R rc = glass ? R(m.rcG) : R(m.rcL) + phic * R(m.drc);
+    R rc, lat;
+    heat_capacity_mask(m, glass, phic, rc, lat);
     // varphi'(T) = -gamma I_W (1 - tanh^2)/2
     const R dphi = R(-2) * iw * R(m.gamma) * bump_e(e);
-    kth = (R(0.5) * R(m.cH) * qq) / (rc - R(m.Lv) * dphi);
+    kth = (R(0.5) * R(m.cH) * qq) / (rc - lat * dphi);
     kphi = dphi * kth;
   }
 };
@@ -317,12 +337,20 @@ struct CellRHSSmooth {
     }
     const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
     if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
-    const R rc = blend3(Gc, pc, R(m.rcL), R(m.drc), R(m.rcG));
+    R rc, lat;
+    if (m.sep) {
+      const R rho = blend3(Gc, pc, R(m.rhoL), R(m.drho), R(m.rhoG));
+      rc = rho * blend3(Gc, pc, R(m.csL), R(m.dcs), R(m.csG));
+      lat = rho * R(m.Lm);
+    } else {
+      rc = blend3(Gc, pc, R(m.rcL), R(m.drc), R(m.rcG));
+      lat = R(m.Lv);
+    }
     if (MODEL == PF_MODEL_TEMP) {
-      kth = (R(0.5) * R(m.cH) * qq) / (rc - R(m.Lv) * dphi);
+      kth = (R(0.5) * R(m.cH) * qq) / (rc - lat * dphi);
       kphi = dphi * kth;
     } else {
-      kth = (R(0.5) * R(m.cH) * qq + R(m.Lv) * kphi) / rc;
+      kth = (R(0.5) * R(m.cH) * qq + lat * kphi) / rc;
     }
   }
 };
@@ -840,14 +868,25 @@ __global__ __launch_bounds__(kBlock) void diag_kernel(const uint8_t* code, const
                        : MODEL == PF_MODEL_TEMP  ? (double)phi[i]
                                                  : -m.dT;
     const double Gd = (double)Gc;
-    const double rc = G ? Gd * m.rcG + (1.0 - Gd) * (m.rcL + ph * m.drc)
-                        : glass ? m.rcG : m.rcL + ph * m.drc;
+    // blend (eq. material-properties-blending-formula) of the cell
+    auto bl = [&](double wL, double dw, double wG) {
+      return G ? Gd * wG + (1.0 - Gd) * (wL + ph * dw) : glass ? wG : wL + ph * dw;
+    };
+    double rc, lat;
+    if (m.sep) {
+      const double rho = bl(m.rhoL, m.drho, m.rhoG);
+      rc = rho * bl(m.csL, m.dcs, m.csG);
+      lat = rho * m.Lm;
+    } else {
+      rc = bl(m.rcL, m.drc, m.rcG);
+      lat = m.Lv;
+    }
     if (!glass) {
       v[0] += 1.0;
       v[1] += ph;
       v[3] += ph > 0.5 ? 1.0 : 0.0;
     }
-    v[2] += rc * thc - m.Lv * ph;
+    v[2] += rc * thc - lat * ph;
   }
   const int ops[4] = {0, 0, 0, 0};
   block_reduce<4>(v, ops, smem);

@@ -71,6 +71,13 @@ ALPHA_REAL = 3.39782e11
 ALPHA_LARGE_SIGMA = 4.17e6
 # Tab. 1: mobility [m s^-1 K^-1].
 MU = 1.0e-4
+# Tab. 1 physical properties (liquid, ice, glass) for the paper's own
+# material model: density [kg m^-3], specific heat [J kg^-1 K^-1], heat
+# conductivity [W m^-1 K^-1], specific latent heat [J kg^-1]
+RHO_TAB1 = (997.0, 917.0, 2500.0)
+C_TAB1 = (4180.0, 2050.0, 840.0)
+LAM_TAB1 = (0.6, 2.22, 1.1)
+L_TAB1 = 3.34e5
 
 
 class SplitMix64:
@@ -479,7 +486,8 @@ def nucleation_disk(shape_zyx) -> np.ndarray:
 
 def case_paper(n3: int = 100, seed: int = 5, model: str = "coupled",
                L3: float = 0.06, alpha: float = ALPHA_LARGE_SIGMA, dT: float = 0.0,
-               bed_fraction: float = 0.35, bed_height: float = 0.75) -> Case:
+               bed_fraction: float = 0.35, bed_height: float = 0.75,
+               materials: str = "paper") -> Case:
     """Paper-mode setup (Sec. 2.1, Sec. 3.1, Tab. 2) on a synthetic bead bed.
 
     Vessel N1 x N2 x N3 = N3/2 x N3/2 x N3 cells, h = L3/N3; bead radius
@@ -490,7 +498,10 @@ def case_paper(n3: int = 100, seed: int = 5, model: str = "coupled",
     ``bed_height`` of the vessel to a voxel solid fraction ``bed_fraction``.
     Coupled model: T_ini = T* + 20 K, the top face (the cap) held at
     T* - 25 K for 5 h, then at T* + 20 K (freeze/thaw step); other faces
-    insulated.  Micro-scale model ("ac"): constant supercooling dT."""
+    insulated.  Micro-scale model ("ac"): constant supercooling dT.
+    ``materials="paper"``: Tab. 1 properties with density and specific heat
+    blended separately (the paper's material model); ``"cases"``: the
+    volumetric values of the other cases."""
     if n3 % 2:
         raise ValueError("n3 must be even")
     n1 = n2 = n3 // 2
@@ -506,6 +517,10 @@ def case_paper(n3: int = 100, seed: int = 5, model: str = "coupled",
     p = _base_params(n1, n2, n3, h, h, alpha, model)
     p["phi_face_mask"] = 0
     p["gamma"] = 2.0
+    if materials == "paper":
+        p.update(rho_c_separate=1, rho=RHO_TAB1, cs=C_TAB1, lam=LAM_TAB1, L=L_TAB1)
+    elif materials != "cases":
+        raise ValueError("materials must be 'paper' or 'cases'")
     if model == "ac":
         p["dT"] = dT
         T0 = None

@@ -60,6 +60,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(pf_params, h), offsetof(pf_params, lam),
          offsetof(pf_params, tol), offsetof(pf_params, dt_max));
   printf("%zu %zu\n", offsetof(pf_run_stats, ice_count), offsetof(pf_run_stats, status));
+  printf("%zu %zu\n", offsetof(pf_params, rho_c_separate), offsetof(pf_params, L));
   return 0;
 }
 '''
@@ -84,6 +85,8 @@ def test_ctypes_structs_match_c_layout():
     assert v[6] == pf.PFParams.dt_max.offset
     assert v[7] == pf.PFRunStats.ice_count.offset
     assert v[8] == pf.PFRunStats.status.offset
+    assert v[9] == pf.PFParams.rho_c_separate.offset
+    assert v[10] == pf.PFParams.L.offset
 
 
 def test_make_params_from_case():

@@ -357,3 +357,57 @@ def test_smooth_vector_equals_one_cell(model, reaction, dt, precision):
         assert rel(gp, kp) <= 1e-12
         if model != "ac":
             assert rel(gT, kT) <= 1e-12
+
+
+TAB1 = dict(rho_c_separate=1, rho=pi.RHO_TAB1, cs=pi.C_TAB1, lam=pi.LAM_TAB1, L=pi.L_TAB1)
+
+
+@pytest.mark.parametrize("model", ["coupled", "temp"])
+@pytest.mark.parametrize("shape", [(9, 7, 12), (8, 5, 11)])  # n1 = 12: vector; 11: one-cell
+def test_separate_rho_c_rhs_matches_oracle(model, shape):
+    """The paper's material model (rho and c blended separately, latent term
+    blend(rho) L) on the voxel mask, FP64 and FP32."""
+    p, mask, phi, T = problem(shape, model, "sigma", 81, faces=1 << 4, bc_kind=1)
+    p.update(TAB1)
+    kp, kT = oracle_rhs(p, mask, 0.3, phi, T)
+    gp, gT = gpu_rhs(p, mask, 0.3, phi, T)
+    assert rel(gT, kT) <= 1e-12
+    if model == "coupled":
+        assert rel(gp, kp) <= 1e-12
+    phi32 = phi.astype(np.float32).astype(np.float64)
+    T32 = (T - T_STAR).astype(np.float32).astype(np.float64) + T_STAR
+    kp, kT = oracle_rhs(p, mask, 0.3, phi32, T32)
+    gp, gT = gpu_rhs(p, mask, 0.3, phi32, T32, "fp32")
+    assert rel(gT, kT) <= 2e-5
+
+
+@pytest.mark.parametrize("vector", [True, False])
+def test_separate_rho_c_steps_and_enthalpy_match_oracle(vector):
+    """Fixed steps of the coupled model with the paper's material model, on
+    both kernel forms, and the enthalpy diagnostic with the per-cell rho c
+    and rho L."""
+    p, mask, phi, T = problem((14, 12, 16), "coupled", "sigma", 83, faces=1 << 4, bc_kind=1)
+    p.update(TAB1)
+    P = oracle.make_params(p)
+    dt, steps = 2e-3, 10
+    ph_o, T_o, _ = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt, phi, T,
+                                    max_steps=steps)
+    s = pf.Solver(p, mask, "fp64", dict(tol=0.0))
+    s.set_vector(vector)
+    s.set_state(phi, T - T_STAR)
+    s.set_time(0.0, dt)
+    s.integrate(max_steps=steps)
+    ph, th = s.get_state()
+    d = s.diagnostics()
+    s.close()
+    assert rel(ph, ph_o) <= 1e-12 and rel(th, T_o - T_STAR) <= 1e-12
+    od = oracle.diagnostics(P, mask, ph_o, T_o)
+    assert abs(d["enthalpy"] - od["enthalpy"]) <= 1e-10 * abs(od["enthalpy"])
+
+
+def test_separate_rho_c_smooth_rhs_matches_oracle():
+    p, G, phi, T = smooth_problem((10, 9, 14), "coupled", "sigma", 85, faces=1 << 5, bc_kind=2)
+    p.update(TAB1)
+    kp, kT = oracle_rhs(p, G, 0.2, phi, T)
+    gp, gT = gpu_rhs_smooth(p, G, 0.2, phi, T)
+    assert rel(gp, kp) <= 1e-12 and rel(gT, kT) <= 1e-12

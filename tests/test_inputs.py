@@ -145,6 +145,8 @@ def test_paper_glass_field_and_case():
     assert k.mask.shape == (40, 20, 20) and k.G.shape == k.mask.shape
     assert np.array_equal(k.mask, (k.G >= 0.5).astype(np.uint8))
     assert k.params["phi_face_mask"] == 0 and k.params["dirichlet_faces"] == 1 << 5
+    assert k.params["rho_c_separate"] == 1 and k.params["L"] == pi.L_TAB1
+    assert pi.case_paper(40, seed=5, materials="cases").params.get("rho_c_separate", 0) == 0
     # cap from 11/12 L3 up; nucleation disk inside 0.87..0.97 L3
     x3 = np.arange(40) + 0.5
     assert np.all(k.mask[x3 > 11 / 12 * 40 + 1] == 1)

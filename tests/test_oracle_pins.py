@@ -59,6 +59,11 @@ def test_input_constants_match_tables():
     assert pi.ALPHA_LARGE_SIGMA == GOLD["table2"]["alpha_large_printed"]
     assert pi.T_STAR == GOLD["table1"]["T_star"]
     assert pi.MU == GOLD["table1"]["mu"]
+    t1 = GOLD["table1"]
+    assert pi.RHO_TAB1 == (t1["rho"]["L"], t1["rho"]["I"], t1["rho"]["G"])
+    assert pi.C_TAB1 == (t1["c"]["L"], t1["c"]["I"], t1["c"]["G"])
+    assert pi.LAM_TAB1 == (t1["lambda"]["L"], t1["lambda"]["I"], t1["lambda"]["G"])
+    assert pi.L_TAB1 == t1["L"]
 
 
 # --------------------------------------------------------------------------
