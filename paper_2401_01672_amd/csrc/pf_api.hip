@@ -429,8 +429,28 @@ int autotune_measure(pf_handle* h) {
   // passes run in attempt order with an event between each two (each reads
   // what its predecessor wrote, as in a run); each pass keeps its fastest
   // depth (median of three timed repetitions after a warm-up), and the kernel
-  // form with the smaller sum of per-pass minima wins.
-  const int zcands[] = {1, 2, 4, 8, 16, 32};
+  // form with the smaller sum of per-pass minima wins.  Besides powers of
+  // two, the candidates include the depths whose grid is one or two whole
+  // rounds of resident workgroups at 2..4 per CU (no partly filled last
+  // round on large grids).
+  int cus = 0, cdev = 0;
+  PF_HIP(h, hipGetDevice(&cdev));
+  PF_HIP(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cdev));
+  auto depth_cands = [&](int vec) {
+    std::vector<int> zs = {1, 2, 4, 8, 16, 32};
+    int tp1 = 0, tz1 = 0;
+    pf::grid_blocks(h->mc, 1, vec ? pf::vec_cells(h->esize) : 1, &tp1, &tz1);
+    for (int per_cu = 2; per_cu <= 4; ++per_cu)
+      for (int rounds = 1; rounds <= 2; ++rounds) {
+        const long long nz = ((long long)rounds * per_cu * cus + tp1 - 1) / tp1;
+        if (nz < 1 || nz > h->P.n3) continue;
+        const int zc = (int)((h->P.n3 + nz - 1) / nz);
+        bool have = false;
+        for (int z : zs) have = have || z == zc;
+        if (!have) zs.push_back(zc);
+      }
+    return zs;
+  };
   int best_vec = h->vec, best_z[6] = {0, h->z_chunk, h->z_chunk, h->z_chunk, h->z_chunk,
                                       h->z_chunk};
   float best_total = 1e30f;
@@ -443,8 +463,8 @@ int autotune_measure(pf_handle* h) {
     float bst[6];
     int bz[6] = {0, 0, 0, 0, 0, 0};
     for (int st = 0; st < 6; ++st) bst[st] = 1e30f;
-    for (int zc : zcands) {
-      if (zc > h->P.n3 && zc != zcands[0]) continue;
+    for (int zc : depth_cands(vec)) {
+      if (zc > h->P.n3 && zc != 1) continue;
       if (set_tiles(h, zc)) continue;
       float reps[3][6];
       for (int rep = 0; rep < 4; ++rep) {

@@ -46,6 +46,10 @@ __device__ __forceinline__ double dmax_nf(double a, double v) {
   v = (v <= DBL_MAX) ? v : INFINITY;
   return v > a ? v : a;
 }
+__device__ __forceinline__ float dmax_nf(float a, float v) {
+  v = (v <= FLT_MAX) ? v : INFINITY;
+  return v > a ? v : a;
+}
 
 template <typename R>
 __device__ __forceinline__ R limiter(R w, R e0, R inv_de) {
@@ -109,15 +113,16 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&ops)[N
 // ---------------------------------------------------------------------------
 // Right-hand side of one cell.
 
-// x if bit f of code is set, else +0: a sign-extended bit field used as an
-// and-mask (two VALU operations, no compare/select).
-__device__ __forceinline__ float keep_if_bit(unsigned code, int f, float x) {
-  const int msk = ((int)(code << (31 - f))) >> 31;
+// x if bit f of code is set, else +0: the sign-extended bit (one bit-field
+// extract) used as an and-mask, with no compare/select.
+__device__ __forceinline__ int bit_mask(unsigned code, int f) {
+  return __builtin_amdgcn_sbfe((int)code, (unsigned)f, 1u);
+}
+__device__ __forceinline__ float keep_if_mask(int msk, float x) {
   return __int_as_float(__float_as_int(x) & msk);
 }
-__device__ __forceinline__ double keep_if_bit(unsigned code, int f, double x) {
-  const long long msk = (long long)(((int)(code << (31 - f))) >> 31);
-  return __longlong_as_double(__double_as_longlong(x) & msk);
+__device__ __forceinline__ double keep_if_mask(int msk, double x) {
+  return __longlong_as_double(__double_as_longlong(x) & (long long)msk);
 }
 
 // Sigma limiter with the clamp as one med3 (FP32); s = w inv - e0 inv.
@@ -188,7 +193,7 @@ struct CellRHS {
     const bool glass = code & kGlassBit;
     R lap = R(0);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) lap += keep_if_bit(code, f, phn[f] - phic);
+    for (int f = 0; f < 6; ++f) lap += keep_if_mask(bit_mask(code, f), phn[f] - phic);
     R f;
     if (REACT == PF_REACT_GRADP) {
       // eq. reaction-term-GradP: 2 phi (1 - phi)(phi - 1/2) + xi^2 mu alpha |grad phi| (T* - T)
@@ -1117,6 +1122,9 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   };
 
   double red0 = 0.0;
+  // S1's maximum of |k1_phi| in the field precision (max is exact in any
+  // precision; widened to FP64 once per tile)
+  R red1 = R(0);
   // The workgroup's quads are the run [q0, q0 + kBlock) of the plane's quads
   // (Q per x1-row).  Per plane, the stencil input of the run and of the Q
   // quads on either side (the rows below and above) is staged in LDS, double
@@ -1135,16 +1143,50 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   const bool xm_remote = xm_in && (lane == 0);
   const bool xp_remote = xp_in && (lane == 63 || p + VW >= plane);
   const unsigned dirf = (unsigned)m.dirichlet_faces;
+  // LDS slots of the x2 neighbours; on a boundary face the cell's own slot
+  // (the face then carries the cell's own value)
+  const uint32_t sym = ym_in ? t : Q + t, syp = yp_in ? 2u * Q + t : Q + t;
 
   // z window of the stencil input, and the cell's own k1 (S2) or y, k1, k3 (S4)
   Quad<R> cm[3], cc[3], cp[3];
   Quad<R> rc[3][3], rp[3][3];
   uint32_t n = p + plane * (uint32_t)z0;
+  // Loads whose values a plane needs right after its barrier (the halo rows,
+  // the cell codes) are issued one plane ahead, so that their latency
+  // overlaps the previous plane's arithmetic.  The halo prefetch holds one
+  // quad per thread: it applies when both rows together have at most kBlock
+  // quads, and to passes whose stencil input is a single load (in S2 and S4
+  // it is a combination of two or three loads, whose extra registers would
+  // cost occupancy).
+  constexpr bool kHaloPf = !(STAGE == 2 || STAGE == 4);
+  const bool hpf = kHaloPf && 2u * Q <= (uint32_t)kBlock;
+  const long long hq = t < Q ? (long long)q0 - (long long)Q + t : (long long)(q0 + kBlock + t - Q);
+  const bool hown = hpf && t < 2u * Q && hq >= 0 && hq < (long long)nq;
+  const uint32_t hsl = t < Q ? t : t + kBlock;
+  Quad<R> hr[3];
+  uint32_t codes_nx = 0;
+  if (hown) {
+#pragma unroll
+    for (int v = 0; v < NL; ++v) hr[v] = ldin(v, plane * (uint32_t)z0 + (uint32_t)hq * VW, nullptr);
+  }
+  auto ld_codes = [&](uint32_t i) -> uint32_t {
+    if constexpr (VW == 4) return *reinterpret_cast<const uint32_t*>(a.code + i);
+    else return *reinterpret_cast<const uint16_t*>(a.code + i);
+  };
+  // Passes with a single-load stencil input also keep the x3 window one
+  // plane deeper: the plane above is loaded one iteration before its use.
+  constexpr bool kDeep = STAGE == 0 || STAGE == 1 || STAGE == 3;
+  Quad<R> cn[3];
   if (active) {
+    codes_nx = ld_codes(n);
 #pragma unroll
     for (int v = 0; v < NL; ++v) {
       cc[v] = ldin(v, n, rc[v]);
       cm[v] = z0 > 0 ? ldin(v, n - plane, nullptr) : cc[v];
+      if constexpr (kDeep) {
+        cp[v] = cc[v];
+        if (z0 + 1 < m.n3) cp[v] = ldin(v, n + plane, nullptr);
+      }
     }
   }
   for (int z = z0; z < z1; ++z, n += plane) {
@@ -1152,25 +1194,38 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     Quad<R>* L = lds + (size_t)((z - z0) & 1) * NL * W;
     Quad<R> ym[3], yp[3];
     R xl[3], xr[3];
-    uint32_t codes = 0;
+    const uint32_t codes = codes_nx;
     if (active) {
-      if constexpr (VW == 4) codes = *reinterpret_cast<const uint32_t*>(a.code + n);
-      else codes = *reinterpret_cast<const uint16_t*>(a.code + n);
+      if (z + 1 < z1) codes_nx = ld_codes(n + plane);
 #pragma unroll
       for (int v = 0; v < NL; ++v) {
-        cp[v] = zp_in ? ldin(v, n + plane, rp[v]) : cc[v];
+        if constexpr (kDeep) {
+          if (z + 2 < m.n3 && z + 1 < z1) cn[v] = ldin(v, n + 2u * plane, nullptr);
+        } else {
+          cp[v] = zp_in ? ldin(v, n + plane, rp[v]) : cc[v];
+        }
         L[v * W + Q + t] = cc[v];
       }
     }
     // the rows below and above the run, in this plane
     const uint32_t zoff = plane * (uint32_t)z;
-    for (uint32_t h = t; h < 2u * Q; h += kBlock) {
-      const long long hq = h < Q ? (long long)q0 - (long long)Q + h : (long long)(q0 + kBlock + h - Q);
-      if (hq >= 0 && hq < (long long)nq) {
-        const uint32_t sl = h < Q ? h : h + kBlock;
+    if (hpf) {
+      if (hown) {
 #pragma unroll
-        for (int v = 0; v < NL; ++v)
-          L[v * W + sl] = ldin(v, zoff + (uint32_t)hq * (uint32_t)VW, nullptr);
+        for (int v = 0; v < NL; ++v) {
+          L[v * W + hsl] = hr[v];
+          if (z + 1 < z1) hr[v] = ldin(v, zoff + plane + (uint32_t)hq * VW, nullptr);
+        }
+      }
+    } else {
+      for (uint32_t h = t; h < 2u * Q; h += kBlock) {
+        const long long hh = h < Q ? (long long)q0 - (long long)Q + h : (long long)(q0 + kBlock + h - Q);
+        if (hh >= 0 && hh < (long long)nq) {
+          const uint32_t sl = h < Q ? h : h + kBlock;
+#pragma unroll
+          for (int v = 0; v < NL; ++v)
+            L[v * W + sl] = ldin(v, zoff + (uint32_t)hh * (uint32_t)VW, nullptr);
+        }
       }
     }
     __syncthreads();
@@ -1184,10 +1239,8 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       // a boundary face carries the cell's own value
       if (!xm_in) xl[v] = cc[v].v[0];
       if (!xp_in) xr[v] = cc[v].v[VW - 1];
-      ym[v] = cc[v];
-      yp[v] = cc[v];
-      if (active && ym_in) ym[v] = L[v * W + t];
-      if (active && yp_in) yp[v] = L[v * W + 2u * Q + t];
+      ym[v] = L[v * W + sym];
+      yp[v] = L[v * W + syp];
     }
     if (active) {
       const unsigned inb_c = (ym_in ? 4u : 0u) | (yp_in ? 8u : 0u) | (z > 0 ? 16u : 0u) |
@@ -1242,7 +1295,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
         kq[1].v[k] = kt;
         // equilibrium measure (no phase-field equation in the Temp model)
         if (STAGE == 1 && MODEL != PF_MODEL_TEMP && !(code & kGlassBit))
-          red0 = dmax_nf(red0, fabs((double)kp));
+          red1 = dmax_nf(red1, fabs(kp));
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1287,6 +1340,9 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       for (int v = 0; v < NL; ++v) {
         cm[v] = cc[v];
         cc[v] = cp[v];
+        if constexpr (kDeep) {
+          if (z + 2 < m.n3) cp[v] = cn[v];  // else cp stays the new cc
+        }
         if constexpr (STAGE == 2) rc[v][1] = rp[v][1];
         if constexpr (STAGE == 4) {
 #pragma unroll
@@ -1295,6 +1351,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       }
     }
   }
+  if (STAGE == 1) red0 = (double)red1;
   // the plane buffers are reused by the next tile of a persistent block
   __syncthreads();
   if (STAGE == 1) {
