@@ -289,7 +289,10 @@ def run_gpu(args, wl):
             kl = kl.replace("stage4_kernel", "stage_kernel")
         per_pass.append(dict(pass_=PASS_NAMES[sched][i], kernel=kl,
                              ms=round(ms[i], 5), bytes_per_cell=sb[i], gbs=round(gbs, 1)))
-    dom = max(range(npass), key=lambda i: ms[i])
+    # the dominant kernel: the pass that moves the most bytes (also the
+    # longest one; choosing by bytes keeps the choice stable under a profiler,
+    # which lengthens the first launch after each timing event)
+    dom = max(range(npass), key=lambda i: (sb[i], ms[i]))
     step_ms = sum(ms[:npass]) + ms[5]
     src_hash = kernel_source_hash()
     kname = f"{sched}_pass{dom + 1}"
