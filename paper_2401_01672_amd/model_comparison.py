@@ -11,6 +11,14 @@ with adaptive Merson steps, and reports per run the range of phi over the
 water cells, the ice fraction, and how the run ended (a step size collapsing
 below dt_min is the instability).
 
+The Temp model (Sec. 2.3: phi follows T through eq.
+explicit-p-dependence-on-T) has no phase-field equation and no attachment
+coefficient; the paper finds its ice volume insensitive to the transition
+rate gamma (2 against 10) and to the mesh resolution.  ``run_temp`` runs it on
+the same vessel and reports the ice fraction of the water volume and of the
+whole box and the final temperature field, so that runs at two values of gamma
+or two resolutions can be compared.
+
 Run ``python -m paper_2401_01672_amd.model_comparison --help``.
 """
 from __future__ import annotations
@@ -54,6 +62,28 @@ def run_one(c, reaction: str, t_end: float, budget: int) -> Dict:
                 ice_fraction=float(st["ice_fraction"]), wall_s=wall)
 
 
+def run_temp(n3: int, gamma: float, t_end: float, budget: int, seed: int = 5) -> Dict:
+    """Temp model on the paper-mode vessel of height n3 cells to t_end."""
+    import paper_2401_01672_amd as pf
+    c = pi.case_paper(n3, seed=seed, model="temp")
+    p = dict(c.params, gamma=gamma)
+    s = pf.Solver(p, None, "fp64", dict(c.run, dt_min=DT_MIN), glass_field=c.G)
+    s.set_state(None, c.T0 - pi.T_STAR)
+    s.set_time(0.0, 1e-3)
+    t0 = time.perf_counter()
+    st = s.integrate(t_end=t_end, max_steps=budget, raise_on_error=False)
+    wall = time.perf_counter() - t0
+    _, theta = s.get_state()
+    s.close()
+    water = int(np.count_nonzero(c.G < 0.5))
+    ice = float(st["ice_fraction"]) * water
+    return dict(model="temp", n3=n3, gamma=gamma, status=int(st["status"]), t=float(st["t"]),
+                attempts=int(st["steps_accepted"] + st["steps_rejected"]),
+                ice_fraction=float(st["ice_fraction"]), ice_fraction_box=ice / c.G.size,
+                theta_min=float(theta.min()), theta_max=float(theta.max()), wall_s=wall,
+                theta=theta)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--n3", type=int, default=100)
@@ -61,6 +91,9 @@ def main():
     ap.add_argument("--budget", type=int, default=400000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--out", default="")
+    ap.add_argument("--temp-n3", default="",
+                    help="comma-separated vessel heights for the Temp-model runs "
+                         "(gamma 2 and 10 each); empty: the --n3 vessel")
     a = ap.parse_args()
     cases = {k: pi.case_paper(a.n3, seed=a.seed, alpha=v) for k, v in ALPHAS.items()}
     import torch
@@ -71,6 +104,18 @@ def main():
             r = dict(setting=name, alpha=ALPHAS[name], **run_one(c, reaction, a.t_end, a.budget))
             res.append(r)
             print(json.dumps(r), flush=True)
+    temp_n3 = [int(v) for v in a.temp_n3.split(",") if v] or [a.n3]
+    for n3 in temp_n3:
+        th = {}
+        for gamma in (2.0, 10.0):
+            r = run_temp(n3, gamma, a.t_end, a.budget, a.seed)
+            th[gamma] = r.pop("theta")
+            res.append(r)
+            print(json.dumps(r), flush=True)
+        d = dict(model="temp", n3=n3, compare="gamma 2 vs 10",
+                 max_abs_dtheta=float(np.max(np.abs(th[2.0] - th[10.0]))))
+        res.append(d)
+        print(json.dumps(d), flush=True)
     if a.out:
         json.dump(dict(results=res, args=vars(a)), open(a.out, "w"), indent=1)
 

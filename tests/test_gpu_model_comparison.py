@@ -1,8 +1,9 @@
 """The model comparison of Sec. 3.2 at a small scale: on the paper-mode
 vessel SigmaP1-P keeps phi in [0, 1] at every attachment coefficient of
 Tab. 2, while GradP leaves [0, 1] and, at the "tiny sigma" coefficient, its
-step size collapses (the instability the paper reports).  The GPU runs are
-checked against the oracle on the same runs."""
+step size collapses (the instability the paper reports); the Temp model's
+ice volume hardly depends on gamma or on the mesh resolution.  The GPU runs
+are checked against the oracle on the same runs."""
 import numpy as np
 import pytest
 
@@ -61,4 +62,49 @@ def test_comparison_runs_match_oracle(cases, reaction):
     # adaptive runs: the step sequences agree up to roundoff-sized error
     # estimates, so the states agree to the tolerance level
     assert np.abs(ph - ph_o).max() <= 1e-5
+    assert np.abs(th - (T_o - pi.T_STAR)).max() <= 1e-5 * np.abs(T_o - pi.T_STAR).max()
+
+
+# Temp model (Sec. 2.3, Sec. 3.2 "properties of the Temp model"): runs to
+# 30 min of cooling on the same vessel
+T_END_TEMP = 1800.0
+
+
+def test_temp_ice_volume_weakly_depends_on_gamma():
+    """The transition rate gamma (2 against 10) changes the interface
+    thickness, but the ice volume and the temperature field hardly move."""
+    r2 = MC.run_temp(N3, 2.0, T_END_TEMP, 400000)
+    r10 = MC.run_temp(N3, 10.0, T_END_TEMP, 400000)
+    for r in (r2, r10):
+        assert r["status"] == 0 and r["t"] == T_END_TEMP, r
+    assert r2["ice_fraction"] > 0.05
+    assert abs(r2["ice_fraction"] - r10["ice_fraction"]) <= 0.02 * r2["ice_fraction"]
+    span = r2["theta_max"] - r2["theta_min"]
+    assert np.abs(r2["theta"] - r10["theta"]).max() <= 0.05 * span
+
+
+def test_temp_ice_volume_mesh_resolution():
+    """Ice volume over the whole box on two resolutions of the vessel
+    (heights 80 and 100 cells): within 3% of each other."""
+    a = MC.run_temp(80, 2.0, T_END_TEMP, 400000)
+    b = MC.run_temp(100, 2.0, T_END_TEMP, 400000)
+    assert a["status"] == 0 and b["status"] == 0
+    assert abs(a["ice_fraction_box"] - b["ice_fraction_box"]) <= 0.03 * b["ice_fraction_box"]
+
+
+def test_temp_run_matches_oracle():
+    """A 20 s adaptive Temp-model run on the vessel, GPU against the oracle."""
+    c = pi.case_paper(N3, seed=5, model="temp")
+    P = oracle.make_params(c.params)
+    ctl = oracle.make_ctl(tol=c.run["tol"], dt_min=MC.DT_MIN)
+    _, T_o, ost = oracle.integrate(P, c.G, ctl, 0.0, 1e-3, None, c.T0, t_end=20.0,
+                                   max_steps=100000)
+    import paper_2401_01672_amd as pf
+    s = pf.Solver(c.params, None, "fp64", dict(c.run, dt_min=MC.DT_MIN), glass_field=c.G)
+    s.set_state(None, c.T0 - pi.T_STAR)
+    s.set_time(0.0, 1e-3)
+    st = s.integrate(t_end=20.0, max_steps=100000)
+    _, th = s.get_state()
+    s.close()
+    assert st["t"] == ost["t"] == 20.0
     assert np.abs(th - (T_o - pi.T_STAR)).max() <= 1e-5 * np.abs(T_o - pi.T_STAR).max()
