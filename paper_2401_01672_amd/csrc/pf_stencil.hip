@@ -582,24 +582,24 @@ __device__ void controller_body(DevCtl* ctl, const double* p1, int np1, const do
                                 int np5, double h3, double* smem) {
   __syncthreads();  // smem reuse across consecutive calls
   if (ctl->done) return;
-  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < np1; i += blockDim.x) {
+  // Only the maxima are reduced per attempt: the stage kernels leave the
+  // partial sums of the state (slots 1..3) at zero, and runs report those
+  // sums from a diagnostics pass over the final state.
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < np1; i += blockDim.x)
     v[0] = dmax_nf(v[0], p1[(size_t)i * kPartS1 + 0]);
-    v[1] += p1[(size_t)i * kPartS1 + 1];
-    v[2] += p1[(size_t)i * kPartS1 + 2];
-    v[3] += p1[(size_t)i * kPartS1 + 3];
-  }
-  for (int i = threadIdx.x; i < np5; i += blockDim.x) v[4] = dmax_nf(v[4], p5[i]);
-  const int ops[5] = {1, 0, 0, 0, 1};
-  block_reduce<5>(v, ops, smem);
+  for (int i = threadIdx.x; i < np5; i += blockDim.x) v[1] = dmax_nf(v[1], p5[i]);
+  const int ops[2] = {1, 1};
+  block_reduce<2>(v, ops, smem);
   if (threadIdx.x != 0) return;
+  (void)h3;
 
   DevCtl c = *ctl;
   c.maxk1 = v[0];
-  c.sum_phi = v[1];
-  c.enthalpy = v[2] * h3;
-  c.ice = v[3];
-  const double eps = v[4];
+  c.sum_phi = 0.0;
+  c.enthalpy = 0.0;
+  c.ice = 0.0;
+  const double eps = v[1];
   c.eps = eps;
   c.dt_used = c.dt_att;
   c.accepted = 0;
