@@ -1114,13 +1114,20 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   int2* ditems = nullptr;
   int* dact = nullptr;
   unsigned* dbar = nullptr;  // [0] arrivals, [1] generation, [2] barrier-overrun flag
+  DevCtl* dgath = nullptr;   // control blocks of the running instances, gathered per poll
+  DevCtl* hgath = nullptr;   // pinned host copy
   if (hipMalloc(&ddesc, sizeof(pf::BatchDesc) * n) != hipSuccess ||
       hipMalloc(&ditems, sizeof(int2) * (size_t)(max_items > 0 ? max_items : 1)) != hipSuccess ||
       hipMalloc(&dact, sizeof(int) * n) != hipSuccess ||
-      hipMalloc(&dbar, 4 * sizeof(unsigned)) != hipSuccess) {
+      hipMalloc(&dbar, 4 * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&dgath, sizeof(DevCtl) * n) != hipSuccess ||
+      hipHostMalloc((void**)&hgath, sizeof(DevCtl) * n, hipHostMallocDefault) != hipSuccess) {
     (void)hipFree(ddesc);
     (void)hipFree(ditems);
     (void)hipFree(dact);
+    (void)hipFree(dbar);
+    (void)hipFree(dgath);
+    if (hgath) (void)hipHostFree(hgath);
     return fail(h0, PF_ENOMEM, "batch: descriptor allocation failed");
   }
   hipGraphExec_t gexec = nullptr;
@@ -1132,6 +1139,8 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     (void)hipFree(ditems);
     (void)hipFree(dact);
     (void)hipFree(dbar);
+    (void)hipFree(dgath);
+    (void)hipHostFree(hgath);
   };
   unsigned hbar[4] = {0, 0, 0, 0};
   if (hipMemcpyAsync(dbar, hbar, sizeof(hbar), hipMemcpyHostToDevice, s) != hipSuccess) {
@@ -1212,17 +1221,20 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       cleanup();
       return fail(h0, PF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
-    for (int i : act)
-      if (hipMemcpyAsync(inst[i]->hctl, inst[i]->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s) !=
-          hipSuccess) {
-        cleanup();
-        return fail(h0, PF_EHIP, "batch: control readback failed");
-      }
+    // the running instances' control blocks: one gather, one copy (dact
+    // lists them in the order of act)
+    if (pf::launch_gather_ctl(ddesc, dact, (int)act.size(), dgath, s) != hipSuccess ||
+        hipMemcpyAsync(hgath, dgath, sizeof(DevCtl) * act.size(), hipMemcpyDeviceToHost, s) !=
+            hipSuccess) {
+      cleanup();
+      return fail(h0, PF_EHIP, "batch: control readback failed");
+    }
     if (hipMemcpyAsync(hbar, dbar, sizeof(hbar), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       cleanup();
       return fail(h0, PF_EHIP, "batch: synchronize failed");
     }
+    for (size_t k = 0; k < act.size(); ++k) *inst[act[k]]->hctl = hgath[k];
     if (hbar[2]) {
       cleanup();
       return fail(h0, PF_EHIP, "batch: a grid barrier wait overran its bound");
@@ -1232,7 +1244,16 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       if (!inst[i]->hctl->done) still.push_back(i);
     if (still.size() == act.size()) continue;
     act.swap(still);
-    if (act.empty() || mode == 1) continue;
+    if (act.empty()) continue;
+    if (mode == 1) {  // the persistent kernel keeps its table; dact follows act for the gather
+      if (hipMemcpyAsync(dact, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        return fail(h0, PF_EHIP, "batch: instance list upload failed");
+      }
+      continue;
+    }
     int rc = build();  // fewer instances: smaller grids, maybe thinner tiles
     if (rc) {
       cleanup();

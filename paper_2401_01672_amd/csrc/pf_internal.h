@@ -182,4 +182,8 @@ int batch_max_blocks(int precision, int model, size_t lds);
 hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
                              int nitems, const int* inst_list, int ninst, size_t lds,
                              hipStream_t s);
+// control blocks of the instances in inst_list, gathered into out[ninst]
+// (one device-to-host copy per poll instead of one per instance)
+hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ninst,
+                             DevCtl* out, hipStream_t s);
 }  // namespace pf

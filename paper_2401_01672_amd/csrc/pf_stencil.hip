@@ -776,6 +776,25 @@ __global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc,
   controller_body(d.st[0].ctl, d.p1, d.ntiles, d.p5, d.ntiles, d.h3, smem);
 }
 
+// One workgroup of 64 lanes per listed instance copies its control block.
+__global__ __launch_bounds__(64) void gather_ctl_kernel(const BatchDesc* desc,
+                                                        const int* inst_list, DevCtl* out) {
+  static_assert(sizeof(DevCtl) % 8 == 0, "control block of whole doubles");
+  constexpr int kWords = (int)(sizeof(DevCtl) / 8);
+  const unsigned long long* src =
+      reinterpret_cast<const unsigned long long*>(desc[inst_list[blockIdx.x]].st[0].ctl);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(out + blockIdx.x);
+  for (int w = threadIdx.x; w < kWords; w += 64) dst[w] = src[w];
+}
+
+hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ninst,
+                             DevCtl* out, hipStream_t s) {
+  if (ninst < 1) return hipSuccess;
+  hipLaunchKernelGGL(gather_ctl_kernel, dim3((unsigned)ninst), dim3(64), 0, s, desc, inst_list,
+                     out);
+  return hipGetLastError();
+}
+
 template <typename R, int MODEL>
 static hipError_t launch_batch_step_t(const BatchDesc* desc, const int2* items, int nitems,
                                       const int* inst_list, int ninst, size_t lds,
