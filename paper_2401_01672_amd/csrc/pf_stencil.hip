@@ -1449,7 +1449,6 @@ __global__ __launch_bounds__(TX* TY) void pair_kernel(PairArgs a) {
   constexpr int NV = kCoupled ? 2 : 1;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;  // staged input region
   constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;  // first-stage region
-  constexpr int NRING = N1 - NT;
   __shared__ R inS[3][NV][N2];
   __shared__ R midS[3][NV][N1];
   __shared__ double smem[8 * (NT / 64)];
