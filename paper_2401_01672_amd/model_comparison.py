@@ -17,7 +17,8 @@ coefficient; the paper finds its ice volume insensitive to the transition
 rate gamma (2 against 10) and to the mesh resolution.  ``run_temp`` runs it on
 the same vessel and reports the ice fraction of the water volume and of the
 whole box and the final temperature field, so that runs at two values of gamma
-or two resolutions can be compared.
+or two resolutions can be compared.  ``--sigma-n3`` runs the same resolution
+study for SigmaP1-P (the paper's convergence check, Sec. 3.2).
 
 Run ``python -m paper_2401_01672_amd.model_comparison --help``.
 """
@@ -56,10 +57,12 @@ def run_one(c, reaction: str, t_end: float, budget: int) -> Dict:
     phi, _ = s.get_state()
     s.close()
     water = c.G < 0.5
+    nwater = int(np.count_nonzero(water))
     return dict(reaction=reaction, status=int(st["status"]), t=float(st["t"]),
                 attempts=int(st["steps_accepted"] + st["steps_rejected"]),
                 phi_max=float(np.max(phi[water])), phi_min=float(np.min(phi[water])),
-                ice_fraction=float(st["ice_fraction"]), wall_s=wall)
+                ice_fraction=float(st["ice_fraction"]),
+                ice_fraction_box=float(st["ice_fraction"]) * nwater / c.G.size, wall_s=wall)
 
 
 def run_temp(n3: int, gamma: float, t_end: float, budget: int, seed: int = 5) -> Dict:
@@ -94,6 +97,9 @@ def main():
     ap.add_argument("--temp-n3", default="",
                     help="comma-separated vessel heights for the Temp-model runs "
                          "(gamma 2 and 10 each); empty: the --n3 vessel")
+    ap.add_argument("--sigma-n3", default="",
+                    help="comma-separated vessel heights for a resolution study of "
+                         "SigmaP1-P at the 'large sigma' coefficient (ice over the box)")
     a = ap.parse_args()
     cases = {k: pi.case_paper(a.n3, seed=a.seed, alpha=v) for k, v in ALPHAS.items()}
     import torch
@@ -104,6 +110,11 @@ def main():
             r = dict(setting=name, alpha=ALPHAS[name], **run_one(c, reaction, a.t_end, a.budget))
             res.append(r)
             print(json.dumps(r), flush=True)
+    for n3 in [int(v) for v in a.sigma_n3.split(",") if v]:
+        c = pi.case_paper(n3, seed=a.seed, alpha=ALPHAS["large_sigma"])
+        r = dict(setting="large_sigma", n3=n3, **run_one(c, "sigma", a.t_end, a.budget))
+        res.append(r)
+        print(json.dumps(r), flush=True)
     temp_n3 = [int(v) for v in a.temp_n3.split(",") if v] or [a.n3]
     for n3 in temp_n3:
         th = {}
