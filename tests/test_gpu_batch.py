@@ -207,6 +207,7 @@ def test_sweep_fp32_batch_matches_fp64_runs():
         assert st32["status"] == st64["status"] == pf.PF_EQUILIBRIUM
         assert st32["pore_count"] == st64["pore_count"]
         d_uwc = abs(st32["ice_count"] - st64["ice_count"]) / st64["pore_count"]
+        print(f"sweep instance {c.name}: FP32 batch vs FP64 run, UWC difference {d_uwc:.2e}")
         assert d_uwc <= 1e-3, (c.name, st32["ice_count"], st64["ice_count"])
     for s in ss:
         s.close()

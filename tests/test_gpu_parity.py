@@ -254,8 +254,12 @@ def test_fp32_micro32_adaptive_within_precision_bounds():
     assert st["status"] == pf.PF_OK and st["t"] == t_end
     g, _ = s.get_state()
     od = oracle.diagnostics(P, c.mask, ph_o)
-    assert np.abs(g.astype(np.float64) - ph_o).max() <= 1e-4
-    assert abs(st["ice_fraction"] - od["ice_fraction"]) <= 1e-3 * od["ice_fraction"]
+    dphi = np.abs(g.astype(np.float64) - ph_o).max()
+    dice = abs(st["ice_fraction"] - od["ice_fraction"]) / od["ice_fraction"]
+    print(f"micro 32^3 FP32 vs FP64 oracle at t = {t_end}: max|dphi| = {dphi:.2e}, "
+          f"ice fraction rel. error = {dice:.2e}")
+    assert dphi <= 1e-4
+    assert dice <= 1e-3
     s.close()
 
 
@@ -276,8 +280,11 @@ def test_coupled_crop_fp32_vs_fp64_oracle():
     g, th = s.get_state()
     od = oracle.diagnostics(P, c.mask, ph_o, T_o)
     dphi = np.abs(g.astype(np.float64) - ph_o).max()
+    dice = abs(st["ice_fraction"] - od["ice_fraction"])
+    print(f"64^3 crop FP32 vs FP64 oracle at t = {t_end}: max|dphi| = {dphi:.2e}, "
+          f"ice fraction {od['ice_fraction']:.4f}, abs. error = {dice:.2e}")
     assert dphi <= 1e-4, dphi
-    assert abs(st["ice_fraction"] - od["ice_fraction"]) <= 1e-3 * max(od["ice_fraction"], 1e-3)
+    assert dice <= 1e-3 * max(od["ice_fraction"], 1e-3)
     # latent heat ties theta to phi: a phase-field gap d gives a temperature gap
     # of up to (Lv / min rho c) d, so the phi bound carries over to theta
     th_bound = c.params["Lv"] / min(c.params["rhoc"]) * 1e-4
