@@ -217,3 +217,42 @@ def test_autotune_choice_is_reused_by_equal_handles():
     assert outs[0][0] == outs[1][0]
     assert outs[0][2] == outs[1][2]
     assert np.array_equal(outs[0][1][0], outs[1][1][0])
+
+
+@pytest.mark.parametrize("model", ["ac", "coupled"])
+@pytest.mark.parametrize("shape", [(5, 3, 600), (4, 2, 1024), (2, 9, 12)])
+def test_vector_fp32_depths_and_wide_rows(model, shape):
+    """FP32 vector passes where the two halo rows exceed one vector per
+    thread (n1 = 600, 1024: halo rows loaded in the plane they serve) and on a
+    two-plane grid, at several planes per column (1, 2, 3 and the whole
+    height: the plane-ahead loads stop at every column end): every depth gives
+    the same state bitwise, equal to the one-cell kernels' within FP32
+    rounding and to the oracle within the FP32 bound."""
+    p, mask, phi, T = rand_problem(shape, model, 91, faces=1 << 4, bc_kind=1)
+    dt = 2e-3 if model == "coupled" else 0.5
+    coupled = model == "coupled"
+    outs = []
+    for vec, z in [(True, 1), (True, 2), (True, 3), (True, shape[0]), (False, 2)]:
+        s = pf.Solver(p, mask, "fp32", dict(tol=0.0))
+        s.set_schedule("five")
+        s.set_vector(vec)
+        s.set_tile(z)
+        s.set_state(phi.astype(np.float32), (T - T_STAR).astype(np.float32) if coupled else None)
+        s.set_time(0.0, dt)
+        st = s.integrate(max_steps=4)
+        assert st["steps_accepted"] == 4
+        cfg = s.get_config()
+        assert cfg["vector"] == vec and cfg["stage_z_chunk"] == [min(z, shape[0])] * 5, cfg
+        outs.append(s.get_state())
+        s.close()
+    for o in outs[1:4]:
+        assert np.array_equal(o[0], outs[0][0])
+        if coupled:
+            assert np.array_equal(o[1], outs[0][1])
+    assert rel(outs[0][0], outs[4][0]) <= 2e-6
+    P = oracle.make_params(p)
+    ph_o, T_o, _ = oracle.integrate(P, mask, oracle.make_ctl(tol=0.0), 0.0, dt, phi,
+                                    T if coupled else None, max_steps=4)
+    assert rel(outs[0][0], ph_o) <= 1e-4
+    if coupled:
+        assert rel(outs[0][1], T_o - T_STAR) <= 1e-4
