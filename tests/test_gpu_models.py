@@ -411,3 +411,29 @@ def test_separate_rho_c_smooth_rhs_matches_oracle():
     kp, kT = oracle_rhs(p, G, 0.2, phi, T)
     gp, gT = gpu_rhs_smooth(p, G, 0.2, phi, T)
     assert rel(gp, kp) <= 1e-12 and rel(gT, kT) <= 1e-12
+
+
+@pytest.mark.parametrize("model,reaction,dt", [("coupled", "sigma", 2e-3), ("temp", "sigma", 2e-3)])
+def test_smooth_vector_wide_rows_fp32(model, reaction, dt):
+    """Paper mode on rows too wide for the one-plane-ahead halo rows (n1 = 600:
+    the unknowns and G are staged in the plane they serve): the vector and
+    one-cell kernels give the same state."""
+    p, G, phi, T = smooth_problem((4, 3, 600), model, reaction, 71, faces=1 << 5, bc_kind=2)
+    G = G.astype(np.float32).astype(np.float64)
+    outs = []
+    for vec in (True, False):
+        s = pf.Solver(p, None, "fp32", dict(tol=0.0), glass_field=G)
+        s.set_vector(vec)
+        assert s.get_config()["vector"] == vec
+        if model == "temp":
+            s.set_state(None, (T - T_STAR).astype(np.float32))
+        else:
+            s.set_state(phi.astype(np.float32), (T - T_STAR).astype(np.float32))
+        s.set_time(0.0, dt)
+        st = s.integrate(max_steps=4)
+        assert st["steps_accepted"] == 4
+        outs.append(s.get_state())
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        if a is not None:
+            assert np.array_equal(a, b)
