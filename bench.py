@@ -1,13 +1,14 @@
 #!/usr/bin/env python3
 """Benchmark: GCUPS of the fused Runge-Kutta-Merson step on one MI355X.
 
-Workload (default): the coupled heat + Allen-Cahn model in FP64 on the
-128^3 glass-bead grid (64 spheres of radius 14 voxels, ~35% solid; bottom
-face held at -5 C, T0 = +1 C; tol 1e-6 adaptive steps).  One benchmark step
-is one adaptive Merson attempt over the whole grid: five fused stage passes,
-the FP64 error-norm and diagnostic reductions and the on-device step
+Workload (default): the coupled heat + Allen-Cahn model on the 256^3
+glass-bead grid (64 spheres of radius 28 voxels, ~35% solid; bottom face
+ramped from -5 C to +5 C over 60 s, T0 = +1 C; tol 1e-6 adaptive steps), FP32
+fields with FP64 error norm, time, step and diagnostic sums.  One benchmark
+step is one adaptive Merson attempt over the whole grid: five fused stage
+passes, the FP64 error-norm and diagnostic reductions and the on-device step
 controller.  GCUPS = cells x attempts / s / 1e9 (every cell counts, glass
-included).
+included).  The 128^3 FP64 case and the other workloads run with --workload.
 
 Prints ONE JSON line.  Inputs are synthetic (seeded random sequential addition
 of spheres) and resident in HBM before the timed region.
@@ -18,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -251,6 +253,39 @@ def make_solver(wl):
     return case, s, model
 
 
+def poll_interval(steps: int, warmup: int, cap: int) -> int:
+    """Attempts per host poll (and per captured graph): the largest value up to
+    cap that divides the timed attempts and, if possible, the warm-up ones too,
+    so that the graph is captured during the warm-up and the timed region
+    issues exactly `steps` attempts as whole graphs."""
+    cap = max(1, cap)
+    both = [d for d in range(1, cap + 1) if steps % d == 0 and (warmup == 0 or warmup % d == 0)]
+    if both and both[-1] >= 4:
+        return both[-1]
+    return max(d for d in range(1, cap + 1) if steps % d == 0)
+
+
+def profile_check(workload: str, kernel_sig: str, event_us: float):
+    """The dominant kernel's working average from the committed rocprofv3
+    kernel-trace summary of this workload, beside the HIP-event mean, if the
+    summary was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"stage_kernels_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"Kernel sources: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return dict(file=os.path.relpath(path, ROOT), current=False)
+    for line in text.splitlines():
+        if line.startswith("| `") and kernel_sig in line:
+            cols = [c.strip() for c in line.strip("|").split("|")]
+            prof_us = float(cols[4])
+            return dict(file=os.path.relpath(path, ROOT), current=True, kernel=kernel_sig,
+                        rocprof_working_avg_us=prof_us, event_avg_us=round(event_us, 2),
+                        ratio=round(event_us / prof_us, 4))
+    return dict(file=os.path.relpath(path, ROOT), current=True, kernel=kernel_sig)
+
+
 def run_gpu(args, wl):
     import torch
 
@@ -258,7 +293,8 @@ def run_gpu(args, wl):
     prec = wl["precision"]
     case, s, model = make_solver(wl)
     run = dict(case.run)
-    s.set_loop(args.steps_per_poll, not args.no_graph)
+    spp = poll_interval(args.steps, args.warmup, args.steps_per_poll)
+    s.set_loop(spp, not args.no_graph)
     if args.schedule != "five":
         s.set_schedule(args.schedule)
     if args.z_chunk:
@@ -305,11 +341,16 @@ def run_gpu(args, wl):
     kname = f"{sched}_pass{dom + 1}"
     traffic = read_traffic(args.workload, kname, src_hash)
     achieved = per_pass[dom]["gbs"]
+    kl = per_pass[dom]["kernel"]
+    ksig = (f"{kl.split('<')[0]}<{'float' if prec == 'fp32' else 'double'}, "
+            f"{1 if model == 'coupled' else 0 if model == 'ac' else 2}, {dom + 1},")
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel=f"{per_pass[dom]['kernel']} = {PASS_NAMES[sched][dom]} "
                        f"({prec}, {model}{', GradP' if 'gradp' in args.workload else ''})",
-                algorithmic_bytes_per_launch=sb[dom] * ncell)
+                algorithmic_bytes_per_launch=sb[dom] * ncell,
+                timing="HIP events on the library's stream (pf_time_kernels)",
+                profile_check=profile_check(args.workload, ksig, ms[dom] * 1e3))
     extra = dict(
         passes=per_pass,
         step_kernels_ms=round(step_ms, 5),
@@ -318,15 +359,17 @@ def run_gpu(args, wl):
         controller_ms=round(ms[5], 5),
         accepted=st["steps_accepted"], rejected=st["steps_rejected"], t_sim=st["t"],
         ice_fraction=st["ice_fraction"], source_hash=src_hash, config=cfg,
+        steps_per_poll=spp, attempts_timed=attempts,
     )
     s.close()
     return gcups, wall, roof, extra, case, prec
 
 
-def cpu_baseline(wl, sample_steps: int):
+def cpu_baseline(wl, cell_updates: float):
     """The FP64 oracle (as it stands) on the same grid for a bounded number of
-    adaptive attempts, timed on this host's cores (all of them, and one: the
-    single-thread rate from a tenth of the sample goes into the detail)."""
+    adaptive attempts (about `cell_updates` cell-updates, at least 2 attempts),
+    timed on this host's cores (all of them, and one: the single-thread rate
+    from a tenth of the sample, at least one attempt, goes into the detail)."""
     import ctypes
 
     import oracle
@@ -348,6 +391,7 @@ def cpu_baseline(wl, sample_steps: int):
         return n, wall, case.ncells * n / wall / 1e9
 
     cores = oracle.num_threads()
+    sample_steps = max(2, int(round(cell_updates / case.ncells)))
     n, wall, rate = timed(sample_steps)
     out = dict(value=round(rate, 5), unit="GCUPS", cores=cores, kind="oracle",
                sample=f"{n} adaptive RKM attempts of the same {case.shape[::-1]} grid in "
@@ -371,13 +415,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="coupled_128_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="coupled_256_fp32", choices=sorted(WORKLOADS))
     ap.add_argument("--steps-per-poll", type=int, default=16)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--z-chunk", type=int, default=0)
     ap.add_argument("--schedule", default="five", choices=["paired", "five"])
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-cell-updates", type=float, default=4.2e8,
+                    help="size of the oracle's timed sample in cell-updates (about 10 s on "
+                         "16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-budget", type=int, default=60000,
                     help="attempt budget per instance of the sweep workload")
@@ -419,7 +465,7 @@ def main():
         print(json.dumps(out))
         return
     gcups, wall, roof, extra, case, prec = run_gpu(args, wl)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_steps)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_cell_updates)
     out = dict(
         metric=METRIC, value=round(gcups, 4), unit="GCUPS", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(wall / args.steps * 1e3, 5),

@@ -946,7 +946,11 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
   int rc = push_ctl(h);
   if (rc) return rc;
   while (!c.done) {
-    if (h->use_graph) {
+    // attempts left in the budget: a shorter tail is launched directly, so a
+    // run issues exactly the attempts it makes (no trailing no-op attempts)
+    const long long left = c.max_steps - (c.n_acc + c.n_rej);
+    const int nissue = left < h->steps_per_poll ? (int)left : h->steps_per_poll;
+    if (h->use_graph && nissue == h->steps_per_poll) {
       if (!h->gexec || h->graph_steps != h->steps_per_poll) {
         drop_graph(h);
         hipGraph_t g;
@@ -963,7 +967,7 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
       }
       PF_HIP(h, hipGraphLaunch(h->gexec, h->stream));
     } else {
-      for (int i = 0; i < h->steps_per_poll; ++i) PF_HIP(h, issue_step(h, h->stream));
+      for (int i = 0; i < nissue; ++i) PF_HIP(h, issue_step(h, h->stream));
     }
     rc = pull_ctl(h);
     if (rc) return rc;

@@ -158,7 +158,7 @@ def kernel_stats(title: str, trace_dir: str, command: str, out: str):
             by.setdefault(r["Kernel_Name"], []).append(d)
     total = sum(sum(v) for v in by.values())
     lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (repo root):", "", "```",
-             command, "```", "",
+             command, "```", "", f"Kernel sources: `{source_hash()}`", "",
              "| kernel | calls | avg us | working calls | working avg us | min us | max us | % time |",
              "|---|---|---|---|---|---|---|---|"]
     for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
