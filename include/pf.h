@@ -417,6 +417,23 @@ int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale
 int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b, int32_t relu,
                   uint16_t* y, int32_t cout, int32_t n1, int32_t n2, int32_t n3,
                   uintptr_t stream);
+/* Allocation-free variant of pf_conv3_bf16, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts and result as
+ * pf_conv3_bf16 (the same kernels), with two differences:
+ *   - the BF16 weight copy is kept in a static device array of the library
+ *     (cin <= 96 and cout <= 96; 486 KiB per device, held until the process
+ *     ends) instead of a per-call allocation: no hipMalloc, hipFree or
+ *     allocating library call is made.  Larger cin or cout give PF_EINVAL
+ *     and a message in pf_last_error(NULL);
+ *   - it is asynchronous on `stream`, whose device must be the current one.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, or another thread) race and give wrong
+ * results.  Returns PF_OK, PF_EINVAL or PF_EHIP (message in
+ * pf_last_error(NULL)). */
+int pf_conv3_bf16_noalloc(const uint16_t* x, int32_t cin, const float* w, const float* b,
+                          int32_t relu, uint16_t* y, int32_t cout, int32_t n1, int32_t n2,
+                          int32_t n3, uintptr_t stream);
 /* Gradients of y = conv3x3x3(x) + b given dy: dw [cout][27][cin], db [cout],
  * and dx [n][cin] if dx is non-NULL (then cin in {16, 32, 48, 64, 96}).
  * (cout/16) * ceil(cin/16) <= 16.  Synchronous. */

@@ -113,6 +113,8 @@ SIGNATURES = [
     ("pf_warmstart", C.c_int, [_H, _H, C.c_double, C.c_double, C.c_int32]),
     ("pf_conv3_bf16", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32,
                                 C.c_int32, C.c_int32, C.c_int32, C.c_size_t]),
+    ("pf_conv3_bf16_noalloc", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32,
+                                        C.c_int32, C.c_int32, C.c_int32, C.c_size_t]),
     ("pf_conv3_bf16_backward", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, C.c_int32,
                                          C.c_int32, C.c_int32, _VP, _VP, _VP, C.c_size_t]),
     ("pf_mfma_probe", C.c_int, [_VP, _VP, _VP, C.c_size_t]),
@@ -498,6 +500,23 @@ def conv3_bf16(x, w, b, relu: bool, cout: int):
                              _dev_ptr(y), cout, n1, n2, n3, 0)
     if rc != 0:
         raise PFError(rc, "pf_conv3_bf16 failed")
+    return y
+
+
+def conv3_bf16_noalloc(x, w, b, relu: bool, y, stream: int = 0):
+    """Building block without allocation: y = act(conv3x3x3(x) + b) into the
+    caller's y (n3, n2, n1, cout) BF16 bits, asynchronous on `stream` (a
+    hipStream_t as int; 0 = the null stream).  Shapes as conv3_bf16."""
+    import torch
+    n3, n2, n1, cin = x.shape
+    cout = y.shape[-1]
+    assert tuple(y.shape[:3]) == (n3, n2, n1)
+    rc = lib().pf_conv3_bf16_noalloc(_dev_ptr(x, torch.int16), cin, _dev_ptr(w, torch.float32),
+                                     0 if b is None else _dev_ptr(b, torch.float32),
+                                     1 if relu else 0, _dev_ptr(y, torch.int16), cout, n1, n2,
+                                     n3, int(stream))
+    if rc != 0:
+        raise PFError(rc, lib().pf_last_error(None).decode())
     return y
 
 

@@ -588,6 +588,10 @@ int autotune(pf_handle* h) {
 
 }  // namespace
 
+namespace pf {
+void set_thread_error(const std::string& msg) { g_create_err = msg; }
+}  // namespace pf
+
 extern "C" {
 
 int pf_abi_version(void) { return 1; }

@@ -186,4 +186,7 @@ hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, co
 // (one device-to-host copy per poll instead of one per instance)
 hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ninst,
                              DevCtl* out, hipStream_t s);
+// message returned by pf_last_error(NULL) on the calling thread (calls that
+// have no handle to hold it)
+void set_thread_error(const std::string& msg);
 }  // namespace pf

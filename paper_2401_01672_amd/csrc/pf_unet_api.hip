@@ -14,6 +14,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -447,6 +448,53 @@ int pfu_forward_into(pf_unet* n, const uint8_t* code, int n1, int n2, int n3, do
   return r;
 }
 
+// Allocation-free forward convolution.  The only scratch memory of the
+// forward convolution is the BF16 copy of the weights in the implicit-GEMM
+// layout [cout][kpad]; here it lives in a file-scope device array sized for
+// cin, cout <= 96 instead of a per-call allocation.  Host code never uses the
+// array's name as an address: the device address is looked up once per
+// device and kept.
+namespace {
+constexpr int kNoAllocMaxCin = 96;
+constexpr int kNoAllocMaxCout = 96;
+constexpr size_t kNoAllocWords = (size_t)kNoAllocMaxCout * ((27 * kNoAllocMaxCin + 31) & ~31);
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint16_t* g_scratch_dev[kNoAllocMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) uint16_t scratch[kNoAllocWords];
+
+namespace {
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+int noalloc_scratch(uint16_t** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    pf::set_thread_error(std::string("pf_conv3_bf16_noalloc: hipGetDevice: ") + hipGetErrorString(e));
+    return PF_EHIP;
+  }
+  if (dev < 0 || dev >= kNoAllocMaxDevices) {
+    pf::set_thread_error("pf_conv3_bf16_noalloc: device index out of range");
+    return PF_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      pf::set_thread_error(std::string("pf_conv3_bf16_noalloc: hipGetSymbolAddress: ") +
+                           hipGetErrorString(e));
+      return PF_EHIP;
+    }
+    g_scratch_dev[dev] = static_cast<uint16_t*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return PF_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int pf_unet_create(uint64_t seed, pf_unet** out) {
@@ -704,6 +752,52 @@ int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;
   (void)hipFree(wf);
   return rc;
+}
+
+int pf_conv3_bf16_noalloc(const uint16_t* x, int32_t cin, const float* w, const float* b,
+                          int32_t relu, uint16_t* y, int32_t cout, int32_t n1, int32_t n2,
+                          int32_t n3, uintptr_t stream) {
+  if (!x || !w || !y || n1 <= 0 || n2 <= 0 || n3 <= 0 || cin % 8 || cout % 16 || cin <= 0 ||
+      cout <= 0 || cout > 96 || cout / 16 == 5) {
+    pf::set_thread_error("pf_conv3_bf16_noalloc: invalid argument");
+    return PF_EINVAL;
+  }
+  if (cin > kNoAllocMaxCin || cout > kNoAllocMaxCout) {
+    pf::set_thread_error("pf_conv3_bf16_noalloc: cin " + std::to_string(cin) + ", cout " +
+                         std::to_string(cout) + " exceed the static weight scratch (cin <= " +
+                         std::to_string(kNoAllocMaxCin) + ", cout <= " +
+                         std::to_string(kNoAllocMaxCout) + ")");
+    return PF_EINVAL;
+  }
+  uint16_t* wf = nullptr;
+  int rc = noalloc_scratch(&wf);
+  if (rc) return rc;
+  const int kpad = round32(27 * cin);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = pfu::launch_weights(w, cout, cin, kpad, 0, wf, nullptr, s);
+  ConvArgs a;
+  a.in = x;
+  a.in_stride = cin;
+  a.in_off = 0;
+  a.cin = cin;
+  a.w = wf;
+  a.kpad = kpad;
+  a.bias = b;
+  a.out = y;
+  a.out_stride = cout;
+  a.out_off = 0;
+  a.cout = cout;
+  a.relu = relu ? 1 : 0;
+  a.n1 = n1;
+  a.n2 = n2;
+  a.n3 = n3;
+  a.variant = 1;
+  if (e == hipSuccess) e = pfu::launch_conv_fwd(a, s);
+  if (e != hipSuccess) {
+    pf::set_thread_error(std::string("pf_conv3_bf16_noalloc: launch: ") + hipGetErrorString(e));
+    return PF_EHIP;
+  }
+  return PF_OK;
 }
 
 int pf_conv3_bf16_backward(const uint16_t* x, int32_t cin, const float* w, const uint16_t* dy,
