@@ -94,6 +94,8 @@ def lib():
         L.or_integrate.restype = C.c_int
         L.or_diagnostics.argtypes = [C.POINTER(Params), dp, dp, dp, dp]
         L.or_diagnostics.restype = None
+        L.or_uwc_bottom_half.argtypes = [C.POINTER(Params), dp, dp, dp, dp]
+        L.or_uwc_bottom_half.restype = None
         for name in ("or_sigma",):
             getattr(L, name).argtypes = [C.c_double, C.c_double, C.c_double]
             getattr(L, name).restype = C.c_double
@@ -225,6 +227,18 @@ def diagnostics(P: Params, G, phi, T=None) -> Dict[str, float]:
                 enthalpy=float(out[3]),
                 ice_fraction=float(ice / pore) if pore else 0.0,
                 uwc=float(1.0 - ice / pore) if pore else 0.0)
+
+
+def uwc_bottom_half(P: Params, G, phi, T=None) -> Dict[str, float]:
+    """Sec. 3.3 eq. UWC-formula over the cells whose centre lies below half
+    the vessel height: water cells (G < 1/2), ice cells among them
+    (phi > 1/2) and UWC = 1 - ice / water."""
+    G = _G(G)
+    out = np.zeros(3)
+    phi_a = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+    T_a = None if T is None else np.ascontiguousarray(T, dtype=np.float64)
+    lib().or_uwc_bottom_half(C.byref(P), _dptr(G), _dptr(phi_a), _dptr(T_a), _dptr(out))
+    return dict(water_cells=int(out[0]), ice_cells=int(out[1]), uwc=float(out[2]))
 
 
 def sigma(w: float, e0: float, e1: float) -> float:

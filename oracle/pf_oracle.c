@@ -472,6 +472,33 @@ void or_diagnostics(const or_params* p, const double* G, const double* phi, cons
   out[3] = H * p->h * p->h * p->h;
 }
 
+/* Unfrozen water content of the bottom half of the vessel (Sec. 3.3, eq.
+ * UWC-formula): the water set (eq. water-occupied-subdomain, G < 1/2) and
+ * the ice set (eq. frozen-subdomain, phi > 1/2), both restricted to the
+ * cells whose centre lies strictly below half the vessel height,
+ * (i3 + 1/2) h < n3 h / 2.  Ice cells are counted among the water cells
+ * (cells with G >= 1/2 never evolve: their water indicator is 0).
+ * out = {water cells, ice cells, UWC = 1 - ice / water (0 if no water)}. */
+void or_uwc_bottom_half(const or_params* p, const double* G, const double* phi,
+                        const double* T, double out[3]) {
+  const int64_t plane = (int64_t)p->n1 * p->n2;
+  double water = 0, ice = 0;
+  for (int32_t i3 = 0; i3 < p->n3; ++i3) {
+    if (!(2.0 * i3 + 1.0 < (double)p->n3)) break;
+    for (int64_t j = 0; j < plane; ++j) {
+      const int64_t i = (int64_t)i3 * plane + j;
+      if (!(G[i] < 0.5)) continue;
+      double Tc = (p->model == OR_MODEL_AC) ? p->t_star - p->dT : T[i];
+      double ph = (p->model == OR_MODEL_TEMP) ? temp_phi(G[i], Tc, p) : phi[i];
+      water += 1.0;
+      if (ph > 0.5) ice += 1.0;
+    }
+  }
+  out[0] = water;
+  out[1] = ice;
+  out[2] = water > 0 ? 1.0 - ice / water : 0.0;
+}
+
 /* Threads the oracle's parallel loops use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
