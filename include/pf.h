@@ -179,14 +179,20 @@ const char* pf_last_error(const pf_handle* h);
  * on this handle; 0 restores the handle's own stream. */
 int pf_set_stream(pf_handle* h, uintptr_t stream);
 
+/* Stream arguments: a hipStream_t cast to uintptr_t on which the call's
+ * device work is issued; 0 = the handle's stream.  A caller stream waits for
+ * the work already issued on the handle's stream (the call synchronizes the
+ * handle's stream first). */
+
 /* Copy a state in: phi and theta point to n cells each in the handle's
  * precision, on the device (on_device = 1) or the host (0).  theta is
  * ignored for PF_MODEL_AC and phi for PF_MODEL_TEMP (may be NULL).
  * Synchronous with respect to the host. */
-int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device);
+int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device,
+                 uintptr_t stream);
 
 /* Copy the current state out (same layout rules as pf_set_state). */
-int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device);
+int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device, uintptr_t stream);
 
 /* Change the error tolerance of later runs (params.tol at creation;
  * <= 0: fixed steps). */
@@ -195,12 +201,13 @@ int pf_set_tolerance(pf_handle* h, double tol);
 /* Set the current time and the next proposed step. */
 int pf_set_time(pf_handle* h, double t, double dt);
 
-/* Right-hand side F(t, phi, theta) of the semi-discrete system: writes
- * dphi = d phi/dt and dtheta = d theta/dt.  All four are device pointers of n
- * cells in the handle's precision; unused fields of the model may be NULL.
- * Asynchronous on the handle's stream. */
+/* Right-hand side F(t, phi, theta) of the semi-discrete system (Sec. 2.5,
+ * the method of lines applied to eqs. heat-equation and Allen-Cahn-equation):
+ * writes dphi = d phi/dt and dtheta = d theta/dt.  All four are device
+ * pointers of n cells in the handle's precision; unused fields of the model
+ * may be NULL.  Asynchronous on `stream`. */
 int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dphi,
-           void* dtheta);
+           void* dtheta, uintptr_t stream);
 
 /* One Runge-Kutta-Merson attempt from (*t, current state) with proposed step
  * *dt; on return *t and *dt hold the new time and proposed step and the state
@@ -250,6 +257,13 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
 /* Diagnostics of the current state into stats (ice/pore counts, sum_phi,
  * enthalpy); the step counters and t are left as the last run set them. */
 int pf_diagnostics(pf_handle* h, pf_run_stats* stats);
+
+/* The same diagnostics over the planes i3_lo <= i3 < i3_hi only
+ * (0 <= i3_lo <= i3_hi <= n3, else PF_EINVAL).  With [0, n3/2) (integer
+ * division) these are the cells whose centres lie below half the vessel
+ * height, over which eq. UWC-formula (Sec. 3.3) takes the unfrozen water
+ * content: UWC = 1 - ice_count / pore_count.  Synchronous. */
+int pf_diagnostics_planes(pf_handle* h, int32_t i3_lo, int32_t i3_hi, pf_run_stats* stats);
 
 /* Step-loop options: steps_per_poll attempts are issued between host polls;
  * use_graph = 1 captures them once into a HIP graph and replays it. */
@@ -352,11 +366,14 @@ void pf_unet_destroy(pf_unet* net);
 const char* pf_unet_last_error(const pf_unet* net);
 int pf_unet_set_stream(pf_unet* net, uintptr_t stream);
 /* Forward (and data-gradient) convolution kernel of this network:
+ * 2: register-blocked where it applies (cout <= 32 on grids of at least
+ * 2^16 voxels), else as 1 -- each wavefront keeps the nine (dz, dy) weight
+ * fragments of a k-block in registers and reads every staged input row once
+ * for all the output rows and planes it feeds;
  * 1 (default): LDS-tiled -- a 16 x 4 x 4 block of output voxels per
  * workgroup with its input halo staged in LDS per chunk of input channels;
  * 0: direct -- every B fragment gathered from memory.  Same products; the
- * FP32 partial sums are taken in another order when cin spans several
- * channel chunks. */
+ * FP32 partial sums are taken in another order. */
 int pf_unet_set_conv_kernel(pf_unet* net, int32_t variant);
 int64_t pf_unet_num_params(void);
 
@@ -397,22 +414,31 @@ int pf_unet_time_layers(pf_unet* net, int32_t n1, int32_t n2, int32_t n3, int32_
  * convolutions} of convolution `layer`. */
 int pf_unet_layer_info(int32_t layer, int32_t* out);
 
+/* Warm-start modes. */
+#define PF_WARM_ALL 0     /* the prediction on every cell                       */
+#define PF_WARM_NUCLEUS 1 /* the prediction on the nucleus's water component     */
+#define PF_WARM_FLOOD 2   /* no network: phi = 1 on the nucleus's water component */
+
 /* Write the network's prediction for the handle's mask (PF_MODEL_AC or
  * PF_MODEL_COUPLED; dT > 0, log10_sigma_scale = log10 s) into the handle's
- * current phi (in its precision; theta, t and dt are not changed).  With
- * restrict_to_nucleus != 0 the current phi is read first as the nucleus: the
- * prediction is kept only on the water cells connected through water-water
- * faces to a water cell with phi > 1/2, and is 0 elsewhere (with no
- * phase-field flux through glass faces, a face-connected water component
+ * current phi (in its precision; theta, t and dt are not changed).
+ * PF_WARM_NUCLEUS (the warm start proper) reads the current phi first as the
+ * nucleus: the prediction is kept only on the water cells connected through
+ * water-water faces to a water cell with phi > 1/2, and is 0 elsewhere (with
+ * no phase-field flux through glass faces, a face-connected water component
  * without ice keeps phi = 0, since phi = 0 is a fixed point of the reaction
- * term of the phase-field equation, Sec. 2.2).  The handle's
- * n1, n2, n3 must satisfy the network's grid rule.  Synchronous. */
-int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale,
-                 int32_t restrict_to_nucleus);
+ * term of the phase-field equation, Sec. 2.2).  PF_WARM_FLOOD is the
+ * baseline without the network: phi = 1 on that component (the network
+ * object provides only its work buffers).  The handle's n1, n2, n3 must
+ * satisfy the network's grid rule.  Work is issued on `stream` (0: the
+ * handle's stream); synchronous. */
+int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale, int32_t mode,
+                 uintptr_t stream);
 
 /* Building blocks (each call allocates and frees its own scratch; device
  * pointers; BF16 tensors channels-last [n][c], FP32 weights [cout][27][cin],
- * taps as above).  y = act(conv3x3x3(x) + b) with act = ReLU if relu != 0;
+ * taps as above; the convolutions run on the LDS-tiled kernel).
+ * y = act(conv3x3x3(x) + b) with act = ReLU if relu != 0;
  * cin % 8 == 0, cout in {16, 32, 48, 64, 96}; b may be NULL.  Synchronous. */
 int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b, int32_t relu,
                   uint16_t* y, int32_t cout, int32_t n1, int32_t n2, int32_t n3,

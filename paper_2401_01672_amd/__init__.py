@@ -24,6 +24,7 @@ PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENONFINITE, PF_EDTMIN = -1, -2, -3, -4, -5
 MODELS = {"ac": 0, "coupled": 1, "temp": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 REACTIONS = {"sigma": 0, "gradp": 1}
+WARM_MODES = {"all": 0, "nucleus": 1, "flood": 2}
 STATUS_NAMES = {0: "ok", 1: "equilibrium", 2: "maxsteps", -1: "einval", -2: "enomem",
                 -3: "ehip", -4: "enonfinite", -5: "edtmin"}
 
@@ -70,15 +71,16 @@ SIGNATURES = [
     ("pf_destroy", None, [_H]),
     ("pf_last_error", C.c_char_p, [_H]),
     ("pf_set_stream", C.c_int, [_H, C.c_size_t]),
-    ("pf_set_state", C.c_int, [_H, _VP, _VP, C.c_int]),
-    ("pf_get_state", C.c_int, [_H, _VP, _VP, C.c_int]),
+    ("pf_set_state", C.c_int, [_H, _VP, _VP, C.c_int, C.c_size_t]),
+    ("pf_get_state", C.c_int, [_H, _VP, _VP, C.c_int, C.c_size_t]),
     ("pf_set_time", C.c_int, [_H, C.c_double, C.c_double]),
     ("pf_set_tolerance", C.c_int, [_H, C.c_double]),
-    ("pf_rhs", C.c_int, [_H, C.c_double, _VP, _VP, _VP, _VP]),
+    ("pf_rhs", C.c_int, [_H, C.c_double, _VP, _VP, _VP, _VP, C.c_size_t]),
     ("pf_rkm_step", C.c_int, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(PFStepInfo)]),
     ("pf_integrate", C.c_int, [_H, C.c_double, C.c_int64, C.c_double, C.POINTER(PFRunStats)]),
     ("pf_diagnostics", C.c_int, [_H, C.POINTER(PFRunStats)]),
+    ("pf_diagnostics_planes", C.c_int, [_H, C.c_int32, C.c_int32, C.POINTER(PFRunStats)]),
     ("pf_batch_integrate", C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_int64,
                                      C.c_double, C.POINTER(PFRunStats), C.c_size_t,
                                      C.c_void_p]),
@@ -110,7 +112,7 @@ SIGNATURES = [
     ("pf_unet_time_layers", C.c_int, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_double)]),
     ("pf_unet_layer_info", C.c_int, [C.c_int32, C.POINTER(C.c_int32)]),
-    ("pf_warmstart", C.c_int, [_H, _H, C.c_double, C.c_double, C.c_int32]),
+    ("pf_warmstart", C.c_int, [_H, _H, C.c_double, C.c_double, C.c_int32, C.c_size_t]),
     ("pf_conv3_bf16", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32,
                                 C.c_int32, C.c_int32, C.c_int32, C.c_size_t]),
     ("pf_conv3_bf16_noalloc", C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32,
@@ -237,20 +239,25 @@ class Solver:
         return torch.float64 if self.precision == "fp64" else torch.float32
 
     # -- state ----------------------------------------------------------------
-    def set_state(self, phi, theta=None):
+    def set_state(self, phi, theta=None, stream: int = 0):
         """phi, theta (= T - T*): torch tensors (cuda) or numpy arrays in the
         handle's precision, ncells elements each (Temp model: theta only,
-        phi may be None)."""
+        phi may be None).  stream: a hipStream_t as int (0: the handle's)."""
         if isinstance(phi, np.ndarray) or isinstance(theta, np.ndarray):
             if phi is not None:
                 phi = np.ascontiguousarray(phi, dtype=self.np_dtype)
             if theta is not None:
                 theta = np.ascontiguousarray(theta, dtype=self.np_dtype)
         pp, dev = _ptr(phi)
-        tp, _ = _ptr(theta)
-        self._check(lib().pf_set_state(self.h, pp, tp, dev))
+        tp, dev_t = _ptr(theta)
+        if phi is None:
+            dev = dev_t
+        if dev:  # device inputs written on torch's current stream
+            import torch
+            torch.cuda.current_stream().synchronize()
+        self._check(lib().pf_set_state(self.h, pp, tp, dev, int(stream)))
 
-    def get_state(self, device: bool = False):
+    def get_state(self, device: bool = False, stream: int = 0):
         """(phi, theta); theta is None for the micro-scale model, phi is None
         for the Temp model."""
         has_phi = self.model != "temp"
@@ -264,7 +271,8 @@ class Solver:
         else:
             phi = np.empty(self.shape, dtype=self.np_dtype) if has_phi else None
             th = np.empty(self.shape, dtype=self.np_dtype) if has_th else None
-        self._check(lib().pf_get_state(self.h, _ptr(phi)[0], _ptr(th)[0], 1 if device else 0))
+        self._check(lib().pf_get_state(self.h, _ptr(phi)[0], _ptr(th)[0], 1 if device else 0,
+                                       int(stream)))
         return phi, th
 
     def set_time(self, t: float, dt: float):
@@ -274,13 +282,20 @@ class Solver:
         self._check(lib().pf_set_tolerance(self.h, float(tol)))
 
     # -- computation -----------------------------------------------------------
-    def rhs(self, t: float, phi, theta, dphi, dtheta):
-        """F(t, phi, theta) into dphi, dtheta (device tensors)."""
+    def rhs(self, t: float, phi, theta, dphi, dtheta, stream: Optional[int] = None):
+        """F(t, phi, theta) into dphi, dtheta (device tensors).  By default on
+        the handle's stream, after torch's current stream has finished and
+        waited for before returning; with an explicit stream (a hipStream_t as
+        a nonzero int) the call is left running on that stream."""
         import torch
-        torch.cuda.current_stream().synchronize()
+        wait = stream is None
+        if wait:
+            torch.cuda.current_stream().synchronize()
+            stream = 0
         self._check(lib().pf_rhs(self.h, float(t), _ptr(phi)[0], _ptr(theta)[0],
-                                 _ptr(dphi)[0], _ptr(dtheta)[0]))
-        self._check(lib().pf_synchronize(self.h))
+                                 _ptr(dphi)[0], _ptr(dtheta)[0], int(stream)))
+        if wait:
+            self._check(lib().pf_synchronize(self.h))
 
     def rkm_step(self, t: float, dt: float):
         tt, dd = C.c_double(t), C.c_double(dt)
@@ -303,6 +318,18 @@ class Solver:
         st = PFRunStats()
         self._check(lib().pf_diagnostics(self.h, C.byref(st)))
         return self._stats(st, PF_OK)
+
+    def diagnostics_planes(self, i3_lo: int, i3_hi: int) -> Dict:
+        """Diagnostics over the planes i3_lo <= i3 < i3_hi."""
+        st = PFRunStats()
+        self._check(lib().pf_diagnostics_planes(self.h, int(i3_lo), int(i3_hi), C.byref(st)))
+        return self._stats(st, PF_OK)
+
+    def uwc_bottom_half(self) -> Dict:
+        """Unfrozen water content of the bottom half (the planes below n3/2),
+        reduced on the GPU."""
+        d = self.diagnostics_planes(0, self.shape[0] // 2)
+        return dict(water_cells=d["pore_count"], ice_cells=d["ice_count"], uwc=d["uwc"])
 
     @staticmethod
     def _stats(st: PFRunStats, rc: int) -> Dict:
@@ -426,8 +453,10 @@ class UNet:
             pass
 
     def set_conv_kernel(self, variant: str):
-        """'tiled' (default, LDS-staged input blocks) or 'direct'."""
-        self._check(lib().pf_unet_set_conv_kernel(self.h, {"direct": 0, "tiled": 1}[variant]))
+        """'tiled' (default, LDS-staged input blocks), 'reg' (register-blocked
+        where it applies) or 'direct'."""
+        self._check(lib().pf_unet_set_conv_kernel(
+            self.h, {"direct": 0, "tiled": 1, "reg": 2}[variant]))
 
     def get_params(self) -> np.ndarray:
         out = np.empty(unet_num_params(), np.float32)
@@ -480,12 +509,14 @@ class UNet:
         self._check(lib().pf_unet_time_layers(self.h, n1, n2, n3, int(reps), out))
         return list(out)
 
-    def warmstart(self, solver: "Solver", dT: float, log10_s: float,
-                  restrict_to_nucleus: bool = True):
-        """Write the prediction into the solver's current phi; by default only
-        on the water cells connected to the current nucleus (phi > 1/2)."""
+    def warmstart(self, solver: "Solver", dT: float, log10_s: float, mode: str = "nucleus",
+                  stream: int = 0):
+        """Write the prediction into the solver's current phi: 'nucleus'
+        (default) only on the water cells connected to the current nucleus
+        (phi > 1/2), 'all' everywhere, 'flood' the baseline without the
+        network (phi = 1 on the nucleus's component)."""
         solver._check(lib().pf_warmstart(solver.h, self.h, float(dT), float(log10_s),
-                                         1 if restrict_to_nucleus else 0))
+                                         WARM_MODES[mode], int(stream)))
 
 
 def conv3_bf16(x, w, b, relu: bool, cout: int):

@@ -85,6 +85,11 @@ int fail(pf_handle* h, int code, const std::string& msg) {
       return fail((h), PF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// The stream a call works on: the caller's (nonzero) or the handle's.  Work
+// already issued on the handle's stream is finished first, so a caller
+// stream never overtakes it.
+hipStream_t work_stream(pf_handle* h, uintptr_t stream);
+
 void fill_model_const(const pf_params& P, ModelConst& m) {
   memset(&m, 0, sizeof(m));
   m.n1 = P.n1;
@@ -592,23 +597,34 @@ namespace pf {
 void set_thread_error(const std::string& msg) { g_create_err = msg; }
 }  // namespace pf
 
+namespace {
+hipStream_t work_stream(pf_handle* h, uintptr_t stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!stream || s == h->stream) return h->stream;
+  (void)hipStreamSynchronize(h->stream);
+  return s;
+}
+}  // namespace
+
 extern "C" {
 
-int pf_abi_version(void) { return 1; }
+int pf_abi_version(void) { return 2; }
 
-int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale,
-                 int32_t restrict_to_nucleus) {
+int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale, int32_t mode,
+                 uintptr_t stream) {
   if (!h) return PF_EINVAL;
   if (!net) return fail(h, PF_EINVAL, "network must be non-NULL");
+  if (mode < PF_WARM_ALL || mode > PF_WARM_FLOOD)
+    return fail(h, PF_EINVAL, "mode must be PF_WARM_ALL, PF_WARM_NUCLEUS or PF_WARM_FLOOD");
   if (h->P.model != PF_MODEL_AC && h->P.model != PF_MODEL_COUPLED)
     return fail(h, PF_EINVAL, "warm start needs a phase-field model (PF_MODEL_AC or PF_MODEL_COUPLED)");
   if (!(dT > 0.0)) return fail(h, PF_EINVAL, "dT must be positive");
+  hipStream_t s = work_stream(h, stream);
   std::string e;
   const int r = pfu_forward_into(net, h->code, h->P.n1, h->P.n2, h->P.n3, dT, log10_sigma_scale,
-                                 h->y[h->cur][0], h->P.precision == PF_FP64 ? 1 : 0,
-                                 restrict_to_nucleus ? 1 : 0, h->stream, &e);
+                                 h->y[h->cur][0], h->P.precision == PF_FP64 ? 1 : 0, mode, s, &e);
   if (r != PF_OK) return fail(h, r, "warm start: " + e);
-  PF_HIP(h, hipStreamSynchronize(h->stream));
+  PF_HIP(h, hipStreamSynchronize(s));
   return PF_OK;
 }
 
@@ -782,7 +798,8 @@ int pf_set_time(pf_handle* h, double t, double dt) {
   return PF_OK;
 }
 
-int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device) {
+int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device,
+                 uintptr_t stream) {
   if (!h) return PF_EINVAL;
   if (h->P.model == PF_MODEL_TEMP) {  // the single unknown theta lives in slot 0
     if (!theta) return fail(h, PF_EINVAL, "theta must be non-NULL for the Temp model");
@@ -792,14 +809,15 @@ int pf_set_state(pf_handle* h, const void* phi, const void* theta, int on_device
   if (h->nvar == 2 && !theta) return fail(h, PF_EINVAL, "theta must be non-NULL for the coupled model");
   const size_t bytes = (size_t)h->ncell * h->esize;
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipStream_t s = work_stream(h, stream);
   h->cur = 0;
-  PF_HIP(h, hipMemcpyAsync(h->y[0][0], phi, bytes, k, h->stream));
-  if (h->nvar == 2) PF_HIP(h, hipMemcpyAsync(h->y[0][1], theta, bytes, k, h->stream));
-  PF_HIP(h, hipStreamSynchronize(h->stream));
+  PF_HIP(h, hipMemcpyAsync(h->y[0][0], phi, bytes, k, s));
+  if (h->nvar == 2) PF_HIP(h, hipMemcpyAsync(h->y[0][1], theta, bytes, k, s));
+  PF_HIP(h, hipStreamSynchronize(s));
   return PF_OK;
 }
 
-int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device) {
+int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device, uintptr_t stream) {
   if (!h) return PF_EINVAL;
   const size_t bytes = (size_t)h->ncell * h->esize;
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -807,15 +825,17 @@ int pf_get_state(pf_handle* h, void* phi, void* theta, int on_device) {
     phi = theta;
     theta = nullptr;
   }
-  if (phi) PF_HIP(h, hipMemcpyAsync(phi, h->y[h->cur][0], bytes, k, h->stream));
-  if (theta && h->nvar == 2) PF_HIP(h, hipMemcpyAsync(theta, h->y[h->cur][1], bytes, k, h->stream));
-  PF_HIP(h, hipStreamSynchronize(h->stream));
+  hipStream_t s = work_stream(h, stream);
+  if (phi) PF_HIP(h, hipMemcpyAsync(phi, h->y[h->cur][0], bytes, k, s));
+  if (theta && h->nvar == 2) PF_HIP(h, hipMemcpyAsync(theta, h->y[h->cur][1], bytes, k, s));
+  PF_HIP(h, hipStreamSynchronize(s));
   return PF_OK;
 }
 
 int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dphi,
-           void* dtheta) {
+           void* dtheta, uintptr_t stream) {
   if (!h) return PF_EINVAL;
+  hipStream_t s = work_stream(h, stream);
   if (h->P.model == PF_MODEL_TEMP) {
     // unknown theta in slot 0; the optional second output is d phi/dt
     if (!theta || !dtheta)
@@ -829,7 +849,7 @@ int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dph
     a.in[1] = nullptr;
     a.out[0] = dtheta;
     a.out[1] = dphi;
-    PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, h->stream));
+    PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, s));
     return PF_OK;
   }
   if (!phi || !dphi) return fail(h, PF_EINVAL, "phi and dphi must be non-NULL");
@@ -849,7 +869,7 @@ int pf_rhs(pf_handle* h, double t, const void* phi, const void* theta, void* dph
     a.vec = 0;
     pf::grid_blocks(h->mc, h->z_chunk, 1, &a.tiles_p, &a.tiles_z);
   }
-  PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, h->stream));
+  PF_HIP(h, pf::launch_stage(h->P.precision, h->P.model, 0, a, s));
   return PF_OK;
 }
 
@@ -896,10 +916,25 @@ int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info) {
 }
 
 int pf_diagnostics(pf_handle* h, pf_run_stats* st) {
+  if (!h) return PF_EINVAL;
+  return pf_diagnostics_planes(h, 0, h->P.n3, st);
+}
+
+int pf_diagnostics_planes(pf_handle* h, int32_t i3_lo, int32_t i3_hi, pf_run_stats* st) {
   if (!h || !st) return PF_EINVAL;
-  PF_HIP(h, pf::launch_diag(h->P.precision, h->P.model, h->code, h->G, h->y[h->cur][0],
-                            h->y[h->cur][1], h->mc, h->ncell, h->part1, h->max_parts > 1024 ? 1024 : h->max_parts,
-                            h->diag_out, h->stream));
+  if (i3_lo < 0 || i3_hi > h->P.n3 || i3_lo > i3_hi)
+    return fail(h, PF_EINVAL, "planes must satisfy 0 <= i3_lo <= i3_hi <= n3");
+  // the planes [i3_lo, i3_hi) are one contiguous run of cells
+  const long long plane = (long long)h->P.n1 * h->P.n2;
+  const long long off = plane * i3_lo, n = plane * (i3_hi - i3_lo);
+  const size_t eb = (size_t)h->esize;
+  auto at = [&](const void* q) -> const void* {
+    return q ? static_cast<const char*>(q) + (size_t)off * eb : nullptr;
+  };
+  const void* G = h->G ? static_cast<const char*>(h->G) + (size_t)off * eb : nullptr;
+  PF_HIP(h, pf::launch_diag(h->P.precision, h->P.model, h->code + off, G, at(h->y[h->cur][0]),
+                            at(h->y[h->cur][1]), h->mc, n, h->part1,
+                            h->max_parts > 1024 ? 1024 : h->max_parts, h->diag_out, h->stream));
   double out[4];
   PF_HIP(h, hipMemcpyAsync(out, h->diag_out, sizeof(out), hipMemcpyDeviceToHost, h->stream));
   PF_HIP(h, hipStreamSynchronize(h->stream));

@@ -266,6 +266,130 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
 }
 
 // ---------------------------------------------------------------------------
+// Register-blocked form (16 and 32 output channels on large grids).  A
+// wavefront owns TY x TZ rows of 16 output voxels along x (lane r: x0 + r),
+// all cout; the four wavefronts of a workgroup sit 2 x 2 in (y, z), so a
+// workgroup owns 16 x 2TY x 2TZ voxels.  A k-block of 32 is one group of 8
+// input channels at the three x-shifts: lane group g < 3 takes dx = g - 1,
+// group 3 is zero.  For each channel group the input block with its halo is
+// staged in LDS (16 bytes per voxel), the nine weight fragments (dz, dy) of
+// the k-block stay in registers, and every input fragment -- one halo row y_in
+// of one halo plane z_in -- is read from LDS once and feeds the MFMAs of every
+// output row t = y_in - dy and plane w = z_in - dz it reaches (up to nine),
+// instead of one.  Same products as conv3_tile_kernel; the FP32 sums are
+// taken in another order.
+
+template <int MT, int TY, int TZ>
+__global__ __launch_bounds__(256) void conv3_reg_kernel(ConvArgs a, int tiles_x, int tiles_y,
+                                                         int tiles_z) {
+  constexpr int BY = 2 * TY, BZ = 2 * TZ;
+  constexpr int HX = 18, HY = BY + 2, HZ = BZ + 2, HV = HX * HY * HZ;
+  __shared__ __align__(16) uint4 sx[HV];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, g = lane >> 4, r = lane & 15, w = tid >> 6;
+  const int wy = w & 1, wz = w >> 1;
+  // XCD-aware order: consecutive tiles of a row stay on one XCD
+  const int nblk = gridDim.x;
+  const int b = blockIdx.x;
+  const int q = nblk >> 3, rem = nblk & 7, xcd = b & 7, kk = b >> 3;
+  const int tile = (xcd < rem) ? xcd * (q + 1) + kk : rem * (q + 1) + (xcd - rem) * q + kk;
+  const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
+  const int x0 = tx * 16, y0 = ty * BY, z0 = tz * BZ;
+  (void)tiles_z;
+
+  f32x4 acc[MT][TZ][TY];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int i = 0; i < TZ; ++i)
+#pragma unroll
+      for (int t = 0; t < TY; ++t) acc[m][i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bool gact = g < 3;  // lane group 3 carries the zero quarter of each k-block
+  const int ngroups = a.cin / 8;
+  for (int c8 = 0; c8 < ngroups; ++c8) {
+    __syncthreads();
+    // stage the halo block of channels 8 c8 .. 8 c8 + 7 (zeros outside the grid)
+    for (int i = tid; i < HV; i += 256) {
+      const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+      const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3) {
+        const long long src = ((long long)z * a.n2 + y) * a.n1 + x;
+        val = *reinterpret_cast<const uint4*>(a.in + src * a.in_stride + a.in_off + 8 * c8);
+      }
+      sx[i] = val;
+    }
+    // the nine weight fragments of this k-block: W[co][tap(dz, dy, dx = g - 1)][8 c8 ..]
+    bf16x8 afr[MT][3][3];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int tap = dz * 9 + dy * 3 + (gact ? g : 0);
+          afr[m][dz][dy] = gact ? ld8(a.w + (long long)(m * 16 + r) * a.kpad + tap * a.cin + 8 * c8)
+                                : zero8();
+        }
+    __syncthreads();
+    const int hbase = (wz * TZ * HY + wy * TY) * HX + r + (gact ? g : 0);
+#pragma unroll
+    for (int zi = 0; zi < TZ + 2; ++zi) {
+#pragma unroll
+      for (int yi = 0; yi < TY + 2; ++yi) {
+        bf16x8 f = zero8();
+        if (gact) {
+          const uint4 u = sx[hbase + (zi * HY + yi) * HX];
+          f = *reinterpret_cast<const bf16x8*>(&u);
+        }
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+          const int wv = zi - dz;
+          if (wv < 0 || wv >= TZ) continue;
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            const int tv = yi - dy;
+            if (tv < 0 || tv >= TY) continue;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m][wv][tv] = mfma16(afr[m][dz][dy], f, acc[m][wv][tv]);
+          }
+        }
+      }
+    }
+  }
+  // epilogue: lane holds channels m*16 + 4g .. +3 of voxel (x0 + r, y, z)
+  const int x = x0 + r;
+  if (x >= a.n1) return;
+#pragma unroll
+  for (int i = 0; i < TZ; ++i) {
+    const int z = z0 + wz * TZ + i;
+    if (z >= a.n3) continue;
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+      const int y = y0 + wy * TY + t;
+      if (y >= a.n2) continue;
+      const long long v = ((long long)z * a.n2 + y) * a.n1 + x;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int co = m * 16 + 4 * g;
+        uint16_t o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float yv = acc[m][i][t][j] + (a.bias ? a.bias[co + j] : 0.0f);
+          if (a.relu) yv = yv > 0.0f ? yv : 0.0f;
+          o[j] = f2bf(yv);
+        }
+        uint2 pk;
+        pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+        pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+        *reinterpret_cast<uint2*>(a.out + v * a.out_stride + a.out_off + co) = pk;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient as an implicit GEMM over voxels:
 //   dW[co][tap][ci] = sum_v dY[v][co] X[v + offset(tap)][ci],  db[co] = sum_v dY[v][co].
 // Grid (voxel ranges) x (27 taps).  A workgroup walks its voxel range in
@@ -616,6 +740,17 @@ __global__ void reach_seed_kernel(const uint8_t* code, const void* phi, int fp64
   reach[v] = (!(code[v] & 0x40u) && p > 0.5) ? 1 : 0;
 }
 
+// No-network baseline of the warm start: phi = 1 on the reached cells (the
+// nucleus's water component), 0 elsewhere.
+__global__ void flood_kernel(const uint8_t* reach, void* out, int fp64, long long n) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (fp64)
+    static_cast<double*>(out)[v] = reach[v] ? 1.0 : 0.0;
+  else
+    static_cast<float*>(out)[v] = reach[v] ? 1.0f : 0.0f;
+}
+
 // Sweep: a water cell joins when a face neighbour across a water-water face
 // has joined.  A workgroup loads a 16^3 block of reach flags with a one-cell
 // halo (and the block's cell codes) into LDS and closes the block: rounds of
@@ -746,13 +881,32 @@ static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int TY, int TZ>
+static hipError_t launch_reg(const ConvArgs& a, hipStream_t s) {
+  const int tx = (a.n1 + 15) / 16, ty = (a.n2 + 2 * TY - 1) / (2 * TY),
+            tz = (a.n3 + 2 * TZ - 1) / (2 * TZ);
+  const dim3 grid((unsigned)(tx * ty * tz)), block(256);
+  switch (a.cout / 16) {
+    case 1: hipLaunchKernelGGL((conv3_reg_kernel<1, TY, TZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 2: hipLaunchKernelGGL((conv3_reg_kernel<2, TY, TZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
   if (a.cin % 8 || a.cout % 16 || a.in_stride % 8 || a.in_off % 8 || a.out_stride % 4 ||
       a.out_off % 4 || a.kpad % 32 || a.kpad < 27 * a.cin)
     return hipErrorInvalidValue;
   const long long nvox = (long long)a.n1 * a.n2 * a.n3;
   if (nvox == 0) return hipSuccess;
-  if (a.variant == 1) {
+  if (a.variant == 2) {
+    // register-blocked on grids with enough 16 x 8 x 8 blocks to fill the
+    // chip; the LDS-tiled form elsewhere
+    if (a.cout <= 32 && nvox >= (1LL << 19)) return launch_reg<4, 4>(a, s);
+    if (a.cout <= 32 && nvox >= (1LL << 16)) return launch_reg<2, 2>(a, s);
+  }
+  if (a.variant >= 1) {
     if (a.cin % 32 == 0) return launch_tile_cc<32>(a, s);
     if (a.cin % 16 == 0) return launch_tile_cc<16>(a, s);
     return launch_tile_cc<8>(a, s);
@@ -911,6 +1065,12 @@ hipError_t launch_reach_seed(const uint8_t* code, const void* phi, int fp64, uin
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(reach_seed_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, code, phi, fp64,
                      reach, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_flood(const uint8_t* reach, void* out, int fp64, long long n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(flood_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, reach, out, fp64, n);
   return hipGetLastError();
 }
 

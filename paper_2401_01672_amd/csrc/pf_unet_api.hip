@@ -96,7 +96,7 @@ struct pf_unet {
   uint16_t* wslab = nullptr;
   long long adam_step = 0;
   int weights_dirty = 1;
-  int conv_variant = 1;  // forward-convolution kernel (1 LDS-tiled, 0 direct)
+  int conv_variant = 1;  // forward-convolution kernel (2 register-blocked, 1 LDS-tiled, 0 direct)
   // grid-dependent buffers
   int n1 = 0, n2 = 0, n3 = 0, train = 0;
   void* slab = nullptr;
@@ -433,16 +433,21 @@ int nucleus_reach(pf_unet* n, const uint8_t* code, const void* phi, int fp64) {
 
 // internal entry used by pf_warmstart: forward pass into a solver state
 int pfu_forward_into(pf_unet* n, const uint8_t* code, int n1, int n2, int n3, double dT,
-                     double log10_s, void* out, int out_fp64, int keep_from_phi,
-                     hipStream_t s, std::string* err) {
+                     double log10_s, void* out, int out_fp64, int mode, hipStream_t s,
+                     std::string* err) {
   hipStream_t saved = n->stream;
   n->stream = s;
+  const bool reach = mode == PF_WARM_NUCLEUS || mode == PF_WARM_FLOOD;
   int r = check_dims(n, n1, n2, n3);
   if (r == PF_OK) r = ensure_grid(n, n1, n2, n3, n->train);
-  if (r == PF_OK && keep_from_phi) r = nucleus_reach(n, code, out, out_fp64);
-  if (r == PF_OK)
-    r = run_net(n, code, 1, dT, log10_s, out, out_fp64, nullptr,
-                keep_from_phi ? n->reach : nullptr);
+  if (r == PF_OK && reach) r = nucleus_reach(n, code, out, out_fp64);
+  if (r == PF_OK && mode == PF_WARM_FLOOD) {
+    const hipError_t e =
+        pfu::launch_flood(n->reach, out, out_fp64, (long long)n1 * n2 * n3, n->stream);
+    if (e != hipSuccess) r = ufail(n, PF_EHIP, std::string("flood: ") + hipGetErrorString(e));
+  } else if (r == PF_OK) {
+    r = run_net(n, code, 1, dT, log10_s, out, out_fp64, nullptr, reach ? n->reach : nullptr);
+  }
   n->stream = saved;
   if (r != PF_OK && err) *err = n->err;
   return r;
@@ -561,7 +566,7 @@ const char* pf_unet_last_error(const pf_unet* n) { return n ? n->err.c_str() : "
 
 int pf_unet_set_conv_kernel(pf_unet* n, int32_t variant) {
   if (!n) return PF_EINVAL;
-  if (variant != 0 && variant != 1) return ufail(n, PF_EINVAL, "variant must be 0 or 1");
+  if (variant < 0 || variant > 2) return ufail(n, PF_EINVAL, "variant must be 0, 1 or 2");
   n->conv_variant = variant;
   return PF_OK;
 }

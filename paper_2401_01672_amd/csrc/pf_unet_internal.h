@@ -22,8 +22,9 @@ struct ConvArgs {
   int out_stride, out_off, cout;
   int relu;
   int n1, n2, n3;
-  int variant;         // 1: LDS-tiled kernel, 0: direct kernel (same products,
-                       // FP32 sums in another order when cin spans several chunks)
+  int variant;         // 2: register-blocked kernel on large grids with cout <= 32,
+                       // else as 1; 1: LDS-tiled kernel; 0: direct kernel (same
+                       // products, FP32 sums in another order)
 };
 
 struct WgradArgs {
@@ -85,6 +86,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n
 hipError_t launch_f32_to_bf16(const float* in, uint16_t* out, long long n, hipStream_t s);
 hipError_t launch_bf16_to_f32(const uint16_t* in, float* out, long long n, hipStream_t s);
 hipError_t launch_mfma_probe(const float* A, const float* B, float* C, hipStream_t s);
+// out = 1 on the reached cells, 0 elsewhere (FP64 if fp64, else FP32)
+hipError_t launch_flood(const uint8_t* reach, void* out, int fp64, long long n, hipStream_t s);
 hipError_t launch_reach_seed(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
                              long long n, hipStream_t s);
 hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
@@ -98,9 +101,11 @@ hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int 
 
 // forward pass of the network on a solver's cell codes (glass = bit 6),
 // writing phi0 (FP32 or FP64) into out on stream s; used by pf_warmstart
-// If keep_from_phi: before out is written, the water cells connected through
-// water-water faces to a cell with out > 1/2 (the current nucleus) are found,
-// and the prediction is zero on every other cell.
+// mode (PF_WARM_*): ALL writes the prediction on every cell; NUCLEUS first
+// finds the water cells connected through water-water faces to a cell with
+// out > 1/2 (the current nucleus) and writes the prediction there, zero on
+// every other cell; FLOOD writes 1 on those cells and 0 elsewhere without
+// running the network.
 int pfu_forward_into(pf_unet* n, const uint8_t* code, int n1, int n2, int n3, double dT,
-                     double log10_s, void* out, int out_fp64, int keep_from_phi,
-                     hipStream_t s, std::string* err);
+                     double log10_s, void* out, int out_fp64, int mode, hipStream_t s,
+                     std::string* err);

@@ -171,9 +171,75 @@ def kernel_stats(title: str, trace_dir: str, command: str, out: str):
     print(out)
 
 
+def conv(edge: int, reps: int, variant: str):
+    """The trained warm-start network's ten forward convolutions on an
+    edge^3 grid (pf_unet_time_layers: reps launches of each, back to back)."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import torch
+
+    import paper_2401_01672_amd as pf
+    torch.cuda.set_device(0)
+    net = pf.UNet(seed=0)
+    net.set_params(np.load(os.path.join(ROOT, "paper_2401_01672_amd", "data",
+                                        "unet_warmstart_96.npz"))["params"])
+    net.set_conv_kernel(variant)
+    ms = net.time_layers((edge, edge, edge), reps=reps)
+    out = []
+    for i, t in enumerate(ms):
+        info = pf.unet_layer_info(i)
+        nv = edge ** 3 // (8 ** info["level"])
+        fl = 2 * 27 * info["cin"] * info["cout"] * nv
+        out.append(dict(layer=i, cin=info["cin"], cout=info["cout"], voxels=nv,
+                        us=round(t * 1e3, 2), tflops=round(fl / (t * 1e-3) / 1e12, 1)))
+    print(json.dumps(dict(edge=edge, variant=variant, layers=out)), flush=True)
+    net.close()
+
+
+def pmc_summary(title: str, dirs, commands, out: str, match: str = ""):
+    """Markdown table of per-dispatch counter means per kernel, from one or
+    more rocprofv3 --pmc runs (one counter set per run)."""
+    vals = {}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise FileNotFoundError(f"no counter_collection.csv under {d}")
+        for f in files:
+            for row in csv.DictReader(open(f)):
+                k = row.get("Kernel_Name", "")
+                if match and match not in k:
+                    continue
+                key = (k, row.get("Dispatch_Id", ""))
+                vals.setdefault(k, {}).setdefault(row["Counter_Name"], {}).setdefault(
+                    key, 0.0)
+                vals[k][row["Counter_Name"]][key] += float(row["Counter_Value"])
+    lines = [f"# rocprofv3 counters: {title}", "", "Commands (repo root):", "", "```",
+             *commands, "```", "", f"Kernel sources: `{source_hash()}`", "",
+             "Per-dispatch means (counters summed over the GPU's instances).", ""]
+    for k in sorted(vals):
+        lines += [f"## `{k[:100]}`", "", "| counter | dispatches | mean per dispatch |",
+                  "|---|---|---|"]
+        for cname in sorted(vals[k]):
+            v = list(vals[k][cname].values())
+            lines.append(f"| {cname} | {len(v)} | {sum(v) / len(v):.6g} |")
+        lines.append("")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    pm = sub.add_parser("pmcsum")
+    pm.add_argument("--title", required=True)
+    pm.add_argument("--dirs", nargs="+", required=True)
+    pm.add_argument("--commands", nargs="+", required=True)
+    pm.add_argument("--match", default="")
+    pm.add_argument("--out", required=True)
+    cv = sub.add_parser("conv")
+    cv.add_argument("--edge", type=int, default=96)
+    cv.add_argument("--reps", type=int, default=5)
+    cv.add_argument("--variant", default="tiled", choices=["tiled", "direct", "reg"])
     k = sub.add_parser("stats")
     k.add_argument("--title", required=True)
     k.add_argument("--trace", required=True)
@@ -190,7 +256,11 @@ def main():
     s.add_argument("--write", required=True)
     s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
-    if a.cmd == "stats":
+    if a.cmd == "pmcsum":
+        pmc_summary(a.title, a.dirs, a.commands, a.out, a.match)
+    elif a.cmd == "conv":
+        conv(a.edge, a.reps, a.variant)
+    elif a.cmd == "stats":
         kernel_stats(a.title, a.trace, a.command, a.out)
     elif a.cmd == "run":
         run(a.workload, a.schedule, a.steps)

@@ -7,7 +7,7 @@ micro-scale model of Sec. 2.4 (Allen-Cahn at constant supercooling dT) with
 the realistic attachment coefficient of Tab. 1, ice growing from the
 nucleation disk anchored in the glass cap until the state is stationary, and
 the unfrozen water content of eq. UWC-formula evaluated over the bottom half
-of the vessel.  The geometry is the paper-mode vessel of
+of the vessel (reduced on the GPU, pf_diagnostics_planes).  The geometry is the paper-mode vessel of
 ``pf_inputs.case_paper`` (smooth glass field, no phase-field face rule) on a
 synthetic bead bed.
 
@@ -26,7 +26,6 @@ import sys
 import time
 from typing import Dict, List
 
-import numpy as np
 
 _ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if _ROOT not in sys.path:
@@ -52,17 +51,6 @@ def problem(r_m: float, dT: float, n3: int = 100, seed: int = 5):
     return c
 
 
-def bottom_half_uwc(G: np.ndarray, phi: np.ndarray) -> Dict[str, float]:
-    """eq. UWC-formula over the bottom half x3 < L3/2: water cells G < 1/2,
-    ice cells among them phi > 1/2."""
-    n3 = G.shape[0]
-    Gb, pb = G[: n3 // 2], phi[: n3 // 2]
-    water = Gb < 0.5
-    nw = int(water.sum())
-    ni = int((water & (pb > 0.5)).sum())
-    return dict(water_cells=nw, ice_cells=ni, uwc=1.0 - ni / nw if nw else float("nan"))
-
-
 def run_one(c, budget: int) -> Dict:
     """Phase 1 at tol = 1e-6 until max water |d phi/dt| falls below the level
     that tolerance can resolve (4 lam_max tol); phase 2 at tol_eq down to the
@@ -80,12 +68,12 @@ def run_one(c, budget: int) -> Dict:
         s.set_tolerance(c.run["tol_eq"])
         st = s.integrate(max_steps=budget - n1, eq_tol=EQ_TOL, raise_on_error=False)
     wall = time.perf_counter() - t0
-    phi, _ = s.get_state()
+    uwc = s.uwc_bottom_half()  # eq. UWC-formula, reduced on the GPU
     s.close()
     n2 = st["steps_accepted"] + st["steps_rejected"] if st is not st1 else 0
     out = dict(status=st["status"], attempts=n1 + n2, attempts_phase1=n1,
                t=st["t"], wall_s=wall, cells=c.ncells)
-    out.update(bottom_half_uwc(c.G, phi))
+    out.update(uwc)
     return out
 
 

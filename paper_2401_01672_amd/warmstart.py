@@ -130,8 +130,15 @@ def train(net, data: List[Dict], epochs: int, lr0: float = 2e-4, lr1: float = 2e
     return hist
 
 
-def evaluate(net, probs: List[Dict], budget: int, log=print) -> List[Dict]:
-    """Wall time to equilibrium, cold and warm, one problem at a time."""
+def _relerr(u, ref):
+    return abs(u - ref) / ref if ref > 0 else (0.0 if u == ref else float("inf"))
+
+
+def evaluate(net, probs: List[Dict], budget: int, log=print, flood: bool = True) -> List[Dict]:
+    """Wall time to equilibrium, one problem at a time: cold (the sharp
+    nucleus), warm (the network's prediction on the nucleus's water
+    component) and, with flood, the baseline without the network (phi = 1 on
+    that component)."""
     import torch
     res = []
     for p in probs:
@@ -154,7 +161,24 @@ def evaluate(net, probs: List[Dict], budget: int, log=print) -> List[Dict]:
         ww = time.perf_counter() - t0
         warm.close()
         uc, uw = sc["uwc"], sw["uwc"]
-        relerr = abs(uw - uc) / uc if uc > 0 else (0.0 if uw == uc else float("inf"))
+        relerr = _relerr(uw, uc)
+        fl = {}
+        if flood:
+            fs = _solver(p)
+            fs.set_state(p["phi0"].astype(np.float32))
+            fs.set_time(0.0, p["run"]["dt0"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            net.warmstart(fs, p["meta"]["dT"], log10_scale(p), mode="flood")
+            sf = fs.integrate(max_steps=budget, eq_tol=EQ_TOL, raise_on_error=False)
+            wf = time.perf_counter() - t0
+            fs.close()
+            fl = dict(flood_status=sf["status"],
+                      flood_attempts=sf["steps_accepted"] + sf["steps_rejected"],
+                      flood_s=wf, uwc_flood=sf["uwc"], uwc_flood_relerr=_relerr(sf["uwc"], uc),
+                      flood_speedup=wc / wf if wf > 0 else float("nan"))
+            fl["flood_pass"] = bool(sc["status"] == 1 and sf["status"] == 1 and
+                                    fl["uwc_flood_relerr"] <= 1e-3)
         r = dict(seed=p["seed"], edge=int(p["params"]["n1"]), dT=p["meta"]["dT"],
                  sigma_scale=p["meta"]["sigma_scale"],
                  cold_status=sc["status"], warm_status=sw["status"],
@@ -166,6 +190,7 @@ def evaluate(net, probs: List[Dict], budget: int, log=print) -> List[Dict]:
                  speedup=wc / ww if ww > 0 else float("nan"))
         r["pass"] = bool(sc["status"] == 1 and sw["status"] == 1 and relerr <= 1e-3)
         r["pass_abs"] = bool(sc["status"] == 1 and sw["status"] == 1 and abs(uw - uc) <= 1e-3)
+        r.update(fl)
         res.append(r)
         log(json.dumps({k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}))
     return res
@@ -189,7 +214,24 @@ def summarize(res: List[Dict]) -> Dict:
                 median_effective_speedup=float(np.median(eff)),
                 median_cold_s=float(np.median([r["cold_s"] for r in ok])),
                 median_warm_s=float(np.median([r["warm_s"] for r in ok])),
-                median_uwc_relerr=float(np.median([r["uwc_relerr"] for r in ok])))
+                median_uwc_relerr=float(np.median([r["uwc_relerr"] for r in ok])),
+                **_flood_summary(ok))
+
+
+def _flood_summary(ok: List[Dict]) -> Dict:
+    """The no-network baseline beside the network, over the problems whose
+    cold run reached equilibrium."""
+    if not ok or "flood_pass" not in ok[0]:
+        return {}
+    fp = [r for r in ok if r["flood_pass"]]
+    both = [r for r in ok if r["flood_pass"] and r["pass"]]
+    return dict(flood_pass_rate=len(fp) / len(ok),
+                flood_median_speedup_passing=float(np.median([r["flood_speedup"] for r in fp]))
+                if fp else None,
+                network_only_passes=sum(r["pass"] and not r["flood_pass"] for r in ok),
+                flood_only_passes=sum(r["flood_pass"] and not r["pass"] for r in ok),
+                median_warm_over_flood_s=float(np.median([r["warm_s"] / r["flood_s"]
+                                                          for r in both])) if both else None)
 
 
 def main():

@@ -33,7 +33,33 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(L, name), f"{name} declared in pf.h but not exported"
         assert name in bound, f"{name} has no ctypes signature in the binding"
-    assert L.pf_abi_version() == 1
+    assert L.pf_abi_version() == 2
+
+
+def declared_parameters():
+    """{function: [parameter declarations]} from include/pf.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(pf_\w+)\s*\(([^;{]*?)\)\s*;", text, flags=re.S):
+        args = " ".join(m.group(2).split())
+        out[m.group(1)] = [] if args in ("", "void") else [a.strip() for a in args.split(",")]
+    return out
+
+
+def test_binding_arity_matches_header():
+    decl = declared_parameters()
+    for name, _, args in pf.SIGNATURES:
+        assert name in decl, name
+        assert len(args) == len(decl[name]), (name, len(args), decl[name])
+
+
+def test_stream_arguments_of_the_boundary():
+    """The state copies, the right-hand side, the batch and the warm start
+    take the stream to work on as their last argument."""
+    decl = declared_parameters()
+    for name in ("pf_set_state", "pf_get_state", "pf_rhs", "pf_warmstart"):
+        assert decl[name][-1] == "uintptr_t stream", (name, decl[name])
+    assert "uintptr_t stream" in decl["pf_batch_integrate"]
 
 
 def test_error_paths_without_gpu():

@@ -55,7 +55,7 @@ CONV_CASES = [(8, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (96, 32
 
 
 @pytest.mark.parametrize("cin,cout", CONV_CASES)
-@pytest.mark.parametrize("shape", [(7, 10, 13), (4, 4, 4), (16, 8, 24)])
+@pytest.mark.parametrize("shape", [(7, 10, 13), (4, 4, 4), (16, 8, 24), (32, 48, 48), (33, 41, 50)])
 def test_conv_forward(cin, cout, shape):
     rng = np.random.default_rng(cin * 1000 + cout + shape[0])
     x = U.round_bf16(rng.normal(size=shape + (cin,)))
@@ -111,8 +111,8 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-@pytest.mark.parametrize("variant", ["tiled", "direct"])
-@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 20, 24), (8, 36, 20)])
+@pytest.mark.parametrize("variant", ["tiled", "direct", "reg"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 20, 24), (8, 36, 20), (32, 48, 48)])
 def test_forward_matches_reference(shape, variant):
     net = pf.UNet(seed=3)
     net.set_conv_kernel(variant)
@@ -131,6 +131,77 @@ def test_forward_matches_reference(shape, variant):
         assert np.abs(got - ref).max() <= 5e-2 and np.abs(got - ref).mean() <= 5e-3
 
 
+def routing_params(seed: int):
+    """Parameters of a network whose every convolution copies one input channel
+    at one tap (weight 1, bias 0): with the glass mask and the constant 1
+    features as input, every activation is a multiple of 1/64 in [0, 1], so
+    BF16 storage, FP32 accumulation and pooling are exact and the forward
+    pass has one correct value per voxel.  The decoder convolutions take half
+    of their outputs from the upsampled path and half from the skip."""
+    rng = np.random.default_rng(seed)
+    offs, hw, hb, n = U.layout()
+    p = np.zeros(n, np.float32)
+    for i, ((cin, cout), (wo, bo)) in enumerate(zip(U.LAYERS, offs)):
+        w = np.zeros((cout, 27, cin), np.float32)
+        for co in range(cout):
+            if i == 0:  # mostly the glass mask, some constant features
+                src = 0 if co % 4 else int(rng.integers(1, 3))
+            elif i in (6, 8):                             # [upsampled, skip]
+                n_up = cin - (32 if i == 6 else 16)
+                src = int(rng.integers(0, n_up)) if co < cout // 2 else \
+                    int(rng.integers(n_up, cin))
+            else:
+                src = int(rng.integers(0, cin))
+            w[co, int(rng.integers(0, 27)), src] = 1.0
+        p[wo:bo] = w.ravel()
+    return p, hw, hb
+
+
+@pytest.mark.parametrize("variant", ["tiled", "direct", "reg"])
+@pytest.mark.parametrize("shape", [(12, 20, 24), (8, 8, 16), (32, 48, 48)])
+def test_forward_exact_routing_network_every_voxel(shape, variant):
+    """Element-wise check of the whole forward pass, glue included (pooling,
+    upsampling, the concatenation halves, zero padding at the borders, the
+    head and its masking): each of the 16 channels of the last convolution
+    is read out through a one-hot head, and every voxel must equal the
+    reference up to the sigmoid's FP32 rounding (no other rounding happens;
+    the reference with and without BF16 storage agree exactly)."""
+    _routing_check(shape, variant, range(16))
+
+
+def test_forward_exact_routing_network_large_grid():
+    """The same on a grid large enough for the 16 x 8 x 8 register blocks of
+    the full-resolution layers (four readouts: the FP64 reference takes
+    seconds per forward pass here)."""
+    _routing_check((84, 80, 80), "reg", (0, 5, 10, 15))
+
+
+def _routing_check(shape, variant, readouts):
+    net = pf.UNet(seed=1)
+    net.set_conv_kernel(variant)
+    mask, _ = _sample(shape, 5)
+    dT, ls = 2.0, 3.0   # input features log10(dT/0.2) = 1 and (ls - 1.5)/1.5 = 1
+    p, hw, hb = routing_params(11 + shape[0])
+    md = _dev(mask, torch.uint8)
+    distinct = set()
+    for c in readouts:
+        p[hw:hw + 16] = 0.0
+        p[hw + c] = 1.0
+        p[hb] = -0.25
+        net.set_params(p)
+        got = net.forward(md, dT, ls).cpu().numpy().astype(np.float64)
+        ref_b = U.forward(p.astype(np.float64), mask, dT, ls, bf16=True).numpy()
+        ref = U.forward(p.astype(np.float64), mask, dT, ls).numpy()
+        assert np.array_equal(ref_b, ref)  # nothing is rounded on the way
+        assert np.all(got[mask == 1] == 0)
+        err = np.abs(got - ref)
+        assert np.all(err <= 2.0 ** -21), (c, float(err.max()), np.argwhere(err > 2.0 ** -21)[:5])
+        distinct.update(np.unique(np.round(ref[mask == 0], 9)).tolist())
+    # the readouts see many different activation values (not a constant net)
+    assert len(distinct) >= 8
+    net.close()
+
+
 def test_forward_deterministic():
     net = pf.UNet(seed=4)
     mask, _ = _sample((16, 16, 16), 2)
@@ -140,7 +211,7 @@ def test_forward_deterministic():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("variant", ["tiled", "direct"])
+@pytest.mark.parametrize("variant", ["tiled", "direct", "reg"])
 def test_gradient_matches_reference(variant):
     shape = (16, 16, 16)
     net = pf.UNet(seed=5)
@@ -199,7 +270,7 @@ def test_warmstart_writes_prediction(precision):
     net = pf.UNet(seed=8)
     dT, ls = c.params["dT"], 0.0
     pred = net.forward(_dev(c.mask, torch.uint8), dT, ls).cpu().numpy()
-    net.warmstart(s, dT, ls, restrict_to_nucleus=False)
+    net.warmstart(s, dT, ls, mode="all")
     phi, _ = s.get_state()
     assert np.array_equal(phi.reshape(pred.shape), pred.astype(phi.dtype))
     # restricted to the water component(s) of the nucleus
@@ -209,6 +280,11 @@ def test_warmstart_writes_prediction(precision):
     keep = U.nucleus_component(c.mask, c.phi0)
     assert np.array_equal(phi2[keep], pred[keep].astype(phi.dtype))
     assert np.all(phi2[~keep] == 0)
+    # the baseline without the network: 1 on the nucleus's component
+    s.set_state(c.phi0.astype(phi.dtype))
+    net.warmstart(s, dT, ls, mode="flood")
+    phi3, _ = s.get_state()
+    assert np.array_equal(phi3, keep.astype(phi.dtype))
     s.close()
 
 
@@ -247,11 +323,12 @@ def test_errors():
 
 
 @pytest.mark.parametrize("edge", [96, 192])
-def test_full_size_convolution_sampled(edge):
-    """The largest convolution (48 -> 16 channels, full resolution) at the
-    benchmark grids; sampled voxels against the direct sum."""
-    rng = np.random.default_rng(edge)
-    cin, cout = 48, 16
+@pytest.mark.parametrize("cin,cout", [(48, 16), (16, 16), (8, 16), (16, 32)])
+def test_full_size_convolution_sampled(edge, cin, cout):
+    """The full-resolution convolutions at the benchmark grids (the largest,
+    48 -> 16 channels, and the other shapes of the register-blocked form);
+    sampled voxels against the direct sum."""
+    rng = np.random.default_rng(edge + cin)
     shape = (edge, edge, edge)
     xb = torch.randint(-16000, 16000, shape + (cin,), dtype=torch.int16, device=DEV)
     # keep the BF16 values moderate: sign, exponent in [-8, 1]

@@ -1,6 +1,8 @@
 """Micro-scale UWC experiment (paper-mode vessel at the carbon-black scale):
 the GPU run to a stationary state against the FP64 oracle run to the same
-criterion, compared on the unfrozen water content of the bottom half."""
+criterion, compared on the unfrozen water content of the bottom half (Sec.
+3.3, eq. UWC-formula): the GPU's plane-range reduction against the oracle's
+own bottom-half count."""
 import numpy as np
 import pytest
 
@@ -26,7 +28,12 @@ def test_uwc_run_matches_oracle(dT):
                                      c.run["dt0"], c.phi0, None, max_steps=200000, eq_tol=eq1)
     phi_o, _, st = oracle.integrate(P, c.G, oracle.make_ctl(tol=c.run["tol_eq"]), st1["t"],
                                     st1["dt"], phi_o, None, max_steps=200000, eq_tol=U.EQ_TOL)
-    ref = U.bottom_half_uwc(c.G, phi_o)
+    ref = oracle.uwc_bottom_half(P, c.G, phi_o)
+    # the ice set of eq. frozen-subdomain is every cell with phi > 1/2; the
+    # counts take it among the water cells, the same set here because no
+    # glass cell of the bottom half holds phi > 1/2
+    half = c.G.shape[0] // 2
+    assert not np.any((c.G[:half] >= 0.5) & (phi_o[:half] > 0.5))
     assert st["status"] == oracle.EQUILIBRIUM and gpu["status"] == 1
     assert gpu["water_cells"] == ref["water_cells"]
     assert gpu["ice_cells"] == ref["ice_cells"]

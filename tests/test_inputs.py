@@ -152,17 +152,3 @@ def test_paper_glass_field_and_case():
     assert np.all(k.mask[x3 > 11 / 12 * 40 + 1] == 1)
     z = np.nonzero(k.phi0.sum(axis=(1, 2)))[0]
     assert (z.min() + 0.5) > 0.87 * 40 and (z.max() + 0.5) < 0.97 * 40
-
-
-def test_bottom_half_uwc_definition():
-    from paper_2401_01672_amd.uwc_sweep import bottom_half_uwc
-    G = np.zeros((4, 2, 2))
-    G[0, 0, 0] = 1.0      # glass in the bottom half
-    G[3, :, :] = 1.0      # glass in the top half (ignored)
-    phi = np.zeros((4, 2, 2))
-    phi[1, :, :] = 0.9    # 4 ice cells in the bottom half
-    phi[0, 0, 1] = 0.5    # not ice (strict phi > 1/2)
-    phi[2, :, :] = 1.0    # top half (ignored)
-    r = bottom_half_uwc(G, phi)
-    assert r["water_cells"] == 7 and r["ice_cells"] == 4
-    assert r["uwc"] == pytest.approx(3 / 7)
