@@ -1,6 +1,9 @@
 """Batched sweep (per-stage launches over all running instances, or one
 persistent cooperative kernel) against per-instance runs and the FP64
 oracle, through the C ABI."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -184,30 +187,58 @@ def test_sweep_instances_batch_to_equilibrium_small_subset():
         s.close()
 
 
-def test_sweep_fp32_batch_matches_fp64_runs():
-    """Four 48^3 instances of the sweep generator: the FP32 batch run to
-    equilibrium against FP64 single runs to equilibrium.  The FP32 trajectory
-    differs by rounding, so the comparison is on what the run is for: both
-    reach equilibrium and give the same unfrozen water content (eq.
-    UWC-formula) to within 1e-3 of the water cells."""
-    cases = [pi.sweep_instance(4000 + i) for i in (5, 9, 17, 27)]
+SWEEP48 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sweep48.json")
+
+
+def test_sweep48_fp32_batch_to_equilibrium_against_oracle():
+    """Six 48^3 instances of the sweep generator (four freeze, two melt back)
+    run together in one FP32 batch to equilibrium, against the FP64 oracle's
+    own runs (tests/golden/sweep48.json, written by
+    tests/golden/make_sweep48.py): both reach equilibrium with the same water
+    cells and an unfrozen water content within 1e-3 of the water cells."""
+    gold = json.load(open(SWEEP48))
+    cases = [pi.sweep_instance(r["seed"]) for r in gold["runs"]]
     ss = []
     for c in cases:
         s = pf.Solver(c.params, c.mask, "fp32", c.run)
         s.set_state(c.phi0.astype(np.float32))
         s.set_time(0.0, c.run["dt0"])
         ss.append(s)
-    stats = pf.batch_integrate(ss, max_steps=400000, eq_tol=1e-6)
-    for c, st32 in zip(cases, stats):
-        s64 = pf.Solver(c.params, c.mask, "fp64", c.run)
-        s64.set_state(c.phi0)
-        s64.set_time(0.0, c.run["dt0"])
-        st64 = s64.integrate(max_steps=400000, eq_tol=1e-6)
-        s64.close()
-        assert st32["status"] == st64["status"] == pf.PF_EQUILIBRIUM
-        assert st32["pore_count"] == st64["pore_count"]
-        d_uwc = abs(st32["ice_count"] - st64["ice_count"]) / st64["pore_count"]
-        print(f"sweep instance {c.name}: FP32 batch vs FP64 run, UWC difference {d_uwc:.2e}")
-        assert d_uwc <= 1e-3, (c.name, st32["ice_count"], st64["ice_count"])
+    stats = pf.batch_integrate(ss, max_steps=gold["budget"], eq_tol=gold["eq_tol"])
+    for r, st in zip(gold["runs"], stats):
+        d_uwc = abs(st["ice_count"] - r["ice_cells"]) / r["water_cells"]
+        print(f"sweep instance {r['seed']}: FP32 batch UWC {st['uwc']:.6f} "
+              f"({st['steps_accepted'] + st['steps_rejected']} attempts), oracle UWC "
+              f"{r['uwc']:.6f} ({r['steps_accepted'] + r['steps_rejected']} attempts), "
+              f"difference {d_uwc:.2e} of the water cells")
+        assert r["status"] == oracle.EQUILIBRIUM and st["status"] == pf.PF_EQUILIBRIUM
+        assert st["pore_count"] == r["water_cells"]
+        assert d_uwc <= 1e-3, (r["seed"], st["ice_count"], r["ice_cells"])
     for s in ss:
+        s.close()
+
+
+def test_sweep48_fp32_batch_fixed_steps_against_oracle():
+    """The same six instances, 100 fixed steps of 0.05 s in one FP32 batch,
+    against the FP64 oracle element by element (max |d phi| <= 1e-4)."""
+    gold = json.load(open(SWEEP48))
+    cases = [pi.sweep_instance(r["seed"]) for r in gold["runs"]]
+    dt, steps = 0.05, 100
+    ss = []
+    for c in cases:
+        s = pf.Solver(c.params, c.mask, "fp32", dict(c.run, tol=0.0))
+        s.set_state(c.phi0.astype(np.float32))
+        s.set_time(0.0, dt)
+        ss.append(s)
+    stats = pf.batch_integrate(ss, max_steps=steps)
+    for c, s, st in zip(cases, ss, stats):
+        assert st["steps_accepted"] == steps
+        P = oracle.make_params(c.params)
+        ph_o, _, _ = oracle.integrate(P, c.mask, oracle.make_ctl(tol=0.0), 0.0, dt, c.phi0,
+                                      max_steps=steps)
+        g, _ = s.get_state()
+        err = float(np.abs(g.astype(np.float64) - ph_o).max())
+        print(f"sweep instance {c.name}: {steps} fixed steps, FP32 batch vs FP64 oracle "
+              f"max|dphi| = {err:.2e}")
+        assert err <= 1e-4
         s.close()
