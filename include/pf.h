@@ -366,12 +366,13 @@ void pf_unet_destroy(pf_unet* net);
 const char* pf_unet_last_error(const pf_unet* net);
 int pf_unet_set_stream(pf_unet* net, uintptr_t stream);
 /* Forward (and data-gradient) convolution kernel of this network:
- * 2: register-blocked where it applies (cout <= 32 on grids of at least
- * 2^16 voxels), else as 1 -- each wavefront keeps the nine (dz, dy) weight
- * fragments of a k-block in registers and reads every staged input row once
- * for all the output rows and planes it feeds;
- * 1 (default): LDS-tiled -- a 16 x 4 x 4 block of output voxels per
- * workgroup with its input halo staged in LDS per chunk of input channels;
+ * 2 (default): register-blocked where it is faster (16 input channels,
+ * cout <= 32, grids of at least 2^16 voxels), else as 1 -- per group of 8
+ * input channels the input block and the weights are copied into LDS
+ * asynchronously (double buffered) and every staged input row feeds all the
+ * output rows and planes it reaches;
+ * 1: LDS-tiled -- a 16 x 4 x 4 block of output voxels per workgroup with
+ * its input halo staged in LDS per chunk of input channels;
  * 0: direct -- every B fragment gathered from memory.  Same products; the
  * FP32 partial sums are taken in another order. */
 int pf_unet_set_conv_kernel(pf_unet* net, int32_t variant);
@@ -437,8 +438,9 @@ int pf_warmstart(pf_handle* h, pf_unet* net, double dT, double log10_sigma_scale
 
 /* Building blocks (each call allocates and frees its own scratch; device
  * pointers; BF16 tensors channels-last [n][c], FP32 weights [cout][27][cin],
- * taps as above; the convolutions run on the LDS-tiled kernel).
- * y = act(conv3x3x3(x) + b) with act = ReLU if relu != 0;
+ * taps as above; the convolutions run on the kernel that
+ * pf_unet_set_conv_kernel selects with 2).  y = act(conv3x3x3(x) + b) with
+ * act = ReLU if relu != 0;
  * cin % 8 == 0, cout in {16, 32, 48, 64, 96}; b may be NULL.  Synchronous. */
 int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b, int32_t relu,
                   uint16_t* y, int32_t cout, int32_t n1, int32_t n2, int32_t n3,

@@ -453,8 +453,8 @@ class UNet:
             pass
 
     def set_conv_kernel(self, variant: str):
-        """'tiled' (default, LDS-staged input blocks), 'reg' (register-blocked
-        where it applies) or 'direct'."""
+        """'reg' (default: register-blocked where it is faster, else tiled),
+        'tiled' (LDS-staged input blocks) or 'direct'."""
         self._check(lib().pf_unet_set_conv_kernel(
             self.h, {"direct": 0, "tiled": 1, "reg": 2}[variant]))
 

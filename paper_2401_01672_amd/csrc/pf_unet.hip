@@ -271,22 +271,50 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
 // all cout; the four wavefronts of a workgroup sit 2 x 2 in (y, z), so a
 // workgroup owns 16 x 2TY x 2TZ voxels.  A k-block of 32 is one group of 8
 // input channels at the three x-shifts: lane group g < 3 takes dx = g - 1,
-// group 3 is zero.  For each channel group the input block with its halo is
-// staged in LDS (16 bytes per voxel), the nine weight fragments (dz, dy) of
-// the k-block stay in registers, and every input fragment -- one halo row y_in
-// of one halo plane z_in -- is read from LDS once and feeds the MFMAs of every
-// output row t = y_in - dy and plane w = z_in - dz it reaches (up to nine),
-// instead of one.  Same products as conv3_tile_kernel; the FP32 sums are
-// taken in another order.
+// group 3 is zero.  Per channel group the input block with its halo (16
+// bytes per voxel) and the group's weight fragments (nine (dz, dy) per lane)
+// are copied from global memory straight into LDS (global_load_lds, no
+// registers), double buffered: the copy of group c + 1 runs while group c is
+// computed.  Every input fragment -- one halo row y_in of one halo plane
+// z_in -- is read from LDS once and feeds the MFMAs of every output row
+// t = y_in - dy and plane w = z_in - dz it reaches (up to nine).  Voxels
+// outside the grid, and the zero lane group's weights, are read from a
+// zeroed line.  Same products as conv3_tile_kernel; the FP32 sums are taken
+// in another order.
+
+__device__ __align__(16) const uint4 kZeroLine = {0u, 0u, 0u, 0u};
+
+// one 16-byte global -> LDS copy per lane; dst is the wavefront's slot 0 (the
+// lane's slot is dst + lane)
+__device__ __forceinline__ void copy16_lds(const void* src, uint4* dst_wave) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst_wave, 16, 0,
+                                   0);
+}
+
+template <int MT, int TY, int TZ>
+__host__ __device__ constexpr int reg_halo() { return 18 * (2 * TY + 2) * (2 * TZ + 2); }
+template <int MT>
+__host__ __device__ constexpr int reg_wslots() { return 9 * 64 * MT; }
+template <int MT, int TY, int TZ>
+__host__ __device__ constexpr int reg_lds_bytes() {
+  // two buffers, each: the halo block rounded up to whole wavefront copies,
+  // then the weight fragments
+  return 2 * (((reg_halo<MT, TY, TZ>() + 63) / 64) * 64 + reg_wslots<MT>()) * 16;
+}
 
 template <int MT, int TY, int TZ>
 __global__ __launch_bounds__(256) void conv3_reg_kernel(ConvArgs a, int tiles_x, int tiles_y,
                                                          int tiles_z) {
   constexpr int BY = 2 * TY, BZ = 2 * TZ;
   constexpr int HX = 18, HY = BY + 2, HZ = BZ + 2, HV = HX * HY * HZ;
-  __shared__ __align__(16) uint4 sx[HV];
+  constexpr int HVP = ((HV + 63) / 64) * 64;  // halo slots per buffer
+  constexpr int WS = reg_wslots<MT>();        // weight slots per buffer
+  constexpr int BUF = HVP + WS;
+  extern __shared__ __align__(16) uint4 reg_lds[];
+  uint4* lds = reg_lds;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, g = lane >> 4, r = lane & 15, w = tid >> 6;
+  const int lane = tid & 63, g = lane >> 4, r = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wy = w & 1, wz = w >> 1;
   // XCD-aware order: consecutive tiles of a row stay on one XCD
   const int nblk = gridDim.x;
@@ -296,6 +324,36 @@ __global__ __launch_bounds__(256) void conv3_reg_kernel(ConvArgs a, int tiles_x,
   const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
   const int x0 = tx * 16, y0 = ty * BY, z0 = tz * BZ;
   (void)tiles_z;
+  const bool gact = g < 3;  // lane group 3 carries the zero quarter of each k-block
+
+  // issue the copies of channel group c8 into buffer `buf` (asynchronous)
+  auto stage = [&](int c8, int buf) {
+    uint4* base = lds + (size_t)buf * BUF;
+    for (int i0 = w * 64; i0 < HV; i0 += 256) {
+      const int i = i0 + lane;
+      if (i < HV) {
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        const void* src = &kZeroLine;
+        if (x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3) {
+          const long long v = ((long long)z * a.n2 + y) * a.n1 + x;
+          src = a.in + v * a.in_stride + a.in_off + 8 * c8;
+        }
+        copy16_lds(src, base + i0);
+      }
+    }
+    // weight slot (m, dz, dy) x lane: W[m*16 + r][tap(dz, dy, dx = g - 1)][8 c8 ..]
+    for (int s0 = w * 64; s0 < WS; s0 += 256) {
+      const int f = s0 / 64;  // fragment index m * 9 + dz * 3 + dy
+      const int m = f / 9, dz = (f % 9) / 3, dy = f % 3;
+      const void* src = &kZeroLine;
+      if (gact) {
+        const int tap = dz * 9 + dy * 3 + g;
+        src = a.w + (long long)(m * 16 + r) * a.kpad + tap * a.cin + 8 * c8;
+      }
+      copy16_lds(src, base + HVP + s0);
+    }
+  };
 
   f32x4 acc[MT][TZ][TY];
 #pragma unroll
@@ -305,22 +363,17 @@ __global__ __launch_bounds__(256) void conv3_reg_kernel(ConvArgs a, int tiles_x,
 #pragma unroll
       for (int t = 0; t < TY; ++t) acc[m][i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const bool gact = g < 3;  // lane group 3 carries the zero quarter of each k-block
   const int ngroups = a.cin / 8;
+  stage(0, 0);
+  const int hoff = (wz * TZ * HY + wy * TY) * HX + r + (gact ? g : 0);
   for (int c8 = 0; c8 < ngroups; ++c8) {
+    // this group's copies are complete and visible; every wavefront is done
+    // with the other buffer (group c8 - 1), which the next copy overwrites
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // stage the halo block of channels 8 c8 .. 8 c8 + 7 (zeros outside the grid)
-    for (int i = tid; i < HV; i += 256) {
-      const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-      const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-      uint4 val = make_uint4(0u, 0u, 0u, 0u);
-      if (x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3) {
-        const long long src = ((long long)z * a.n2 + y) * a.n1 + x;
-        val = *reinterpret_cast<const uint4*>(a.in + src * a.in_stride + a.in_off + 8 * c8);
-      }
-      sx[i] = val;
-    }
-    // the nine weight fragments of this k-block: W[co][tap(dz, dy, dx = g - 1)][8 c8 ..]
+    if (c8 + 1 < ngroups) stage(c8 + 1, (c8 + 1) & 1);
+    const uint4* hb = lds + (size_t)(c8 & 1) * BUF;
+    const uint4* wb = hb + HVP;
     bf16x8 afr[MT][3][3];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -328,21 +381,16 @@ __global__ __launch_bounds__(256) void conv3_reg_kernel(ConvArgs a, int tiles_x,
       for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-          const int tap = dz * 9 + dy * 3 + (gact ? g : 0);
-          afr[m][dz][dy] = gact ? ld8(a.w + (long long)(m * 16 + r) * a.kpad + tap * a.cin + 8 * c8)
-                                : zero8();
+          const uint4 u = wb[(m * 9 + dz * 3 + dy) * 64 + lane];
+          afr[m][dz][dy] = *reinterpret_cast<const bf16x8*>(&u);
         }
-    __syncthreads();
-    const int hbase = (wz * TZ * HY + wy * TY) * HX + r + (gact ? g : 0);
 #pragma unroll
     for (int zi = 0; zi < TZ + 2; ++zi) {
 #pragma unroll
       for (int yi = 0; yi < TY + 2; ++yi) {
-        bf16x8 f = zero8();
-        if (gact) {
-          const uint4 u = sx[hbase + (zi * HY + yi) * HX];
-          f = *reinterpret_cast<const bf16x8*>(&u);
-        }
+        const uint4 u = hb[hoff + (zi * HY + yi) * HX];
+        bf16x8 f = *reinterpret_cast<const bf16x8*>(&u);
+        if (!gact) f = zero8();
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
           const int wv = zi - dz;
@@ -881,17 +929,24 @@ static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int TY, int TZ>
-static hipError_t launch_reg(const ConvArgs& a, hipStream_t s) {
+template <int MT, int TY, int TZ>
+static hipError_t launch_reg_mt(const ConvArgs& a, hipStream_t s) {
   const int tx = (a.n1 + 15) / 16, ty = (a.n2 + 2 * TY - 1) / (2 * TY),
             tz = (a.n3 + 2 * TZ - 1) / (2 * TZ);
-  const dim3 grid((unsigned)(tx * ty * tz)), block(256);
+  constexpr size_t lds = reg_lds_bytes<MT, TY, TZ>();
+  static_assert(lds <= 65536, "register-blocked convolution: LDS block too large");
+  hipLaunchKernelGGL((conv3_reg_kernel<MT, TY, TZ>), dim3((unsigned)(tx * ty * tz)), dim3(256),
+                     lds, s, a, tx, ty, tz);
+  return hipGetLastError();
+}
+
+template <int TY, int TZ>
+static hipError_t launch_reg(const ConvArgs& a, hipStream_t s) {
   switch (a.cout / 16) {
-    case 1: hipLaunchKernelGGL((conv3_reg_kernel<1, TY, TZ>), grid, block, 0, s, a, tx, ty, tz); break;
-    case 2: hipLaunchKernelGGL((conv3_reg_kernel<2, TY, TZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 1: return launch_reg_mt<1, TY, TZ>(a, s);
+    case 2: return launch_reg_mt<2, TY, TZ>(a, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
@@ -900,10 +955,14 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const long long nvox = (long long)a.n1 * a.n2 * a.n3;
   if (nvox == 0) return hipSuccess;
-  if (a.variant == 2) {
-    // register-blocked on grids with enough 16 x 8 x 8 blocks to fill the
-    // chip; the LDS-tiled form elsewhere
-    if (a.cout <= 32 && nvox >= (1LL << 19)) return launch_reg<4, 4>(a, s);
+  if (a.variant == 2 && a.cin == 16) {
+    // register-blocked where it was measured faster: 16 input channels on
+    // grids with enough blocks to fill the chip (at 96^3: 16 -> 16 in 40 us
+    // against 53 us, 16 -> 32 at 48^3 in 15 us against 18 us); with 8 or 48
+    // and more input channels the per-group copy latency of the
+    // register-blocked form costs more than its LDS savings, and the
+    // LDS-tiled form runs
+    if (a.cout == 16 && nvox >= (1LL << 19)) return launch_reg_mt<1, 4, 2>(a, s);
     if (a.cout <= 32 && nvox >= (1LL << 16)) return launch_reg<2, 2>(a, s);
   }
   if (a.variant >= 1) {

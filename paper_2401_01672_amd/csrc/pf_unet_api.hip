@@ -96,7 +96,7 @@ struct pf_unet {
   uint16_t* wslab = nullptr;
   long long adam_step = 0;
   int weights_dirty = 1;
-  int conv_variant = 1;  // forward-convolution kernel (2 register-blocked, 1 LDS-tiled, 0 direct)
+  int conv_variant = 2;  // forward-convolution kernel (2 register-blocked where it is faster, 1 LDS-tiled, 0 direct)
   // grid-dependent buffers
   int n1 = 0, n2 = 0, n3 = 0, train = 0;
   void* slab = nullptr;
@@ -752,7 +752,7 @@ int pf_conv3_bf16(const uint16_t* x, int32_t cin, const float* w, const float* b
   a.n1 = n1;
   a.n2 = n2;
   a.n3 = n3;
-  a.variant = 1;
+  a.variant = 2;
   if (rc == PF_OK && pfu::launch_conv_fwd(a, s) != hipSuccess) rc = PF_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;
   (void)hipFree(wf);
@@ -796,7 +796,7 @@ int pf_conv3_bf16_noalloc(const uint16_t* x, int32_t cin, const float* w, const 
   a.n1 = n1;
   a.n2 = n2;
   a.n3 = n3;
-  a.variant = 1;
+  a.variant = 2;
   if (e == hipSuccess) e = pfu::launch_conv_fwd(a, s);
   if (e != hipSuccess) {
     pf::set_thread_error(std::string("pf_conv3_bf16_noalloc: launch: ") + hipGetErrorString(e));
@@ -862,7 +862,7 @@ int pf_conv3_bf16_backward(const uint16_t* x, int32_t cin, const float* w, const
     a.n1 = n1;
     a.n2 = n2;
     a.n3 = n3;
-    a.variant = 1;
+    a.variant = 2;
     if (rc == PF_OK && pfu::launch_conv_fwd(a, s) != hipSuccess) rc = PF_EHIP;
   }
   if (hipStreamSynchronize(s) != hipSuccess) rc = PF_EHIP;

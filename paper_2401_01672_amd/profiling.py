@@ -30,11 +30,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CAL_BYTES = 1 << 30
 
 
-def source_hash() -> str:
-    """Hash of the stencil kernel sources (the traffic depends only on them)."""
+STENCIL_SOURCES = ("pf_internal.h", "pf_stencil.hip")
+UNET_SOURCES = ("pf_unet_internal.h", "pf_unet.hip")
+
+
+def source_hash(files=STENCIL_SOURCES) -> str:
+    """Hash of kernel sources (by default the stencil kernels', on which the
+    stencil traffic depends)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2401_01672_amd", "csrc")
-    for f in ("pf_internal.h", "pf_stencil.hip"):
+    for f in files:
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -139,7 +144,7 @@ def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_
     print("\n".join(written))
 
 
-def kernel_stats(title: str, trace_dir: str, command: str, out: str):
+def kernel_stats(title: str, trace_dir: str, command: str, out: str, sources=STENCIL_SOURCES):
     """Markdown table of per-kernel durations from a rocprofv3 kernel trace.
 
     Besides the plain average over all dispatches it gives the average over
@@ -158,7 +163,7 @@ def kernel_stats(title: str, trace_dir: str, command: str, out: str):
             by.setdefault(r["Kernel_Name"], []).append(d)
     total = sum(sum(v) for v in by.values())
     lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (repo root):", "", "```",
-             command, "```", "", f"Kernel sources: `{source_hash()}`", "",
+             command, "```", "", f"Kernel sources: `{source_hash(sources)}`", "",
              "| kernel | calls | avg us | working calls | working avg us | min us | max us | % time |",
              "|---|---|---|---|---|---|---|---|"]
     for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
@@ -196,7 +201,8 @@ def conv(edge: int, reps: int, variant: str):
     net.close()
 
 
-def pmc_summary(title: str, dirs, commands, out: str, match: str = ""):
+def pmc_summary(title: str, dirs, commands, out: str, match: str = "",
+                sources=STENCIL_SOURCES):
     """Markdown table of per-dispatch counter means per kernel, from one or
     more rocprofv3 --pmc runs (one counter set per run)."""
     vals = {}
@@ -214,7 +220,7 @@ def pmc_summary(title: str, dirs, commands, out: str, match: str = ""):
                     key, 0.0)
                 vals[k][row["Counter_Name"]][key] += float(row["Counter_Value"])
     lines = [f"# rocprofv3 counters: {title}", "", "Commands (repo root):", "", "```",
-             *commands, "```", "", f"Kernel sources: `{source_hash()}`", "",
+             *commands, "```", "", f"Kernel sources: `{source_hash(sources)}`", "",
              "Per-dispatch means (counters summed over the GPU's instances).", ""]
     for k in sorted(vals):
         lines += [f"## `{k[:100]}`", "", "| counter | dispatches | mean per dispatch |",
@@ -236,15 +242,17 @@ def main():
     pm.add_argument("--commands", nargs="+", required=True)
     pm.add_argument("--match", default="")
     pm.add_argument("--out", required=True)
+    pm.add_argument("--unet", action="store_true", help="hash the network's kernel sources")
     cv = sub.add_parser("conv")
     cv.add_argument("--edge", type=int, default=96)
     cv.add_argument("--reps", type=int, default=5)
-    cv.add_argument("--variant", default="tiled", choices=["tiled", "direct", "reg"])
+    cv.add_argument("--variant", default="reg", choices=["tiled", "direct", "reg"])
     k = sub.add_parser("stats")
     k.add_argument("--title", required=True)
     k.add_argument("--trace", required=True)
     k.add_argument("--command", required=True)
     k.add_argument("--out", required=True)
+    k.add_argument("--unet", action="store_true", help="hash the network's kernel sources")
     r = sub.add_parser("run")
     r.add_argument("--workload", default="coupled_256_fp32")
     r.add_argument("--schedule", default="five", choices=["paired", "five"])
@@ -257,11 +265,13 @@ def main():
     s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
     if a.cmd == "pmcsum":
-        pmc_summary(a.title, a.dirs, a.commands, a.out, a.match)
+        pmc_summary(a.title, a.dirs, a.commands, a.out, a.match,
+                    UNET_SOURCES if a.unet else STENCIL_SOURCES)
     elif a.cmd == "conv":
         conv(a.edge, a.reps, a.variant)
     elif a.cmd == "stats":
-        kernel_stats(a.title, a.trace, a.command, a.out)
+        kernel_stats(a.title, a.trace, a.command, a.out,
+                     UNET_SOURCES if a.unet else STENCIL_SOURCES)
     elif a.cmd == "run":
         run(a.workload, a.schedule, a.steps)
     else:
