@@ -103,7 +103,8 @@ def dirichlet_T(p, t):
 def gradient_norm(G, phi, h, face_mask=True):
     """|grad phi| per cell: for each axis the difference quotient over the
     open faces (both open: central, one open: one-sided, none: 0).  A face is
-    open when the neighbour exists and (face_mask) both cells are water."""
+    open when the neighbour exists and is water (G < 1/2), and (face_mask)
+    the cell is water too."""
     G = np.asarray(G, np.float64)
     ph = np.asarray(phi, np.float64)
     g2 = np.zeros(G.shape)
@@ -117,7 +118,7 @@ def gradient_norm(G, phi, h, face_mask=True):
                 lo = [slice(None)] * 3
                 lo[ax] = i - 1
                 lo = tuple(lo)
-                om = (G[sl] < 0.5) & (G[lo] < 0.5) if face_mask else np.ones(G[sl].shape, bool)
+                om = ((G[sl] < 0.5) & (G[lo] < 0.5)) if face_mask else (G[lo] < 0.5)
                 phm = np.where(om, ph[lo], ph[sl])
             else:
                 om = np.zeros(G[sl].shape, bool)
@@ -126,7 +127,7 @@ def gradient_norm(G, phi, h, face_mask=True):
                 hi = [slice(None)] * 3
                 hi[ax] = i + 1
                 hi = tuple(hi)
-                oq = (G[sl] < 0.5) & (G[hi] < 0.5) if face_mask else np.ones(G[sl].shape, bool)
+                oq = ((G[sl] < 0.5) & (G[hi] < 0.5)) if face_mask else (G[hi] < 0.5)
                 phq = np.where(oq, ph[hi], ph[sl])
             else:
                 oq = np.zeros(G[sl].shape, bool)

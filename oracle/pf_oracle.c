@@ -176,16 +176,20 @@ static int64_t neighbour(const or_params* p, int i1, int i2, int i3, int f) {
 }
 
 /* |grad phi| at a cell centre for the GradP reaction term: central
- * differences, one-sided where a neighbour is missing or closed to the phase
- * field (the zero-flux condition makes the normal derivative vanish there). */
+ * differences, one-sided where a neighbour is missing or not water (the
+ * zero-flux condition makes the normal derivative vanish at the domain
+ * boundary and at glass).  With the binary mask a face is open when both
+ * cells are water; with the smooth glass field when the neighbour is water
+ * (G < 1/2): the phase field inside the glass never evolves (I_W = 0 there)
+ * and carries no interface. */
 static double grad_phi_norm(const or_params* p, const double* G, const double* phi,
                             int i1, int i2, int i3, int64_t n) {
   double g2 = 0.0;
   for (int ax = 0; ax < 3; ++ax) {
     int64_t m = neighbour(p, i1, i2, i3, 2 * ax);
     int64_t q = neighbour(p, i1, i2, i3, 2 * ax + 1);
-    int open_m = m >= 0 && (!p->phi_face_mask || (G[n] < 0.5 && G[m] < 0.5));
-    int open_q = q >= 0 && (!p->phi_face_mask || (G[n] < 0.5 && G[q] < 0.5));
+    int open_m = m >= 0 && G[m] < 0.5 && (!p->phi_face_mask || G[n] < 0.5);
+    int open_q = q >= 0 && G[q] < 0.5 && (!p->phi_face_mask || G[n] < 0.5);
     double d = 0.0;
     if (open_m && open_q) d = (phi[q] - phi[m]) / (2.0 * p->h);
     else if (open_q) d = (phi[q] - phi[n]) / p->h;

@@ -318,7 +318,12 @@ struct CellRHSSmooth {
       for (int f = 0; f < 6; ++f) lap += pn[f] - pc;
       R fr;
       if (REACT == PF_REACT_GRADP) {
-        const R gn = grad_norm(m, pc, pn, inb);
+        // |grad phi| over the faces towards water neighbours (G < 1/2): the
+        // phase field inside the glass never evolves and carries no interface
+        unsigned wnb = 0u;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) wnb |= (Gn[f] < R(0.5) ? 1u : 0u) << f;
+        const R gn = grad_norm(m, pc, pn, inb & wnb);
         const R under = (MODEL == PF_MODEL_AC) ? R(m.dT) : -thc;
         fr = R(2) * pc * (R(1) - pc) * (pc - R(0.5)) + R(m.gpc) * gn * under;
       } else {

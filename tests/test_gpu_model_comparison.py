@@ -40,6 +40,8 @@ def test_gradp_leaves_range_and_fails_at_tiny_sigma(cases):
         assert r["phi_max"] > 1.0 and r["phi_min"] < 0.0, (setting, r)
         if setting == "tiny_sigma":
             assert r["status"] == -5 and r["t"] < T_END, r  # PF_EDTMIN
+        if setting == "large_sigma":  # completes, as in Tab. 3
+            assert r["status"] == 0 and r["t"] == T_END, r
 
 
 @pytest.mark.parametrize("reaction", ["sigma", "gradp"])
