@@ -222,8 +222,10 @@ int pf_rkm_step(pf_handle* h, double* t, double* dt, pf_step_info* info);
 int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
                  pf_run_stats* stats);
 
-/* Batched sweep: integrate n independent instances (same model and
- * precision, each with n1 divisible by 4 (FP32) or 2 (FP64), each with its own geometry,
+/* Batched sweep: integrate n independent instances (same model, precision
+ * and glass representation; the SigmaP1-P reaction; binary masks, or smooth
+ * glass fields (pf_create_field) with mode 2; each with n1 divisible by 4
+ * (FP32) or 2 (FP64), each with its own geometry,
  * constants, state, t and dt) together: every stage pass processes the tiles
  * of all unfinished instances in one launch (or one persistent cooperative
  * kernel runs all passes of a poll interval, see pf_batch_options), then each
@@ -231,7 +233,12 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
  * and status); finished instances drop out.  Stops each instance at t_end,
  * max_steps attempts, or equilibrium (eq_tol > 0), like pf_integrate.
  * out[i] receives instance i's statistics (wall_s: the whole batch).  stream:
- * a hipStream_t cast to uintptr_t, 0 = the first instance's stream.
+ * a hipStream_t cast to uintptr_t, 0 = the first instance's stream.  The
+ * first instance's handle keeps the batch's device work tables (descriptors,
+ * work items, gathered control blocks) until pf_destroy, grown when a call
+ * needs more: a repeat call with no more instances and work items than an
+ * earlier one on the same first handle allocates no device memory of its
+ * own (the HIP graph of the poll interval is instantiated per call).
  * Returns PF_OK or the first instance error code; synchronous. */
 typedef struct {
   int32_t mode;           /* 1: persistent cooperative kernel: one launch

@@ -66,6 +66,18 @@ struct pf_handle {
   double t = 0.0, dt = 0.0;
   int cur = 0;
   std::string err;
+  // work tables of pf_batch_integrate calls that list this handle first:
+  // kept (grown when a call needs more) so that repeat calls allocate nothing
+  struct BatchWork {
+    pf::BatchDesc* desc = nullptr;
+    int2* items = nullptr;
+    int* act = nullptr;
+    unsigned* bar = nullptr;
+    DevCtl* gath = nullptr;
+    DevCtl* hgath = nullptr;  // pinned
+    long long cap_items = 0;
+    int cap_inst = 0;
+  } bw;
 };
 
 namespace {
@@ -598,6 +610,40 @@ void set_thread_error(const std::string& msg) { g_create_err = msg; }
 }  // namespace pf
 
 namespace {
+void free_batch_work(pf_handle* h) {
+  pf_handle::BatchWork& b = h->bw;
+  (void)hipFree(b.desc);
+  (void)hipFree(b.items);
+  (void)hipFree(b.act);
+  (void)hipFree(b.bar);
+  (void)hipFree(b.gath);
+  if (b.hgath) (void)hipHostFree(b.hgath);
+  b = pf_handle::BatchWork();
+}
+
+// the batch work tables of h for n instances and nitems work items (grown,
+// never shrunk)
+int batch_work(pf_handle* h, int n, long long nitems) {
+  pf_handle::BatchWork& b = h->bw;
+  if (b.desc && n <= b.cap_inst && nitems <= b.cap_items) return PF_OK;
+  (void)hipStreamSynchronize(h->stream);
+  const int ni = n > b.cap_inst ? n : b.cap_inst;
+  const long long nit = nitems > b.cap_items ? nitems : b.cap_items;
+  free_batch_work(h);
+  if (hipMalloc(&b.desc, sizeof(pf::BatchDesc) * ni) != hipSuccess ||
+      hipMalloc(&b.items, sizeof(int2) * (size_t)(nit > 0 ? nit : 1)) != hipSuccess ||
+      hipMalloc(&b.act, sizeof(int) * ni) != hipSuccess ||
+      hipMalloc(&b.bar, 4 * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&b.gath, sizeof(DevCtl) * ni) != hipSuccess ||
+      hipHostMalloc((void**)&b.hgath, sizeof(DevCtl) * ni, hipHostMallocDefault) != hipSuccess) {
+    free_batch_work(h);
+    return PF_ENOMEM;
+  }
+  b.cap_inst = ni;
+  b.cap_items = nit;
+  return PF_OK;
+}
+
 hipStream_t work_stream(pf_handle* h, uintptr_t stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!stream || s == h->stream) return h->stream;
@@ -758,6 +804,7 @@ void pf_destroy(pf_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   drop_graph(h);
+  free_batch_work(h);
   if (h->slab) (void)hipFree(h->slab);
   if (h->hctl) (void)hipHostFree(h->hctl);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
@@ -1108,8 +1155,13 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
     if (inst[i]->P.precision != inst[0]->P.precision || inst[i]->P.model != inst[0]->P.model)
       return fail(nullptr, PF_EINVAL, "batch: all instances need the same model and precision");
-    if (simple_kernels_only(inst[i]->P, inst[i]->smooth))
+    if (inst[i]->P.model == PF_MODEL_TEMP || inst[i]->P.reaction != PF_REACT_SIGMA)
       return fail(nullptr, PF_EINVAL, "batch: the SigmaP1-P AC and coupled models only");
+    if (inst[i]->smooth != inst[0]->smooth)
+      return fail(nullptr, PF_EINVAL, "batch: all instances need the same glass representation");
+    if (inst[i]->smooth && mode == 1)
+      return fail(nullptr, PF_EINVAL,
+                  "batch: the persistent kernel takes binary masks only (paper mode: mode 2)");
     if (!vector_ok(inst[i]->P, inst[i]->smooth))
       return fail(nullptr, PF_EINVAL,
                   "batch: every instance needs n1 divisible by 4 (FP32) or 2 (FP64) and "
@@ -1120,6 +1172,8 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   // Planes per work item.  Fixed when given; otherwise 4 while the running
   // instances make at least kMinItems items, halved (down to 1) when fewer
   // remain, so that a few small instances still spread over the whole chip.
+  // (Deeper items, 8 or 16 planes, read fewer halo planes but leave the last
+  // round of workgroups ragged: measured slower on the 48-instance sweep.)
   const int z_fixed = (opts && opts->z_chunk) ? opts->z_chunk : 0;
   const int kBatchZ = 4;
   const long long kMinItems = 1024;
@@ -1147,55 +1201,41 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     all[i] = i;
     n1max = inst[i]->P.n1 > n1max ? inst[i]->P.n1 : n1max;
   }
-  const size_t lds = pf::stage4_lds_bytes(n1max, h0->nvar, h0->esize);
+  const size_t lds = pf::stage4_lds_bytes(n1max, h0->nvar + (h0->smooth ? 1 : 0), h0->esize);
   const long long max_items = batch_items_at(inst, all, z_fixed ? z_fixed : 1);
   if (max_items > (1LL << 30)) return fail(h0, PF_EINVAL, "batch: too many work items");
   std::vector<pf::BatchDesc> desc(n);
   memset(desc.data(), 0, sizeof(pf::BatchDesc) * n);
   std::vector<int2> items;
-  pf::BatchDesc* ddesc = nullptr;
-  int2* ditems = nullptr;
-  int* dact = nullptr;
-  unsigned* dbar = nullptr;  // [0] arrivals, [1] generation, [2] barrier-overrun flag
-  DevCtl* dgath = nullptr;   // control blocks of the running instances, gathered per poll
-  DevCtl* hgath = nullptr;   // pinned host copy
-  if (hipMalloc(&ddesc, sizeof(pf::BatchDesc) * n) != hipSuccess ||
-      hipMalloc(&ditems, sizeof(int2) * (size_t)(max_items > 0 ? max_items : 1)) != hipSuccess ||
-      hipMalloc(&dact, sizeof(int) * n) != hipSuccess ||
-      hipMalloc(&dbar, 4 * sizeof(unsigned)) != hipSuccess ||
-      hipMalloc(&dgath, sizeof(DevCtl) * n) != hipSuccess ||
-      hipHostMalloc((void**)&hgath, sizeof(DevCtl) * n, hipHostMallocDefault) != hipSuccess) {
-    (void)hipFree(ddesc);
-    (void)hipFree(ditems);
-    (void)hipFree(dact);
-    (void)hipFree(dbar);
-    (void)hipFree(dgath);
-    if (hgath) (void)hipHostFree(hgath);
+  // the first instance's work tables (allocated on its first batch, reused)
+  if (batch_work(h0, n, max_items) != PF_OK)
     return fail(h0, PF_ENOMEM, "batch: descriptor allocation failed");
-  }
+  pf::BatchDesc* ddesc = h0->bw.desc;
+  int2* ditems = h0->bw.items;
+  int* dact = h0->bw.act;
+  unsigned* dbar = h0->bw.bar;     // [0] arrivals, [1] generation, [2] barrier-overrun flag
+  DevCtl* dgath = h0->bw.gath;     // control blocks of the running instances, gathered per poll
+  DevCtl* hgath = h0->bw.hgath;    // pinned host copy
   hipGraphExec_t gexec = nullptr;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
-    (void)hipFree(ddesc);
-    (void)hipFree(ditems);
-    (void)hipFree(dact);
-    (void)hipFree(dbar);
-    (void)hipFree(dgath);
-    (void)hipHostFree(hgath);
   };
   unsigned hbar[4] = {0, 0, 0, 0};
   if (hipMemcpyAsync(dbar, hbar, sizeof(hbar), hipMemcpyHostToDevice, s) != hipSuccess) {
     cleanup();
     return fail(h0, PF_EHIP, "batch: barrier upload failed");
   }
-  // Tiles, descriptors and items of the running instances (act); the
-  // multi-launch form also captures kStepsPerLaunch attempts over them.
+  // Tiles, descriptors and items of the running instances (act), which
+  // become the table's instances (tab); the multi-launch form also captures
+  // kStepsPerLaunch attempts over them.
+  std::vector<int> tab;
   auto build = [&]() -> int {
     int z = z_fixed ? z_fixed : kBatchZ;
     if (!z_fixed)
       while (z > 1 && batch_items_at(inst, act, z) < kMinItems) z >>= 1;
+    tab = act;
     items.clear();
     for (int i : act) {
       pf_handle* h = inst[i];
@@ -1223,8 +1263,8 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
-      e = pf::launch_batch_step(h0->P.precision, h0->P.model, ddesc, ditems, (int)items.size(),
-                                dact, (int)act.size(), lds, s);
+      e = pf::launch_batch_step(h0->P.precision, h0->P.model, h0->smooth, ddesc, ditems,
+                                (int)items.size(), dact, (int)act.size(), lds, s);
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e == hipSuccess && e2 == hipSuccess) {
       e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
@@ -1264,10 +1304,10 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       cleanup();
       return fail(h0, PF_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
-    // the running instances' control blocks: one gather, one copy (dact
-    // lists them in the order of act)
-    if (pf::launch_gather_ctl(ddesc, dact, (int)act.size(), dgath, s) != hipSuccess ||
-        hipMemcpyAsync(hgath, dgath, sizeof(DevCtl) * act.size(), hipMemcpyDeviceToHost, s) !=
+    // the table's control blocks: one gather, one copy (dact lists them in
+    // the order of tab)
+    if (pf::launch_gather_ctl(ddesc, dact, (int)tab.size(), dgath, s) != hipSuccess ||
+        hipMemcpyAsync(hgath, dgath, sizeof(DevCtl) * tab.size(), hipMemcpyDeviceToHost, s) !=
             hipSuccess) {
       cleanup();
       return fail(h0, PF_EHIP, "batch: control readback failed");
@@ -1277,7 +1317,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       cleanup();
       return fail(h0, PF_EHIP, "batch: synchronize failed");
     }
-    for (size_t k = 0; k < act.size(); ++k) *inst[act[k]]->hctl = hgath[k];
+    for (size_t k = 0; k < tab.size(); ++k) *inst[tab[k]]->hctl = hgath[k];
     if (hbar[2]) {
       cleanup();
       return fail(h0, PF_EHIP, "batch: a grid barrier wait overran its bound");
@@ -1295,6 +1335,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
         cleanup();
         return fail(h0, PF_EHIP, "batch: instance list upload failed");
       }
+      tab = act;
       continue;
     }
     int rc = build();  // fewer instances: smaller grids, maybe thinner tiles

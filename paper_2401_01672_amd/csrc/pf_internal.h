@@ -178,10 +178,11 @@ hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const i
                         unsigned* err, size_t lds, hipStream_t s);
 int batch_max_blocks(int precision, int model, size_t lds);
 // batched sweep, multi-launch form: one attempt = 5 stage launches over the
-// nitems items + 1 controller launch over the ninst instances of inst_list
-hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
-                             int nitems, const int* inst_list, int ninst, size_t lds,
-                             hipStream_t s);
+// nitems items + 1 controller launch over the ninst instances of inst_list;
+// smooth: the instances carry the smooth glass field (paper mode)
+hipError_t launch_batch_step(int precision, int model, int smooth, const BatchDesc* desc,
+                             const int2* items, int nitems, const int* inst_list, int ninst,
+                             size_t lds, hipStream_t s);
 // control blocks of the instances in inst_list, gathered into out[ninst]
 // (one device-to-host copy per poll instead of one per instance)
 hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ninst,

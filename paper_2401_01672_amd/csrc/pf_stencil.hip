@@ -765,13 +765,14 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc* desc,
 // listed instance; the host captures a run of attempts into a HIP graph and
 // rebuilds the item table (and the graph) when instances finish.  Same
 // per-cell arithmetic as batch_kernel.
-template <typename R, int MODEL, int STAGE>
+template <typename R, int MODEL, int STAGE, int SMOOTH = 0>
 __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchDesc* desc,
                                                              const int2* items) {
   __shared__ double smem[8 * kWaves];
   extern __shared__ __align__(16) unsigned char pf_stage_lds[];
   const int2 it = items[xcd_tile(blockIdx.x, gridDim.x)];
-  stage4_tile<R, MODEL, STAGE>(desc[it.x].st[STAGE - 1], it.y, it.y, smem, pf_stage_lds);
+  stage4_tile<R, MODEL, STAGE, false, PF_REACT_SIGMA, SMOOTH>(desc[it.x].st[STAGE - 1], it.y,
+                                                              it.y, smem, pf_stage_lds);
 }
 
 __global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc,
@@ -800,34 +801,43 @@ hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ni
   return hipGetLastError();
 }
 
-template <typename R, int MODEL>
+template <typename R, int MODEL, int SMOOTH>
 static hipError_t launch_batch_step_t(const BatchDesc* desc, const int2* items, int nitems,
                                       const int* inst_list, int ninst, size_t lds,
                                       hipStream_t s) {
   const dim3 g((unsigned)nitems), b(kBlock);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1>), g, b, lds, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2>), g, b, lds, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3>), g, b, lds, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4>), g, b, lds, s, desc, items);
-  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1, SMOOTH>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2, SMOOTH>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3, SMOOTH>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4, SMOOTH>), g, b, lds, s, desc, items);
+  hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5, SMOOTH>), g, b, lds, s, desc, items);
   hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc, inst_list);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int precision, int model, const BatchDesc* desc, const int2* items,
-                             int nitems, const int* inst_list, int ninst, size_t lds,
-                             hipStream_t s) {
-  if (precision == PF_FP64)
-    return model == PF_MODEL_AC
-               ? launch_batch_step_t<double, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst,
-                                                         lds, s)
-               : launch_batch_step_t<double, PF_MODEL_COUPLED>(desc, items, nitems, inst_list,
-                                                              ninst, lds, s);
+template <typename R, int SMOOTH>
+static hipError_t launch_batch_step_r(int model, const BatchDesc* desc, const int2* items,
+                                      int nitems, const int* inst_list, int ninst, size_t lds,
+                                      hipStream_t s) {
   return model == PF_MODEL_AC
-             ? launch_batch_step_t<float, PF_MODEL_AC>(desc, items, nitems, inst_list, ninst,
-                                                      lds, s)
-             : launch_batch_step_t<float, PF_MODEL_COUPLED>(desc, items, nitems, inst_list,
-                                                           ninst, lds, s);
+             ? launch_batch_step_t<R, PF_MODEL_AC, SMOOTH>(desc, items, nitems, inst_list, ninst,
+                                                          lds, s)
+             : launch_batch_step_t<R, PF_MODEL_COUPLED, SMOOTH>(desc, items, nitems, inst_list,
+                                                               ninst, lds, s);
+}
+
+hipError_t launch_batch_step(int precision, int model, int smooth, const BatchDesc* desc,
+                             const int2* items, int nitems, const int* inst_list, int ninst,
+                             size_t lds, hipStream_t s) {
+  if (precision == PF_FP64)
+    return smooth ? launch_batch_step_r<double, 1>(model, desc, items, nitems, inst_list, ninst,
+                                                   lds, s)
+                  : launch_batch_step_r<double, 0>(model, desc, items, nitems, inst_list, ninst,
+                                                   lds, s);
+  return smooth ? launch_batch_step_r<float, 1>(model, desc, items, nitems, inst_list, ninst, lds,
+                                                s)
+                : launch_batch_step_r<float, 0>(model, desc, items, nitems, inst_list, ninst, lds,
+                                                s);
 }
 
 template <typename R, int MODEL>

@@ -11,9 +11,12 @@ of the vessel (reduced on the GPU, pf_diagnostics_planes).  The geometry is the 
 ``pf_inputs.case_paper`` (smooth glass field, no phase-field face rule) on a
 synthetic bead bed.
 
-Every run goes through the library (pf_create_field, pf_integrate, FP64 on
-the one-cell kernels: at the 0.12 um scale the right-hand side's FP32
-roundoff alone exceeds the 1e-6 s^-1 equilibrium threshold).
+Every run goes through the library in FP64 (at the 0.12 um scale the
+right-hand side's FP32 roundoff alone exceeds the 1e-6 s^-1 equilibrium
+threshold): by default the supercooling values of one material run together
+as one batch (pf_batch_integrate over pf_create_field handles, one batch per
+phase), or one at a time (pf_integrate, --sequential).  Each phase has its
+own attempt budget.
 
 Run ``python -m paper_2401_01672_amd.uwc_sweep --help``.
 """
@@ -51,29 +54,69 @@ def problem(r_m: float, dT: float, n3: int = 100, seed: int = 5):
     return c
 
 
-def run_one(c, budget: int) -> Dict:
-    """Phase 1 at tol = 1e-6 until max water |d phi/dt| falls below the level
-    that tolerance can resolve (4 lam_max tol); phase 2 at tol_eq down to the
-    1e-6 s^-1 equilibrium threshold."""
+def _eq1(c) -> float:
+    return max(EQ_TOL, 4.0 * c.run["lam_max"] * c.run["tol"])
+
+
+def _solver(c):
     import paper_2401_01672_amd as pf
     s = pf.Solver(c.params, None, "fp64", c.run, glass_field=c.G)
     s.set_state(c.phi0)
     s.set_time(0.0, c.run["dt0"])
-    t0 = time.perf_counter()
-    eq1 = max(EQ_TOL, 4.0 * c.run["lam_max"] * c.run["tol"])
-    st1 = s.integrate(max_steps=budget, eq_tol=eq1, raise_on_error=False)
+    return s
+
+
+def _result(s, st1, st2, wall, c) -> Dict:
     n1 = st1["steps_accepted"] + st1["steps_rejected"]
-    st = st1
-    if st1["status"] == 1 and eq1 > EQ_TOL:
-        s.set_tolerance(c.run["tol_eq"])
-        st = s.integrate(max_steps=budget - n1, eq_tol=EQ_TOL, raise_on_error=False)
-    wall = time.perf_counter() - t0
-    uwc = s.uwc_bottom_half()  # eq. UWC-formula, reduced on the GPU
-    s.close()
-    n2 = st["steps_accepted"] + st["steps_rejected"] if st is not st1 else 0
+    st = st2 if st2 is not None else st1
+    n2 = st2["steps_accepted"] + st2["steps_rejected"] if st2 is not None else 0
     out = dict(status=st["status"], attempts=n1 + n2, attempts_phase1=n1,
                t=st["t"], wall_s=wall, cells=c.ncells)
-    out.update(uwc)
+    out.update(s.uwc_bottom_half())  # eq. UWC-formula, reduced on the GPU
+    return out
+
+
+def run_one(c, budget: int) -> Dict:
+    """Phase 1 at tol = 1e-6 until max water |d phi/dt| falls below the level
+    that tolerance can resolve (4 lam_max tol); phase 2 at tol_eq down to the
+    1e-6 s^-1 equilibrium threshold; each phase within `budget` attempts."""
+    s = _solver(c)
+    t0 = time.perf_counter()
+    eq1 = _eq1(c)
+    st1 = s.integrate(max_steps=budget, eq_tol=eq1, raise_on_error=False)
+    st2 = None
+    if st1["status"] == 1 and eq1 > EQ_TOL:
+        s.set_tolerance(c.run["tol_eq"])
+        st2 = s.integrate(max_steps=budget, eq_tol=EQ_TOL, raise_on_error=False)
+    out = _result(s, st1, st2, time.perf_counter() - t0, c)
+    s.close()
+    return out
+
+
+def run_batch(cases: List, budget: int) -> List[Dict]:
+    """The same two phases for problems of one material (the same eq1) as
+    batches: phase 1 over every problem, phase 2 over those that reached the
+    phase-1 threshold.  wall_s: the whole batch's time."""
+    import paper_2401_01672_amd as pf
+    eq1 = _eq1(cases[0])
+    assert all(_eq1(c) == eq1 for c in cases), "one material per batch"
+    ss = [_solver(c) for c in cases]
+    t0 = time.perf_counter()
+    st1 = pf.batch_integrate(ss, max_steps=budget, eq_tol=eq1, raise_on_error=False)
+    st2 = [None] * len(cases)
+    if eq1 > EQ_TOL:
+        again = [i for i, st in enumerate(st1) if st["status"] == 1]
+        for i in again:
+            ss[i].set_tolerance(cases[i].run["tol_eq"])
+        if again:
+            res2 = pf.batch_integrate([ss[i] for i in again], max_steps=budget, eq_tol=EQ_TOL,
+                                      raise_on_error=False)
+            for i, st in zip(again, res2):
+                st2[i] = st
+    wall = time.perf_counter() - t0
+    out = [_result(s, a, b, wall, c) for s, a, b, c in zip(ss, st1, st2, cases)]
+    for s in ss:
+        s.close()
     return out
 
 
@@ -82,20 +125,29 @@ def main():
     ap.add_argument("--n3", type=int, default=100)
     ap.add_argument("--materials", default="polystyrene,carbon_black")
     ap.add_argument("--dT", default=",".join(str(v) for v in DT_LIST))
-    ap.add_argument("--budget", type=int, default=300000)
+    ap.add_argument("--budget", type=int, default=300000, help="attempts per phase")
+    ap.add_argument("--sequential", action="store_true",
+                    help="one problem at a time instead of one batch per material")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     res: List[Dict] = []
+    wall = 0.0
     for mat in a.materials.split(","):
-        for dT in (float(v) for v in a.dT.split(",")):
-            c = problem(MATERIALS[mat], dT, a.n3)
-            r = dict(material=mat, r_m=MATERIALS[mat], dT=dT, h=c.params["h"], **run_one(c, a.budget))
+        dts = [float(v) for v in a.dT.split(",")]
+        cases = [problem(MATERIALS[mat], dT, a.n3) for dT in dts]
+        if a.sequential:
+            rs = [run_one(c, a.budget) for c in cases]
+            wall += sum(r["wall_s"] for r in rs)
+        else:
+            rs = run_batch(cases, a.budget)
+            wall += rs[0]["wall_s"]
+        for dT, c, r in zip(dts, cases, rs):
+            r = dict(material=mat, r_m=MATERIALS[mat], dT=dT, h=c.params["h"], **r)
             res.append(r)
             print(json.dumps(r), flush=True)
     cells = sum(r["cells"] * r["attempts"] for r in res)
-    wall = sum(r["wall_s"] for r in res)
     summary = dict(runs=len(res), equilibrium=sum(r["status"] == 1 for r in res),
                    gcups=cells / wall / 1e9, wall_s=wall)
     print(json.dumps(summary), flush=True)

@@ -41,3 +41,16 @@ def test_uwc_run_matches_oracle(dT):
     n_o = st1["steps_accepted"] + st1["steps_rejected"] + st["steps_accepted"] + \
         st["steps_rejected"]
     assert abs(gpu["attempts"] - n_o) <= max(2, n_o // 1000)
+
+
+def test_uwc_batch_equals_single_runs():
+    """The sweep's batched form (the supercooling values of one material in one
+    batch per phase, paper-mode glass fields) gives each problem exactly the
+    run it gets alone: the same status, attempts, end time and bottom-half
+    counts."""
+    cases = [U.problem(0.12e-6, dT, n3=40) for dT in (5.0, 2.0, 0.2)]
+    batch = U.run_batch(cases, budget=200000)
+    for c, rb in zip(cases, batch):
+        rs = U.run_one(c, budget=200000)
+        for k in ("status", "attempts", "attempts_phase1", "t", "water_cells", "ice_cells"):
+            assert rb[k] == rs[k], (k, rb[k], rs[k])
