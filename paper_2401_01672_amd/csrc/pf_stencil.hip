@@ -1059,6 +1059,32 @@ __device__ __forceinline__ void stq_s(R* base, uint32_t idx, const Quad<R>& q) {
   else stq_plain(base, idx, q);
 }
 
+// Non-temporal load of quad p of one x1-x2 plane (pb: the plane's first cell,
+// plane bytes < 2^32) through a buffer resource.  Its cache policy is part of
+// the intrinsic, so a pass that loads a field non-temporally in some waves
+// and plainly in others keeps two distinct loads (two plain loads that differ
+// only in a non-temporal hint are merged into one plain load).
+template <typename R>
+__device__ __forceinline__ Quad<R> ldq_plane_nt(const R* pb, uint32_t p, uint32_t plane_bytes) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)pb, 0, (int)plane_bytes, 0x00020000);
+  // cache policy 2: nt
+  const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, p * (uint32_t)sizeof(R), 0, 2);
+  Quad<R> q;
+  if constexpr (sizeof(R) == 4) {
+    const float4 t = __builtin_bit_cast(float4, w);
+    q.v[0] = t.x;
+    q.v[1] = t.y;
+    q.v[2] = t.z;
+    q.v[3] = t.w;
+  } else {
+    const double2 t = __builtin_bit_cast(double2, w);
+    q.v[0] = t.x;
+    q.v[1] = t.y;
+  }
+  return q;
+}
+
 template <typename R>
 __device__ __forceinline__ R shfl_up1(R v) {
   return __shfl_up(v, 1, 64);
@@ -1131,12 +1157,13 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   // raw (when given) receives the loaded k1 (S2) or y, k1, k3 (S4), which the
   // pass needs again at the cell one plane later (kept in registers: a reload
   // misses the L2 on large grids).
-  auto ldin = [&](int v, uint32_t i, Quad<R>* raw) -> Quad<R> {
-    if (SMOOTH && v == NV) return ldq(Gf, i);
+  // LD(field) loads the quad in question of a field.
+  auto ldin_g = [&](int v, auto&& LD, Quad<R>* raw) -> Quad<R> {
+    if (SMOOTH && v == NV) return LD(Gf);
     if constexpr (STAGE == 2 || STAGE == 4) {
-      const Quad<R> y0 = ldq(yv[v], i), q1 = ldq(k1[v], i);
+      const Quad<R> y0 = LD(yv[v]), q1 = LD(k1[v]);
       Quad<R> q3, o;
-      if constexpr (STAGE == 4) q3 = ldq(k3[v], i);
+      if constexpr (STAGE == 4) q3 = LD(k3[v]);
 #pragma unroll
       for (int k = 0; k < VW; ++k) {
         if constexpr (STAGE == 2) o.v[k] = y0.v[k] + rdt * (R(1.0 / 3.0) * q1.v[k]);
@@ -1151,8 +1178,11 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
       }
       return o;
     } else {
-      return ldq(in[v], i);
+      return LD(in[v]);
     }
+  };
+  auto ldin = [&](int v, uint32_t i, Quad<R>* raw) -> Quad<R> {
+    return ldin_g(v, [&](const R* f) { return ldq(f, i); }, raw);
   };
 
   double red0 = 0.0;
@@ -1173,6 +1203,24 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
   const uint32_t i2 = active ? p / (uint32_t)m.n1 : 0u;
   const bool xm_in = i1 > 0, xp_in = i1 + VW < (uint32_t)m.n1;
   const bool ym_in = i2 > 0, yp_in = i2 + 1 < (uint32_t)m.n2;
+  // The first and last Q quads of the run are the x2 halo rows of the
+  // neighbouring runs, read by them too; the quads between are read by this
+  // workgroup alone, once per pass.  On large grids (NT) the waves that hold
+  // only such quads load them non-temporally, which leaves the L2 to the
+  // shared rows.  (Not in S1: the extra registers of the second load path
+  // would cost that ALU-bound pass a wavefront per SIMD.)
+  const uint32_t plane_b = plane * (uint32_t)sizeof(R);
+  const uint32_t w0 = threadIdx.x & ~63u;
+  const bool wave_nt =
+      NT && STAGE != 1 && (uint64_t)plane * sizeof(R) < (1ull << 32) &&
+      __builtin_amdgcn_readfirstlane((int)(w0 >= Q && w0 + 64u + Q <= (uint32_t)kBlock)) != 0;
+  // the stencil input of the thread's own quad in plane zz, at index i (the
+  // x3 window)
+  auto ldc = [&](int v, int zz, uint32_t i, Quad<R>* raw) -> Quad<R> {
+    if (!wave_nt) return ldin(v, i, raw);
+    return ldin_g(v, [&](const R* f) { return ldq_plane_nt(f + plane * (uint32_t)zz, p, plane_b); },
+                  raw);
+  };
   // lanes whose x-neighbour quad lives in another wavefront (read from LDS)
   const bool xm_remote = xm_in && (lane == 0);
   const bool xp_remote = xp_in && (lane == 63 || p + VW >= plane);
@@ -1215,11 +1263,11 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     codes_nx = ld_codes(n);
 #pragma unroll
     for (int v = 0; v < NL; ++v) {
-      cc[v] = ldin(v, n, rc[v]);
-      cm[v] = z0 > 0 ? ldin(v, n - plane, nullptr) : cc[v];
+      cc[v] = ldc(v, z0, n, rc[v]);
+      cm[v] = z0 > 0 ? ldc(v, z0 - 1, n - plane, nullptr) : cc[v];
       if constexpr (kDeep) {
         cp[v] = cc[v];
-        if (z0 + 1 < m.n3) cp[v] = ldin(v, n + plane, nullptr);
+        if (z0 + 1 < m.n3) cp[v] = ldc(v, z0 + 1, n + plane, nullptr);
       }
     }
   }
@@ -1234,9 +1282,9 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
 #pragma unroll
       for (int v = 0; v < NL; ++v) {
         if constexpr (kDeep) {
-          if (z + 2 < m.n3 && z + 1 < z1) cn[v] = ldin(v, n + 2u * plane, nullptr);
+          if (z + 2 < m.n3 && z + 1 < z1) cn[v] = ldc(v, z + 2, n + 2u * plane, nullptr);
         } else {
-          cp[v] = zp_in ? ldin(v, n + plane, rp[v]) : cc[v];
+          cp[v] = zp_in ? ldc(v, z + 1, n + plane, rp[v]) : cc[v];
         }
         L[v * W + Q + t] = cc[v];
       }
