@@ -18,6 +18,7 @@ them:
 import json
 import math
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -107,7 +108,7 @@ def _tiny_params(model, shape, rng, faces=0, bc_kind=0):
 @pytest.mark.parametrize("model", ["ac", "coupled"])
 @pytest.mark.parametrize("shape", [(3, 3, 3), (4, 3, 5), (5, 4, 2), (1, 1, 6)])
 def test_rhs_matches_brute_force(model, shape):
-    rng = np.random.default_rng(hash((model, shape)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(f"{model}-{shape}".encode()))
     for trial in range(3):
         faces = int(rng.integers(0, 64))
         p = _tiny_params(model, shape, rng, faces=faces, bc_kind=int(rng.integers(0, 3)))
@@ -452,7 +453,7 @@ def test_gibbs_thomson_critical_radius():
 def test_rhs_variants_match_brute_force(model, reaction, shape):
     """GradP reaction (eq. reaction-term-GradP) and the Temp model (Sec. 2.3)
     against the dense transcription."""
-    rng = np.random.default_rng(hash((model, reaction, shape)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(f"{model}-{reaction}-{shape}".encode()))
     for trial in range(3):
         p = _tiny_params(model, shape, rng, faces=int(rng.integers(0, 64)),
                          bc_kind=int(rng.integers(0, 3)))
@@ -469,7 +470,10 @@ def test_rhs_variants_match_brute_force(model, reaction, shape):
         else:
             kp, kT = oracle.rhs(P, G, t, phi, T if model == "coupled" else None)
         bp, bT = brute.rhs(p, G, t, phi, T)
-        assert np.abs(kp - bp).max() <= 1e-13 * max(np.abs(bp).max(), 1e-300)
+        # Temp model: the phase rate carries varphi'(T), whose 1 - tanh^2 the
+        # two implementations evaluate differently (~1e-12 relative)
+        tol_p = 1e-11 if model == "temp" else 1e-13
+        assert np.abs(kp - bp).max() <= tol_p * max(np.abs(bp).max(), 1e-300)
         if model != "ac":
             assert np.abs(kT - bT).max() <= 1e-13 * np.abs(bT).max()
 
@@ -518,7 +522,7 @@ def test_rhs_smooth_glass_matches_brute_force(model, reaction):
     """Paper mode (Sec. 2.1): a smooth glass field G in [0, 1], the
     phase-field Laplacian across every face, I_W(G) and the blends with
     fractional G."""
-    rng = np.random.default_rng(hash((model, reaction, "smooth")) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(f"{model}-{reaction}-smooth".encode()))
     for shape in ((3, 4, 5), (2, 3, 6)):
         p = _tiny_params(model, shape, rng, faces=int(rng.integers(0, 64)),
                          bc_kind=int(rng.integers(0, 3)))
@@ -535,7 +539,10 @@ def test_rhs_smooth_glass_matches_brute_force(model, reaction):
         else:
             kp, kT = oracle.rhs(P, G, t, phi, T if model == "coupled" else None)
         bp, bT = brute.rhs(p, G, t, phi, T)
-        assert np.abs(kp - bp).max() <= 1e-13 * max(np.abs(bp).max(), 1e-300)
+        # Temp model: the phase rate carries varphi'(T), whose 1 - tanh^2 the
+        # two implementations evaluate differently (~1e-12 relative)
+        tol_p = 1e-11 if model == "temp" else 1e-13
+        assert np.abs(kp - bp).max() <= tol_p * max(np.abs(bp).max(), 1e-300)
         if model != "ac":
             assert np.abs(kT - bT).max() <= 1e-13 * np.abs(bT).max()
 
