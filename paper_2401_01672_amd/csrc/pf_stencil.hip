@@ -113,16 +113,30 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&ops)[N
 // ---------------------------------------------------------------------------
 // Right-hand side of one cell.
 
-// x if bit f of code is set, else +0: the sign-extended bit (one bit-field
-// extract) used as an and-mask, with no compare/select.
-__device__ __forceinline__ int bit_mask(unsigned code, int f) {
-  return __builtin_amdgcn_sbfe((int)code, (unsigned)f, 1u);
+// Bit f of code as 0 or 1 in the field precision: a face weight that enters
+// the Laplacian through a fused multiply-add (lap + w d is lap + d rounded
+// once for w = 1 and exactly lap for w = 0): bit extract, convert and fma
+// where a compare and a select would take one more instruction.
+template <typename R>
+__device__ __forceinline__ R face_weight(unsigned code, int f) {
+  return R((code >> f) & 1u);
 }
-__device__ __forceinline__ float keep_if_mask(int msk, float x) {
+
+// FP32: bit f of code as an all-ones or all-zeros word, used as an and-mask
+// (keep_if: x or +0) and a bitwise select (pick: v_bfi_b32), so that one bit
+// extract serves the Laplacian and the conductivity of a face.  The empty asm
+// hides that the word is a sign-extended bit: the compiler would otherwise
+// turn each use back into a compare and a select.
+__device__ __forceinline__ int face_mask(unsigned code, int f) {
+  int msk = __builtin_amdgcn_sbfe((int)code, (unsigned)f, 1u);
+  asm("" : "+v"(msk));
+  return msk;
+}
+__device__ __forceinline__ float keep_if(int msk, float x) {
   return __int_as_float(__float_as_int(x) & msk);
 }
-__device__ __forceinline__ double keep_if_mask(int msk, double x) {
-  return __longlong_as_double(__double_as_longlong(x) & (long long)msk);
+__device__ __forceinline__ float pick(int msk, float a, float b) {
+  return __int_as_float((__float_as_int(a) & msk) | (__float_as_int(b) & ~msk));
 }
 
 // Sigma limiter with the clamp as one med3 (FP32); s = w inv - e0 inv.
@@ -183,17 +197,37 @@ struct CellRHS {
   // phn/thn: neighbour values through faces 0..5.  Precondition: for a face
   // on the domain boundary thn[f] == thc (the caller passes the cell's own
   // value), so an insulated face contributes exactly zero with no select;
-  // the Dirichlet faces (dirf) among the boundary faces (bits of ~inb) add
+  // the nd Dirichlet faces among the boundary faces add
   // 2 lambda_c (2 theta_D - theta_c - theta_c) each.  Bit f of code: the
   // neighbour through face f exists and is water.
-  __device__ __forceinline__ static void eval(const ModelConst& m, R phic, R thc,
-                                              const R (&phn)[6], const R (&thn)[6],
-                                              unsigned code, unsigned inb, unsigned dirf,
-                                              R thD, R& kphi, R& kth) {
+  __device__ __forceinline__ static void eval_nd(const ModelConst& m, R phic, R thc,
+                                                 const R (&phn)[6], const R (&thn)[6],
+                                                 unsigned code, unsigned nd, R thD, R& kphi,
+                                                 R& kth) {
     const bool glass = code & kGlassBit;
-    R lap = R(0);
+    const R lamc = glass ? R(m.lamG) : R(m.lamL) + phic * R(m.dlam);
+    R lap = R(0), qq = R(0);
+    if constexpr (sizeof(R) == 4) {
 #pragma unroll
-    for (int f = 0; f < 6; ++f) lap += keep_if_mask(bit_mask(code, f), phn[f] - phic);
+      for (int f = 0; f < 6; ++f) {
+        const int msk = face_mask(code, f);
+        lap += keep_if(msk, phn[f] - phic);
+        if (MODEL == PF_MODEL_COUPLED) {
+          const R lamn = pick(msk, R(m.lamL) + phn[f] * R(m.dlam), R(m.lamG));
+          qq += (lamc + lamn) * (thn[f] - thc);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < 6; ++f) lap += face_weight<R>(code, f) * (phn[f] - phic);
+      if (MODEL == PF_MODEL_COUPLED) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const R lamn = ((code >> f) & 1u) ? R(m.lamL) + phn[f] * R(m.dlam) : R(m.lamG);
+          qq += (lamc + lamn) * (thn[f] - thc);
+        }
+      }
+    }
     R f;
     if (REACT == PF_REACT_GRADP) {
       // eq. reaction-term-GradP: 2 phi (1 - phi)(phi - 1/2) + xi^2 mu alpha |grad phi| (T* - T)
@@ -209,21 +243,22 @@ struct CellRHS {
     // glass: no phase-field flux and the water indicator of glass
     kphi = glass ? R(m.iw_glass) * (R(m.cR) * f) : R(m.cL) * lap + R(m.cR) * f;
     if (MODEL == PF_MODEL_COUPLED) {
-      const R lamc = glass ? R(m.lamG) : R(m.lamL) + phic * R(m.dlam);
-      R qq = R(0);
-#pragma unroll
-      for (int f = 0; f < 6; ++f) {
-        const R lamn = ((code >> f) & 1u) ? R(m.lamL) + phn[f] * R(m.dlam) : R(m.lamG);
-        qq += (lamc + lamn) * (thn[f] - thc);
-      }
-      const unsigned nd = __builtin_popcount(~inb & dirf & 63u);
-      if (nd) qq += R(4 * (int)nd) * lamc * (thD - thc);
+      // nd = 0: the term is an exact zero
+      qq += R(4 * (int)nd) * lamc * (thD - thc);
       R rc, lat;
       heat_capacity_mask(m, glass, phic, rc, lat);
       kth = div_fast(R(0.5) * R(m.cH) * qq + lat * kphi, rc);
     } else {
       kth = R(0);
     }
+  }
+  // inb: bit f set where face f is inside the domain; dirf: the Dirichlet
+  // faces of the domain
+  __device__ __forceinline__ static void eval(const ModelConst& m, R phic, R thc,
+                                              const R (&phn)[6], const R (&thn)[6],
+                                              unsigned code, unsigned inb, unsigned dirf,
+                                              R thD, R& kphi, R& kth) {
+    eval_nd(m, phic, thc, phn, thn, code, __builtin_popcount(~inb & dirf & 63u), thD, kphi, kth);
   }
 };
 
@@ -1327,6 +1362,8 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     if (active) {
       const unsigned inb_c = (ym_in ? 4u : 0u) | (yp_in ? 8u : 0u) | (z > 0 ? 16u : 0u) |
                              (zp_in ? 32u : 0u);
+      // Dirichlet faces on the x2 and x3 sides, shared by the quad's cells
+      const unsigned nd_c = __builtin_popcount(~inb_c & dirf & 60u);
       Quad<R> kq[2];
 #pragma unroll
       for (int k = 0; k < VW; ++k) {
@@ -1368,16 +1405,28 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
           else
             CellRHSSmooth<R, MODEL, REACT>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0),
                                                  phn, thn, Gc, Gn, inb, dirf, thD, kp, kt);
-        } else {
+        } else if constexpr (MODEL == PF_MODEL_TEMP) {
           // Temp model: the single unknown (theta) travels in the first slot
-          CellRHS<R, MODEL, REACT>::eval(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn, thn,
-                                         code, inb, dirf, thD, kp, kt);
+          CellRHS<R, MODEL, REACT>::eval(m, cc[0].v[k], R(0), phn, thn, code, inb, dirf, thD, kp,
+                                         kt);
+        } else {
+          const unsigned nd = nd_c + ((k == 0 && !xm_in) ? (dirf & 1u) : 0u) +
+                              ((k == VW - 1 && !xp_in) ? ((dirf >> 1) & 1u) : 0u);
+          CellRHS<R, MODEL, REACT>::eval_nd(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn,
+                                            thn, code, nd, thD, kp, kt);
         }
+        // pin the cell's results here: otherwise parts of the update are sunk
+        // towards the stores after the quad, where the face masks of all four
+        // cells would be live at once
+        asm volatile("" : "+v"(kp), "+v"(kt));
         kq[0].v[k] = kp;
         kq[1].v[k] = kt;
         // equilibrium measure (no phase-field equation in the Temp model)
         if (STAGE == 1 && MODEL != PF_MODEL_TEMP && !(code & kGlassBit))
           red1 = dmax_nf(red1, fabs(kp));
+        // one cell at a time: the pass is ALU-bound with several waves per
+        // SIMD, and interleaving the cells only raises register pressure
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
