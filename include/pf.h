@@ -273,7 +273,11 @@ int pf_diagnostics(pf_handle* h, pf_run_stats* stats);
 int pf_diagnostics_planes(pf_handle* h, int32_t i3_lo, int32_t i3_hi, pf_run_stats* stats);
 
 /* Step-loop options: steps_per_poll attempts are issued between host polls;
- * use_graph = 1 captures them once into a HIP graph and replays it. */
+ * use_graph = 1 captures them once into a HIP graph and replays it.  A
+ * pf_integrate call with the equilibrium test (eq_tol > 0) polls after 1, 2,
+ * 4, ... attempts, launched directly, until the interval reaches
+ * steps_per_poll (a run that starts at or near equilibrium then ends after
+ * a few attempts and builds no graph). */
 int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph);
 
 /* Tile shape of the stencil kernels: z_chunk = planes per workgroup column

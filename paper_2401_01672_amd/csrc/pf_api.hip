@@ -1031,11 +1031,19 @@ int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
   }
   int rc = push_ctl(h);
   if (rc) return rc;
+  // A run with the equilibrium test may end after very few attempts (a warm
+  // start at or near equilibrium): its poll interval starts at one attempt and
+  // doubles up to steps_per_poll, launched directly, and the graph is built
+  // only once the interval is full (instantiating it costs about as much as
+  // two dozen directly launched attempts).  Fixed-horizon runs poll every
+  // steps_per_poll attempts from the start.
+  int poll = c.eq_tol > 0.0 ? 1 : h->steps_per_poll;
   while (!c.done) {
     // attempts left in the budget: a shorter tail is launched directly, so a
     // run issues exactly the attempts it makes (no trailing no-op attempts)
     const long long left = c.max_steps - (c.n_acc + c.n_rej);
-    const int nissue = left < h->steps_per_poll ? (int)left : h->steps_per_poll;
+    const int nissue = left < poll ? (int)left : poll;
+    if (poll < h->steps_per_poll) poll = 2 * poll < h->steps_per_poll ? 2 * poll : h->steps_per_poll;
     if (h->use_graph && nissue == h->steps_per_poll) {
       if (!h->gexec || h->graph_steps != h->steps_per_poll) {
         drop_graph(h);

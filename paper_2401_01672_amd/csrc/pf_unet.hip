@@ -188,6 +188,7 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
   const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
   const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
   (void)tiles_z;
+  const int mb = blockIdx.y * MT;  // first 16-channel output group of this workgroup
 
   f32x4 acc[MT][4];
 #pragma unroll
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
       const int kw = (tap < 27 ? tap : 26) * a.cin + c * CC + cig;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        const bf16x8 afrag = ld8(a.w + (long long)(m * 16 + r) * a.kpad + kw);
+        const bf16x8 afrag = ld8(a.w + (long long)((mb + m) * 16 + r) * a.kpad + kw);
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[m][t] = mfma16(afrag, bfrag[t], acc[m][t]);
       }
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
     const long long v = ((long long)z * a.n2 + y) * a.n1 + x;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      const int co = m * 16 + 4 * g;
+      const int co = (mb + m) * 16 + 4 * g;
       uint16_t o[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -604,6 +605,53 @@ __global__ void pool_bwd_kernel(const uint16_t* dout, int dout_stride, int dout_
   *dst = f2bf(g);
 }
 
+// Vector forms of 2x average pooling and nearest upsampling: one thread per
+// voxel and group of 8 channels (16 bytes), 32-bit index arithmetic (grids
+// below 2^24 voxels).  Per channel the same sums in the same order as the
+// one-element kernels, so the results are bitwise the same.
+__device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+
+__global__ void pool_fwd8_kernel(const uint16_t* in, int in_stride, int in_off, uint16_t* out,
+                                 int out_stride, int out_off, int c8, int m1, int m2,
+                                 unsigned total) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const unsigned v = i / (unsigned)c8, g = i - v * (unsigned)c8;
+  const unsigned x = v % (unsigned)m1, t = v / (unsigned)m1;
+  const unsigned y = t % (unsigned)m2, z = t / (unsigned)m2;
+  const unsigned n1 = 2u * m1, n2 = 2u * m2;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int d = 0; d < 8; ++d) {
+    const unsigned src = ((2u * z + (d >> 2)) * n2 + (2u * y + ((d >> 1) & 1))) * n1 + (2u * x + (d & 1));
+    const uint4 q = ld16(in + (size_t)src * in_stride + in_off + 8 * g);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      acc[2 * k] += bf2f((uint16_t)(w[k] & 0xffffu));
+      acc[2 * k + 1] += bf2f((uint16_t)(w[k] >> 16));
+    }
+  }
+  uint32_t o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    o[k] = (uint32_t)f2bf(0.125f * acc[2 * k]) | ((uint32_t)f2bf(0.125f * acc[2 * k + 1]) << 16);
+  *reinterpret_cast<uint4*>(out + (size_t)v * out_stride + out_off + 8 * g) =
+      make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+__global__ void up_fwd8_kernel(const uint16_t* in, int in_stride, int in_off, uint16_t* out,
+                               int out_stride, int out_off, int c8, int n1, int n2,
+                               unsigned total) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const unsigned v = i / (unsigned)c8, g = i - v * (unsigned)c8;
+  const unsigned x = v % (unsigned)n1, t = v / (unsigned)n1;
+  const unsigned y = t % (unsigned)n2, z = t / (unsigned)n2;
+  const unsigned p = ((z >> 1) * ((unsigned)n2 >> 1) + (y >> 1)) * ((unsigned)n1 >> 1) + (x >> 1);
+  *reinterpret_cast<uint4*>(out + (size_t)v * out_stride + out_off + 8 * g) =
+      ld16(in + (size_t)p * in_stride + in_off + 8 * g);
+}
+
 // nearest 2x upsampling (output grid n = 2 m)
 __global__ void up_fwd_kernel(const uint16_t* in, int in_stride, int in_off, uint16_t* out,
                               int out_stride, int out_off, int c, int n1, int n2, int n3) {
@@ -779,15 +827,6 @@ __global__ void bf16_to_f32_kernel(const uint16_t* in, float* out, long long n) 
 // a fixed point of the reaction term), so ice can only appear in the
 // components that contain the initial nucleus.
 
-__global__ void reach_seed_kernel(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
-                                  long long n) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const double p = fp64 ? static_cast<const double*>(phi)[v]
-                        : (double)static_cast<const float*>(phi)[v];
-  reach[v] = (!(code[v] & 0x40u) && p > 0.5) ? 1 : 0;
-}
-
 // No-network baseline of the warm start: phi = 1 on the reached cells (the
 // nucleus's water component), 0 elsewhere.
 __global__ void flood_kernel(const uint8_t* reach, void* out, int fp64, long long n) {
@@ -799,112 +838,171 @@ __global__ void flood_kernel(const uint8_t* reach, void* out, int fp64, long lon
     static_cast<float*>(out)[v] = reach[v] ? 1.0f : 0.0f;
 }
 
-// Sweep: a water cell joins when a face neighbour across a water-water face
-// has joined.  A workgroup loads a 16^3 block of reach flags with a one-cell
-// halo (and the block's cell codes) into LDS and closes the block: rounds of
-// three line passes, one per axis, in which each thread scans one line of 16
-// cells forward and backward and marks every cell of a run of open faces
-// that touches a joined cell (so a straight stretch of pore is crossed in one
-// pass, and a path is crossed in as many rounds as it turns), until a round
-// changes nothing.  Blocks exchange the front through the halo on the next
-// launch.  Every productive round marks at least one of the block's 4096
-// cells, which bounds the loop.
-constexpr int kRB = 16, kRH = kRB + 2;
+// Connected components of the water cells by union-find (face neighbours
+// joined across water-water faces, bits 0..5 of the cell code), in two
+// levels.  A workgroup first labels the components inside its 16^3 tile with
+// a union-find in LDS and writes, for every cell, the global index of its
+// tile-local root (so every tree in lab is flat at first).  A second kernel
+// then unites only across tile faces, in global memory.  lab[v] is v's parent
+// and a root has lab[v] == v; a link always hangs the root with the larger
+// index under the one with the smaller index, and a find replaces a cell's
+// parent by its grandparent as it climbs, so lab[v] <= v holds throughout:
+// every path descends in index and every find ends.  A failed link means
+// another thread linked that root first, so the retries of a union are
+// bounded by the links made meanwhile (no thread waits on another).
+//
+// The links are agent-scope compare-and-swaps.  The finds of the merge read
+// lab through the caches, which may return an older value of an entry: an
+// older parent is still an ancestor (parents only ever move up), and an entry
+// read as a root that has been linked meanwhile fails the compare-and-swap,
+// whose result is the current parent, from which the union goes on upwards.
+// Reading every step from memory instead (the XCDs' L2s are not coherent
+// with each other) made each step a memory round trip: a single-level
+// union-find over all 3 n faces took 319 us at 96^3.  The kernels after the
+// merge read lab with agent-scope loads.
+constexpr int kUT = 16;  // tile edge of the local labelling
 
-// one line of the block: cells h0 + i*hs (halo index) with codes c0 + i*cs;
-// bm / bp: the code bits of the faces towards -axis / +axis
-__device__ __forceinline__ bool reach_line(uint8_t* sr, const uint8_t* sc, int h0, int hs,
-                                           int c0, int cs, unsigned bm, unsigned bp) {
-  bool changed = false;
-  bool carry = sr[h0 - hs] != 0;  // the halo cell before the line
-  for (int i = 0; i < kRB; ++i) {
-    const unsigned c = sc[c0 + i * cs];
-    uint8_t& f = sr[h0 + i * hs];
-    if (c & 0x40u) {
-      carry = false;
-      continue;
-    }
-    if (!f && carry && (c & bm)) {
-      f = 1;
-      changed = true;
-    }
-    carry = f != 0;
-  }
-  carry = sr[h0 + kRB * hs] != 0;  // the halo cell after the line
-  for (int i = kRB - 1; i >= 0; --i) {
-    const unsigned c = sc[c0 + i * cs];
-    uint8_t& f = sr[h0 + i * hs];
-    if (c & 0x40u) {
-      carry = false;
-      continue;
-    }
-    if (!f && carry && (c & bp)) {
-      f = 1;
-      changed = true;
-    }
-    carry = f != 0;
-  }
-  return changed;
+__device__ __forceinline__ int uf_load(const int* lab, int x) {
+  return __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(256) void reach_block_kernel(const uint8_t* code, uint8_t* reach,
-                                                          int n1, int n2, int n3, int bx, int by,
-                                                          int* changed) {
-  __shared__ uint8_t sr[kRH * kRH * kRH];
-  __shared__ uint8_t sc[kRB * kRB * kRB];
-  __shared__ int flag, any;
-  const int tid = threadIdx.x;
+// CACHED: plain loads and stores (the merge); else agent-scope ones
+template <bool CACHED>
+__device__ __forceinline__ int uf_find(int* lab, int x) {
+  for (;;) {
+    const int p = CACHED ? lab[x] : uf_load(lab, x);
+    if (p == x) return x;
+    const int g = CACHED ? lab[p] : uf_load(lab, p);
+    if (g == p) return p;
+    if (CACHED) lab[x] = g;
+    else __hip_atomic_store(lab + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = g;
+  }
+}
+
+__device__ __forceinline__ void uf_union(int* lab, int a, int b) {
+  a = uf_find<true>(lab, a);
+  b = uf_find<true>(lab, b);
+  while (a != b) {
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    int expected = b;
+    if (__hip_atomic_compare_exchange_strong(lab + b, &expected, a, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return;
+    // b was linked meanwhile: continue from its new parent
+    b = uf_find<true>(lab, expected);
+    a = uf_find<true>(lab, a);
+  }
+}
+
+// the same in LDS, on tile-local indices (workgroup scope)
+__device__ __forceinline__ int lf_find(int* ll, int x) {
+  for (;;) {
+    const int p = __hip_atomic_load(ll + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (p == x) return x;
+    const int g = __hip_atomic_load(ll + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (g == p) return p;
+    __hip_atomic_store(ll + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    x = g;
+  }
+}
+
+__device__ __forceinline__ void lf_union(int* ll, int a, int b) {
+  a = lf_find(ll, a);
+  b = lf_find(ll, b);
+  while (a != b) {
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    int expected = b;
+    if (__hip_atomic_compare_exchange_strong(ll + b, &expected, a, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+    b = lf_find(ll, expected);
+    a = lf_find(ll, a);
+  }
+}
+
+// Level 1: the components inside each 16^3 tile (cells outside the grid
+// count as glass); lab = global index of the cell's tile-local root, and no
+// cell reached yet.
+__global__ __launch_bounds__(1024) void reach_local_kernel(const uint8_t* code, int* lab,
+                                                          uint8_t* reach, int n1, int n2, int n3,
+                                                          int tx, int ty) {
+  constexpr int T = kUT * kUT * kUT;
+  __shared__ int ll[T];
+  __shared__ uint8_t sc[T];
   const int b = blockIdx.x;
-  const int x0 = (b % bx) * kRB, y0 = ((b / bx) % by) * kRB, z0 = (b / (bx * by)) * kRB;
+  const int x0 = (b % tx) * kUT, y0 = ((b / tx) % ty) * kUT, z0 = (b / (tx * ty)) * kUT;
   const long long pl = (long long)n1 * n2;
-  for (int i = tid; i < kRH * kRH * kRH; i += 256) {
-    const int hx = i % kRH, hy = (i / kRH) % kRH, hz = i / (kRH * kRH);
-    const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-    uint8_t v = 0;
-    if (x >= 0 && x < n1 && y >= 0 && y < n2 && z >= 0 && z < n3) v = reach[z * pl + (long long)y * n1 + x];
-    sr[i] = v;
-  }
-  for (int i = tid; i < kRB * kRB * kRB; i += 256) {
-    const int lx = i % kRB, ly = (i / kRB) % kRB, lz = i / (kRB * kRB);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    // cells outside the grid behave as glass (never join, never spread)
-    sc[i] = (x < n1 && y < n2 && z < n3) ? code[z * pl + (long long)y * n1 + x] : (uint8_t)0x40u;
-  }
-  if (tid == 0) any = 0;
-  // thread -> the line through (u, w) of the two other axes
-  const int u = tid % kRB, w = tid / kRB;
-  for (int round = 0; round <= kRB * kRB * kRB; ++round) {
-    if (tid == 0) flag = 0;
-    __syncthreads();
-    bool ch = false;
-    // x lines (y = u, z = w)
-    ch |= reach_line(sr, sc, ((w + 1) * kRH + (u + 1)) * kRH + 1, 1, (w * kRB + u) * kRB, 1,
-                     1u, 2u);
-    __syncthreads();
-    // y lines (x = u, z = w)
-    ch |= reach_line(sr, sc, ((w + 1) * kRH + 1) * kRH + (u + 1), kRH, w * kRB * kRB + u, kRB,
-                     4u, 8u);
-    __syncthreads();
-    // z lines (x = u, y = w)
-    ch |= reach_line(sr, sc, (kRH + (w + 1)) * kRH + (u + 1), kRH * kRH, w * kRB + u,
-                     kRB * kRB, 16u, 32u);
-    if (ch) flag = 1;
-    __syncthreads();
-    const int f = flag;
-    __syncthreads();
-    if (!f) break;
-    if (tid == 0) any = 1;
+  for (int i = threadIdx.x; i < T; i += 1024) {
+    const int x = x0 + (i % kUT), y = y0 + (i / kUT) % kUT, z = z0 + i / (kUT * kUT);
+    const bool in = x < n1 && y < n2 && z < n3;
+    sc[i] = in ? code[z * pl + (long long)y * n1 + x] : (uint8_t)0x40u;
+    ll[i] = i;
   }
   __syncthreads();
-  if (!any) return;
-  for (int i = tid; i < kRB * kRB * kRB; i += 256) {
-    const int lx = i % kRB, ly = (i / kRB) % kRB, lz = i / (kRB * kRB);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    if (x >= n1 || y >= n2 || z >= n3) continue;
-    const int h = ((lz + 1) * kRH + (ly + 1)) * kRH + (lx + 1);
-    if (sr[h]) reach[z * pl + (long long)y * n1 + x] = 1;
+  for (int i = threadIdx.x; i < T; i += 1024) {
+    const unsigned c = sc[i];
+    if (c & 0x40u) continue;
+    const int lx = i % kUT, ly = (i / kUT) % kUT, lz = i / (kUT * kUT);
+    if ((c & 2u) && lx + 1 < kUT) lf_union(ll, i, i + 1);
+    if ((c & 8u) && ly + 1 < kUT) lf_union(ll, i, i + kUT);
+    if ((c & 32u) && lz + 1 < kUT) lf_union(ll, i, i + kUT * kUT);
   }
-  if (tid == 0) atomicOr(changed, 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < T; i += 1024) {
+    const int x = x0 + (i % kUT), y = y0 + (i / kUT) % kUT, z = z0 + i / (kUT * kUT);
+    if (x >= n1 || y >= n2 || z >= n3) continue;
+    const int r = lf_find(ll, i);
+    const long long v = z * pl + (long long)y * n1 + x;
+    lab[v] = (int)((z0 + r / (kUT * kUT)) * pl + (long long)(y0 + (r / kUT) % kUT) * n1 +
+                   (x0 + r % kUT));
+    reach[v] = 0;
+  }
+}
+
+// Level 2: water cells on the +x1, +x2, +x3 face of their tile unite with
+// their water neighbour in the next tile.
+__global__ void reach_merge_kernel(const uint8_t* code, int* lab, int n1, int n2, long long n) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const long long pl = (long long)n1 * n2;
+  const unsigned u = (unsigned)v, t = u / (unsigned)n1;  // n < 2^31
+  const unsigned x = u - t * (unsigned)n1, y = t % (unsigned)n2, z = t / (unsigned)n2;
+  const bool ex = x % kUT == kUT - 1, ey = y % kUT == kUT - 1, ez = z % kUT == kUT - 1;
+  if (!(ex || ey || ez)) return;
+  const unsigned c = code[v];
+  if (c & 0x40u) return;
+  if (ex && (c & 2u)) uf_union(lab, (int)v, (int)(v + 1));
+  if (ey && (c & 8u)) uf_union(lab, (int)v, (int)(v + n1));
+  if (ez && (c & 32u)) uf_union(lab, (int)v, (int)(v + pl));
+}
+
+// the components of the nucleus (water cells with phi > 1/2): flag at the root
+__global__ void reach_seed_kernel(const uint8_t* code, const void* phi, int fp64, int* lab,
+                                  uint8_t* reach, long long n) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double p = fp64 ? static_cast<const double*>(phi)[v]
+                        : (double)static_cast<const float*>(phi)[v];
+  if (!(code[v] & 0x40u) && p > 0.5) reach[uf_find<false>(lab, (int)v)] = 1;
+}
+
+// every water cell takes its root's flag (a root keeps its own; the flags of
+// non-root cells are read by no one)
+__global__ void reach_resolve_kernel(const uint8_t* code, int* lab, uint8_t* reach, long long n) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (code[v] & 0x40u) return;
+  const int r = uf_find<false>(lab, (int)v);
+  if (r != (int)v) reach[v] = reach[r];
 }
 
 __global__ void clear_int_kernel(int* p) { *p = 0; }
@@ -914,11 +1012,30 @@ __global__ void clear_int_kernel(int* p) { *p = 0; }
 
 static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+constexpr long long kSplitBelow = 256;  // workgroups: one per CU
+
 template <int CC>
 static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
   const int tx = (a.n1 + kTX - 1) / kTX, ty = (a.n2 + kTY - 1) / kTY, tz = (a.n3 + kTZ - 1) / kTZ;
-  const dim3 grid((unsigned)(tx * ty * tz)), block(256);
-  switch (a.cout / 16) {
+  // Output channels per workgroup: all of them, unless the grid then has
+  // fewer workgroups than the chip has CUs (the coarsest level of the
+  // network); then the most 16-channel groups per workgroup that still give
+  // one workgroup per CU, else one group, with the groups over gridDim.y
+  // (each workgroup stages the same input block; such small grids stay in
+  // the L2).
+  const long long tiles = (long long)tx * ty * tz;
+  const int groups = a.cout / 16;
+  int mt = groups;
+  if (tiles < kSplitBelow) {
+    mt = 1;
+    for (int d = groups; d > 1; --d)
+      if (groups % d == 0 && tiles * (groups / d) >= kSplitBelow) {
+        mt = d;
+        break;
+      }
+  }
+  const dim3 grid((unsigned)tiles, (unsigned)(groups / mt)), block(256);
+  switch (mt) {
     case 1: hipLaunchKernelGGL((conv3_tile_kernel<1, CC>), grid, block, 0, s, a, tx, ty, tz); break;
     case 2: hipLaunchKernelGGL((conv3_tile_kernel<2, CC>), grid, block, 0, s, a, tx, ty, tz); break;
     case 3: hipLaunchKernelGGL((conv3_tile_kernel<3, CC>), grid, block, 0, s, a, tx, ty, tz); break;
@@ -1028,6 +1145,13 @@ hipError_t launch_pool_fwd(const View& in, const View& out, int c, int m1, int m
                            hipStream_t s) {
   const long long n = (long long)m1 * m2 * m3 * c;
   if (n == 0) return hipSuccess;
+  if (c % 8 == 0 && in.stride % 8 == 0 && in.off % 8 == 0 && out.stride % 8 == 0 &&
+      out.off % 8 == 0 && n < (1LL << 32)) {
+    const unsigned total = (unsigned)(n / 8);
+    hipLaunchKernelGGL(pool_fwd8_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, in.p,
+                       in.stride, in.off, out.p, out.stride, out.off, c / 8, m1, m2, total);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(pool_fwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in.p, in.stride,
                      in.off, out.p, out.stride, out.off, c, m1, m2, m3);
   return hipGetLastError();
@@ -1046,6 +1170,13 @@ hipError_t launch_up_fwd(const View& in, const View& out, int c, int n1, int n2,
                          hipStream_t s) {
   const long long n = (long long)n1 * n2 * n3 * c;
   if (n == 0) return hipSuccess;
+  if (c % 8 == 0 && in.stride % 8 == 0 && in.off % 8 == 0 && out.stride % 8 == 0 &&
+      out.off % 8 == 0 && n < (1LL << 32)) {
+    const unsigned total = (unsigned)(n / 8);
+    hipLaunchKernelGGL(up_fwd8_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, in.p,
+                       in.stride, in.off, out.p, out.stride, out.off, c / 8, n1, n2, total);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(up_fwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in.p, in.stride,
                      in.off, out.p, out.stride, out.off, c, n1, n2, n3);
   return hipGetLastError();
@@ -1119,29 +1250,24 @@ hipError_t launch_bf16_to_f32(const uint16_t* in, float* out, long long n, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_reach_seed(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
-                             long long n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(reach_seed_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, code, phi, fp64,
-                     reach, n);
-  return hipGetLastError();
-}
-
 hipError_t launch_flood(const uint8_t* reach, void* out, int fp64, long long n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(flood_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, reach, out, fp64, n);
   return hipGetLastError();
 }
 
-hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
-                               int sweeps, int* changed, hipStream_t s) {
+hipError_t launch_reach(const uint8_t* code, const void* phi, int fp64, int* lab, uint8_t* reach,
+                        int n1, int n2, int n3, hipStream_t s) {
   const long long n = (long long)n1 * n2 * n3;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(1), 0, s, changed);
-  const int bx = (n1 + kRB - 1) / kRB, by = (n2 + kRB - 1) / kRB, bz = (n3 + kRB - 1) / kRB;
-  for (int i = 0; i < sweeps; ++i)
-    hipLaunchKernelGGL(reach_block_kernel, dim3((unsigned)(bx * by * bz)), dim3(256), 0, s, code,
-                       reach, n1, n2, n3, bx, by, changed);
+  if (n >= (1LL << 31)) return hipErrorInvalidValue;  // cell indices are int
+  const dim3 grid(blocks_for(n, 256)), block(256);
+  const int tx = (n1 + kUT - 1) / kUT, ty = (n2 + kUT - 1) / kUT, tz = (n3 + kUT - 1) / kUT;
+  hipLaunchKernelGGL(reach_local_kernel, dim3((unsigned)(tx * ty * tz)), dim3(1024), 0, s, code,
+                     lab, reach, n1, n2, n3, tx, ty);
+  hipLaunchKernelGGL(reach_merge_kernel, grid, block, 0, s, code, lab, n1, n2, n);
+  hipLaunchKernelGGL(reach_seed_kernel, grid, block, 0, s, code, phi, fp64, lab, reach, n);
+  hipLaunchKernelGGL(reach_resolve_kernel, grid, block, 0, s, code, lab, reach, n);
   return hipGetLastError();
 }
 

@@ -109,7 +109,7 @@ struct pf_unet {
   float* count = nullptr;   // number of water cells
   float* cpart = nullptr;   // count partials
   uint8_t* reach = nullptr; // water cells connected to the nucleus
-  int* changed = nullptr;   // reachability sweep flag
+  int* lab = nullptr;       // union-find parents of the reachability labelling
   float* hostbuf = nullptr; // pinned, 32 floats
 };
 
@@ -175,7 +175,7 @@ int ensure_grid(pf_unet* n, int n1, int n2, int n3, int train) {
     n->count = c.take<float>(1);
     n->cpart = c.take<float>(hb);
     n->reach = c.take<uint8_t>(N);
-    n->changed = c.take<int>(1);
+    n->lab = c.take<int>(N);
     if (train) {
       n->gN16a = c.take<uint16_t>(N * 16);
       n->gN16b = c.take<uint16_t>(N * 16);
@@ -412,21 +412,11 @@ int read_loss(pf_unet* n, double* loss) {
 namespace {
 
 // reach = water cells connected through water-water faces to a water cell
-// with phi > 1/2: sweeps in batches of kSweeps until one batch changes
-// nothing (each batch ends with one flag read by the host)
+// with phi > 1/2: a union-find labelling of the water components, four
+// launches on the stream, no host round trip
 int nucleus_reach(pf_unet* n, const uint8_t* code, const void* phi, int fp64) {
-  const long long N = (long long)n->n1 * n->n2 * n->n3;
-  constexpr int kSweeps = 4;  // blocked sweeps between host checks
-  PFU_HIP(n, pfu::launch_reach_seed(code, phi, fp64, n->reach, N, n->stream));
-  int* flag = reinterpret_cast<int*>(n->hostbuf + 16);
-  for (long long done = 0; done <= N; done += kSweeps) {
-    PFU_HIP(n, pfu::launch_reach_sweeps(code, n->reach, n->n1, n->n2, n->n3, kSweeps, n->changed,
-                                        n->stream));
-    PFU_HIP(n, hipMemcpyAsync(flag, n->changed, sizeof(int), hipMemcpyDeviceToHost, n->stream));
-    PFU_HIP(n, hipStreamSynchronize(n->stream));
-    if (*flag == 0) return PF_OK;
-  }
-  return ufail(n, PF_EHIP, "reachability sweeps did not converge");
+  PFU_HIP(n, pfu::launch_reach(code, phi, fp64, n->lab, n->reach, n->n1, n->n2, n->n3, n->stream));
+  return PF_OK;
 }
 
 }  // namespace

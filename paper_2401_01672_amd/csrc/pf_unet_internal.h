@@ -88,10 +88,11 @@ hipError_t launch_bf16_to_f32(const uint16_t* in, float* out, long long n, hipSt
 hipError_t launch_mfma_probe(const float* A, const float* B, float* C, hipStream_t s);
 // out = 1 on the reached cells, 0 elsewhere (FP64 if fp64, else FP32)
 hipError_t launch_flood(const uint8_t* reach, void* out, int fp64, long long n, hipStream_t s);
-hipError_t launch_reach_seed(const uint8_t* code, const void* phi, int fp64, uint8_t* reach,
-                             long long n, hipStream_t s);
-hipError_t launch_reach_sweeps(const uint8_t* code, uint8_t* reach, int n1, int n2, int n3,
-                               int sweeps, int* changed, hipStream_t s);
+// reach = 1 on the water cells whose face-connected water component holds a
+// nucleus cell (water with phi > 1/2), 0 elsewhere; lab: n1 n2 n3 ints of
+// scratch (the union-find parents)
+hipError_t launch_reach(const uint8_t* code, const void* phi, int fp64, int* lab, uint8_t* reach,
+                        int n1, int n2, int n3, hipStream_t s);
 
 }  // namespace pfu
 
