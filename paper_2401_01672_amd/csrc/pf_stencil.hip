@@ -1415,18 +1415,17 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
           CellRHS<R, MODEL, REACT>::eval_nd(m, cc[0].v[k], kCoupled ? cc[1].v[k] : R(0), phn,
                                             thn, code, nd, thD, kp, kt);
         }
-        // pin the cell's results here: otherwise parts of the update are sunk
-        // towards the stores after the quad, where the face masks of all four
-        // cells would be live at once
-        asm volatile("" : "+v"(kp), "+v"(kt));
+        // coupled model: pin the cell's results here; otherwise the heat part
+        // of the update is sunk towards the stores after the quad, where the
+        // face masks of all four cells are live at once (141-146 VGPRs).  The
+        // pin is also a scheduling barrier, which costs the latency-bound
+        // Allen-Cahn passes of small grids far more than it saves.
+        if constexpr (kCoupled) asm volatile("" : "+v"(kp), "+v"(kt));
         kq[0].v[k] = kp;
         kq[1].v[k] = kt;
         // equilibrium measure (no phase-field equation in the Temp model)
         if (STAGE == 1 && MODEL != PF_MODEL_TEMP && !(code & kGlassBit))
           red1 = dmax_nf(red1, fabs(kp));
-        // one cell at a time: the pass is ALU-bound with several waves per
-        // SIMD, and interleaving the cells only raises register pressure
-        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
