@@ -196,45 +196,101 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // Lane group g holds channels cig .. cig + 7 of the chunk at tap
+  // kb * TPB + tg of k-block kb.  Per k-block: the lane's LDS element offset
+  // of its B fragment for N-tile 0, and its weight column (tap * cin +
+  // channel).  With one tap per k-block (TPB = 1) both are a base plus a
+  // compile-time constant; otherwise they differ between lane groups and are
+  // tabulated once.  Taps past 26 (the padding of the last k-block) read tap
+  // 26 and take zero weights.
+  const int cig = (8 * g) % CC, tg = (8 * g) / CC;
+  const int lbase = ((w * kHY) * kHX + r) * PITCH + cig;
+  int lofs[TPB == 1 ? 1 : KB], wcol[TPB == 1 ? 1 : KB];
+  if constexpr (TPB > 1) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int tap = kb * TPB + tg, tc = tap < 27 ? tap : 26;
+      lofs[kb] = lbase + (((tc / 9) * kHY + (tc / 3) % 3) * kHX + tc % 3) * PITCH;
+      wcol[kb] = tc * a.cin + cig;
+    }
+  }
+  auto lds_off = [&](int kb) -> int {
+    if constexpr (TPB == 1) return lbase + (((kb / 9) * kHY + (kb / 3) % 3) * kHX + kb % 3) * PITCH;
+    else return lofs[kb];
+  };
+  auto w_col = [&](int kb) -> int {
+    if constexpr (TPB == 1) return kb * a.cin + cig;
+    else return wcol[kb];
+  };
+  const bool pad_lane = KB * TPB > 27 && (KB - 1) * TPB + tg >= 27;
+  const uint16_t* wrow[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) wrow[m] = a.w + (long long)((mb + m) * 16 + r) * a.kpad;
+
+  // The halo block of a channel chunk (zeros outside the grid).  With chunks
+  // of up to 16 channels (at most 6 slots of 16 bytes per thread) it is
+  // loaded into registers while the previous chunk is computed and stored to
+  // LDS between the two barriers, so the loads' latency overlaps the MFMAs
+  // (48 -> 16 at 96^3: 83 instead of 91 us); wider chunks would hold too
+  // many registers and load it between the barriers.
+  constexpr int G8 = CC / 8;
+  constexpr bool kPipe = CC <= 16;
+  constexpr int NST = kPipe ? (kHalo * G8 + 255) / 256 : 1;  // 16-byte slots per thread
+  uint4 st[NST];
+  auto halo_src = [&](int i, int c, const uint4** src) -> bool {
+    const int c8 = i % G8, hv = i / G8;
+    const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+    const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+    if (x < 0 || x >= a.n1 || y < 0 || y >= a.n2 || z < 0 || z >= a.n3) return false;
+    const long long v = ((long long)z * a.n2 + y) * a.n1 + x;
+    *src = reinterpret_cast<const uint4*>(a.in + v * a.in_stride + a.in_off + c * CC + 8 * c8);
+    return true;
+  };
+  auto stage_load = [&](int c) {
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+      const int i = tid + 256 * j;
+      const uint4* src;
+      st[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (i < kHalo * G8 && halo_src(i, c, &src)) st[j] = *src;
+    }
+  };
   const int nchunks = a.cin / CC;
+  if constexpr (kPipe) stage_load(0);
   for (int c = 0; c < nchunks; ++c) {
-    __syncthreads();
-    // stage the halo block of this channel chunk (zeros outside the grid)
-    constexpr int G8 = CC / 8;
-    for (int i = tid; i < kHalo * G8; i += 256) {
-      const int c8 = i % G8, hv = i / G8;
-      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
-      const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-      uint4 val = make_uint4(0u, 0u, 0u, 0u);
-      if (x >= 0 && x < a.n1 && y >= 0 && y < a.n2 && z >= 0 && z < a.n3) {
-        const long long src = ((long long)z * a.n2 + y) * a.n1 + x;
-        val = *reinterpret_cast<const uint4*>(a.in + src * a.in_stride + a.in_off + c * CC +
-                                              8 * c8);
+    __syncthreads();  // the previous chunk's LDS reads are done
+    if constexpr (kPipe) {
+#pragma unroll
+      for (int j = 0; j < NST; ++j) {
+        const int i = tid + 256 * j;
+        if (i < kHalo * G8)
+          *reinterpret_cast<uint4*>(sx + (i / G8) * PITCH + 8 * (i % G8)) = st[j];
       }
-      *reinterpret_cast<uint4*>(sx + hv * PITCH + 8 * c8) = val;
+    } else {
+      for (int i = tid; i < kHalo * G8; i += 256) {
+        const uint4* src;
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+        if (halo_src(i, c, &src)) val = *src;
+        *reinterpret_cast<uint4*>(sx + (i / G8) * PITCH + 8 * (i % G8)) = val;
+      }
     }
     __syncthreads();
-    const int cig = (8 * g) % CC;   // this lane group's channels within the chunk
-    const int tg = (8 * g) / CC;    // and its tap within the k-block
-#pragma unroll 3
+    if constexpr (kPipe) {
+      if (c + 1 < nchunks) stage_load(c + 1);
+    }
+    // the k-block loop is unrolled: every address below is a per-lane base
+    // plus a constant (or a per-k-block entry of lofs / wcol), so the loop
+    // issues little besides its loads and MFMAs
+#pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      const int tap = kb * TPB + tg;
       bf16x8 bfrag[4];
-      if (tap < 27) {
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // halo offsets 0..2
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int hv = ((w + dz) * kHY + (t + dy)) * kHX + (r + dx);
-          bfrag[t] = *reinterpret_cast<const bf16x8*>(sx + hv * PITCH + cig);
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) bfrag[t] = zero8();
-      }
-      const int kw = (tap < 27 ? tap : 26) * a.cin + c * CC + cig;
+      for (int t = 0; t < 4; ++t)
+        bfrag[t] = *reinterpret_cast<const bf16x8*>(sx + lds_off(kb) + t * kHX * PITCH);
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        const bf16x8 afrag = ld8(a.w + (long long)((mb + m) * 16 + r) * a.kpad + kw);
+        bf16x8 afrag = ld8(wrow[m] + c * CC + w_col(kb));
+        if (kb == KB - 1 && pad_lane) afrag = zero8();
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[m][t] = mfma16(afrag, bfrag[t], acc[m][t]);
       }
