@@ -218,9 +218,10 @@ def kernel_source_hash() -> str:
     return source_hash()
 
 
-def read_traffic(workload: str, kernel: str, src_hash: str):
+def read_traffic(workload: str, kernel: str, src_hash: str, z_chunk=None):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources and (when it records one) at the
+    depth this run's pass uses; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -229,6 +230,8 @@ def read_traffic(workload: str, kernel: str, src_hash: str):
     except Exception:
         return None
     if d.get("source_hash") != src_hash:
+        return None
+    if d.get("z_chunk") is not None and z_chunk is not None and d["z_chunk"] != z_chunk:
         return None
     return d.get("bytes_per_launch")
 
@@ -339,7 +342,9 @@ def run_gpu(args, wl):
     step_ms = sum(ms[:npass]) + ms[5]
     src_hash = kernel_source_hash()
     kname = f"{sched}_pass{dom + 1}"
-    traffic = read_traffic(args.workload, kname, src_hash)
+    zdom = list(cfg.get("stage_z_chunk", []))
+    zdom = zdom[dom] if sched == "five" and len(zdom) == 5 else None
+    traffic = read_traffic(args.workload, kname, src_hash, zdom)
     achieved = per_pass[dom]["gbs"]
     kl = per_pass[dom]["kernel"]
     ksig = (f"{kl.split('<')[0]}<{'float' if prec == 'fp32' else 'double'}, "

@@ -288,6 +288,13 @@ int pf_set_loop(pf_handle* h, int32_t steps_per_poll, int32_t use_graph);
  * representation, streaming mode, schedule and device. */
 int pf_set_tile(pf_handle* h, int32_t z_chunk);
 
+/* Planes per workgroup column of each five-pass stage pass: z[0..4] for
+ * S1..S5 (each >= 1), in the kernel form the handle has; the RHS pass and
+ * the paired schedule follow z[3].  Replaces the autotuner's choice (for
+ * reproducible timings and counter runs).  PF_EINVAL if z is NULL or an
+ * entry is < 1. */
+int pf_set_stage_tiles(pf_handle* h, const int32_t* z);
+
 /* Stencil schedule of one attempt:
  *   0 (default): five passes, one per Merson stage (each fused with its
  *      combinations);

@@ -86,6 +86,7 @@ SIGNATURES = [
                                      C.c_void_p]),
     ("pf_set_loop", C.c_int, [_H, C.c_int32, C.c_int32]),
     ("pf_set_tile", C.c_int, [_H, C.c_int32]),
+    ("pf_set_stage_tiles", C.c_int, [_H, C.POINTER(C.c_int32)]),
     ("pf_set_schedule", C.c_int, [_H, C.c_int32]),
     ("pf_set_pair_tile", C.c_int, [_H, C.c_int32, C.c_int32]),
     ("pf_set_vector", C.c_int, [_H, C.c_int32]),
@@ -346,6 +347,11 @@ class Solver:
 
     def set_tile(self, z_chunk: int):
         self._check(lib().pf_set_tile(self.h, int(z_chunk)))
+
+    def set_stage_tiles(self, z):
+        """Planes per workgroup column of S1..S5 (five ints >= 1)."""
+        arr = (C.c_int32 * 5)(*[int(v) for v in z])
+        self._check(lib().pf_set_stage_tiles(self.h, arr))
 
     def set_schedule(self, schedule: str):
         """'five' (one pass per stage) or 'paired' (S1+S2, S3+S4, S5)."""

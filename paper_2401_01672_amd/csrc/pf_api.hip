@@ -1010,6 +1010,16 @@ int pf_set_tile(pf_handle* h, int32_t z_chunk) {
   return set_tiles(h, z_chunk);
 }
 
+int pf_set_stage_tiles(pf_handle* h, const int32_t* z) {
+  if (!h || !z) return PF_EINVAL;
+  for (int st = 0; st < 5; ++st)
+    if (z[st] < 1) return fail(h, PF_EINVAL, "stage tiles: every depth must be >= 1");
+  h->autotune_pending = 0;
+  int rc = set_tiles(h, z[3]);
+  for (int st = 1; st <= 5 && rc == PF_OK; ++st) rc = set_stage_tiles(h, st, z[st - 1]);
+  return rc;
+}
+
 int pf_integrate(pf_handle* h, double t_end, int64_t max_steps, double eq_tol,
                  pf_run_stats* stats) {
   if (!h) return PF_EINVAL;

@@ -44,7 +44,7 @@ def source_hash(files=STENCIL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def run(workload: str, schedule: str, steps: int):
+def run(workload: str, schedule: str, steps: int, stage_z=None):
     sys.path.insert(0, ROOT)
     import numpy as np
     import torch
@@ -58,6 +58,8 @@ def run(workload: str, schedule: str, steps: int):
     s.set_loop(16, False)
     if schedule != "five":
         s.set_schedule(schedule)  # and the same tile autotuner as the benchmark
+    if stage_z:
+        s.set_stage_tiles(stage_z)  # fixed depths: the counters then match a known config
     s.set_time(0.0, case.run["dt0"])
     st = s.integrate(max_steps=steps)
     print(json.dumps(dict(steps=steps, accepted=st["steps_accepted"], config=s.get_config())),
@@ -103,7 +105,8 @@ def pass_of(name: str, schedule: str):
     return None
 
 
-def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_dir: str):
+def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_dir: str,
+              stage_z=None):
     fetch = _read_counter(fetch_dir, "FETCH_SIZE")
     write = _read_counter(write_dir, "WRITE_SIZE")
     # calibration: the conversion kernel reads CAL_BYTES (largest FETCH among
@@ -121,8 +124,9 @@ def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_
         if not fk or not wk:
             continue
         f_kib, w_kib = fk[len(fk) // 2], wk[len(wk) // 2]  # median dispatch
+        zarg = f" --stage-z {','.join(str(v) for v in stage_z)}" if stage_z else ""
         run_cmd = (f"python3 -m paper_2401_01672_amd.profiling run --workload {workload}"
-                   + (f" --schedule {schedule}" if schedule != "five" else ""))
+                   + (f" --schedule {schedule}" if schedule != "five" else "") + zarg)
         rec = dict(workload=workload, schedule=schedule, kernel=f"{schedule}_pass{p}",
                    commands=[
                        "cd /tmp && export TMPDIR=/tmp && cd /root/repo",
@@ -131,8 +135,9 @@ def summarize(workload: str, schedule: str, fetch_dir: str, write_dir: str, out_
                        f"rocprofv3 --pmc WRITE_SIZE -d {write_dir} -o run --output-format csv "
                        f"-- {run_cmd}",
                        f"python3 -m paper_2401_01672_amd.profiling summarize --workload {workload}"
-                       f" --fetch {fetch_dir} --write {write_dir}"],
+                       f" --fetch {fetch_dir} --write {write_dir}{zarg}"],
                    source_hash=sh, dispatches=len(fk),
+                   z_chunk=(int(stage_z[p - 1]) if stage_z and schedule == "five" else None),
                    fetch_kib_per_dispatch=f_kib, write_kib_per_dispatch=w_kib,
                    fetch_scale=fr, write_scale=wr,
                    bytes_per_launch=f_kib * 1024 * fr + w_kib * 1024 * wr,
@@ -233,6 +238,15 @@ def pmc_summary(title: str, dirs, commands, out: str, match: str = "",
     print(out)
 
 
+def _depths(text: str):
+    if not text:
+        return None
+    z = [int(v) for v in text.split(",")]
+    if len(z) != 5 or min(z) < 1:
+        raise SystemExit("--stage-z takes five depths >= 1 (S1..S5)")
+    return z
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -257,12 +271,14 @@ def main():
     r.add_argument("--workload", default="coupled_256_fp32")
     r.add_argument("--schedule", default="five", choices=["paired", "five"])
     r.add_argument("--steps", type=int, default=64)
+    r.add_argument("--stage-z", default="", help="S1..S5 depths, e.g. 16,16,16,22,22 (default: autotune)")
     s = sub.add_parser("summarize")
     s.add_argument("--workload", default="coupled_256_fp32")
     s.add_argument("--schedule", default="five", choices=["paired", "five"])
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
     s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    s.add_argument("--stage-z", default="", help="the depths the counter runs used")
     a = ap.parse_args()
     if a.cmd == "pmcsum":
         pmc_summary(a.title, a.dirs, a.commands, a.out, a.match,
@@ -273,9 +289,9 @@ def main():
         kernel_stats(a.title, a.trace, a.command, a.out,
                      UNET_SOURCES if a.unet else STENCIL_SOURCES)
     elif a.cmd == "run":
-        run(a.workload, a.schedule, a.steps)
+        run(a.workload, a.schedule, a.steps, _depths(a.stage_z))
     else:
-        summarize(a.workload, a.schedule, a.fetch, a.write, a.out)
+        summarize(a.workload, a.schedule, a.fetch, a.write, a.out, _depths(a.stage_z))
 
 
 if __name__ == "__main__":

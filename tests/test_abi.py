@@ -72,6 +72,7 @@ def test_error_paths_without_gpu():
     assert rc == pf.PF_EINVAL
     assert b"non-NULL" in L.pf_last_error(None) or b"grid" in L.pf_last_error(None)
     assert L.pf_set_loop(None, 16, 1) == pf.PF_EINVAL
+    assert L.pf_set_stage_tiles(None, None) == pf.PF_EINVAL
     assert L.pf_num_cells(None) == -1
     L.pf_destroy(None)
 
