@@ -178,6 +178,16 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
   constexpr int TPB = 32 / CC;  // taps per k-block
   constexpr int KB = (27 + TPB - 1) / TPB;
   __shared__ __align__(16) uint16_t sx[kHalo * PITCH];
+  // One output group and chunks of 16 channels (the 48 -> 16 layer): the
+  // chunk's weights are staged in LDS with the halo (27 taps x 16 rows, pitch
+  // 24 channels), so the A fragments are LDS reads instead of L2 loads waited
+  // on inside the k-block loop (48 -> 16 at 96^3: 75 instead of 83 us; with
+  // 8-channel chunks the extra 20 KiB of LDS costs more occupancy than the
+  // loads: 8 -> 16 took 32 instead of 26 us).
+  constexpr bool kWL = MT == 1 && CC == 16;
+  static_assert(!kWL || TPB > 1, "weights in LDS assume tabulated offsets");
+  constexpr int WP = 24;
+  __shared__ __align__(16) uint16_t sw[kWL ? 27 * 16 * WP : 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, g = lane >> 4, r = lane & 15, w = tid >> 6;
   // XCD-aware order: consecutive tiles of a row stay on one XCD
@@ -211,7 +221,8 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
     for (int kb = 0; kb < KB; ++kb) {
       const int tap = kb * TPB + tg, tc = tap < 27 ? tap : 26;
       lofs[kb] = lbase + (((tc / 9) * kHY + (tc / 3) % 3) * kHX + tc % 3) * PITCH;
-      wcol[kb] = tc * a.cin + cig;
+      // the weights in LDS: row r of tap tc; else the column in memory
+      wcol[kb] = kWL ? (tc * 16 + r) * WP + cig : tc * a.cin + cig;
     }
   }
   auto lds_off = [&](int kb) -> int {
@@ -237,6 +248,8 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
   constexpr bool kPipe = CC <= 16;
   constexpr int NST = kPipe ? (kHalo * G8 + 255) / 256 : 1;  // 16-byte slots per thread
   uint4 st[NST];
+  constexpr int NWS = kWL ? (27 * 16 * G8 + 255) / 256 : 1;    // weight slots per thread
+  uint4 wst[NWS];
   auto halo_src = [&](int i, int c, const uint4** src) -> bool {
     const int c8 = i % G8, hv = i / G8;
     const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
@@ -254,6 +267,18 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
       st[j] = make_uint4(0u, 0u, 0u, 0u);
       if (i < kHalo * G8 && halo_src(i, c, &src)) st[j] = *src;
     }
+    if constexpr (kWL) {
+#pragma clang loop unroll(full)
+      for (int j = 0; j < NWS; ++j) {
+        const int i = tid + 256 * j;  // (tap, row, 8-channel group)
+        wst[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (i < 27 * 16 * G8) {
+          const int c8 = i % G8, row = (i / G8) % 16, tap = i / (16 * G8);
+          wst[j] = *reinterpret_cast<const uint4*>(a.w + (long long)(mb * 16 + row) * a.kpad +
+                                                   tap * a.cin + c * CC + 8 * c8);
+        }
+      }
+    }
   };
   const int nchunks = a.cin / CC;
   if constexpr (kPipe) stage_load(0);
@@ -265,6 +290,14 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
         const int i = tid + 256 * j;
         if (i < kHalo * G8)
           *reinterpret_cast<uint4*>(sx + (i / G8) * PITCH + 8 * (i % G8)) = st[j];
+      }
+      if constexpr (kWL) {
+#pragma clang loop unroll(full)
+        for (int j = 0; j < NWS; ++j) {
+          const int i = tid + 256 * j;
+          if (i < 27 * 16 * G8)
+            *reinterpret_cast<uint4*>(sw + (i / G8) * WP + 8 * (i % G8)) = wst[j];
+        }
       }
     } else {
       for (int i = tid; i < kHalo * G8; i += 256) {
@@ -289,7 +322,9 @@ __global__ __launch_bounds__(256) void conv3_tile_kernel(ConvArgs a, int tiles_x
         bfrag[t] = *reinterpret_cast<const bf16x8*>(sx + lds_off(kb) + t * kHX * PITCH);
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        bf16x8 afrag = ld8(wrow[m] + c * CC + w_col(kb));
+        bf16x8 afrag;
+        if constexpr (kWL) afrag = *reinterpret_cast<const bf16x8*>(sw + w_col(kb));
+        else afrag = ld8(wrow[m] + c * CC + w_col(kb));
         if (kb == KB - 1 && pad_lane) afrag = zero8();
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[m][t] = mfma16(afrag, bfrag[t], acc[m][t]);
