@@ -180,13 +180,16 @@ __host__ __device__ constexpr int tile_pitch() { return CC == 8 ? 24 : CC == 16 
 template <int MT, int CC>
 constexpr int tile_waves() { return MT == 1 && CC == 16 ? 4 : 1; }
 
-template <int MT, int CC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tile_waves<MT, CC>())))
+// TZ: output planes per workgroup, one wavefront each (64 TZ threads).
+template <int MT, int CC, int TZ>
+__global__ __launch_bounds__(64 * TZ) __attribute__((amdgpu_waves_per_eu(tile_waves<MT, CC>())))
 void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
+  constexpr int NTH = 64 * TZ;                   // threads
+  constexpr int HALO = kHX * kHY * (TZ + 2);     // halo voxels
   constexpr int PITCH = tile_pitch<CC>();
   constexpr int TPB = 32 / CC;  // taps per k-block
   constexpr int KB = (27 + TPB - 1) / TPB;
-  __shared__ __align__(16) uint16_t sx[kHalo * PITCH];
+  __shared__ __align__(16) uint16_t sx[HALO * PITCH];
   // One output group and chunks of 16 channels (the 48 -> 16 layer): the
   // chunk's weights are staged in LDS with the halo (27 taps x 16 rows, pitch
   // 24 channels), so the A fragments are LDS reads instead of L2 loads waited
@@ -205,7 +208,7 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   const int q = nblk >> 3, rem = nblk & 7, xcd = b & 7, kk = b >> 3;
   const int tile = (xcd < rem) ? xcd * (q + 1) + kk : rem * (q + 1) + (xcd - rem) * q + kk;
   const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
-  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * TZ;
   (void)tiles_z;
   const int mb = blockIdx.y * MT;  // first 16-channel output group of this workgroup
 
@@ -255,9 +258,9 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   // many registers and load it between the barriers.
   constexpr int G8 = CC / 8;
   constexpr bool kPipe = CC <= 16;
-  constexpr int NST = kPipe ? (kHalo * G8 + 255) / 256 : 1;  // 16-byte slots per thread
+  constexpr int NST = kPipe ? (HALO * G8 + NTH - 1) / NTH : 1;  // 16-byte slots per thread
   uint4 st[NST];
-  constexpr int NWS = kWL ? (27 * 16 * G8 + 255) / 256 : 1;    // weight slots per thread
+  constexpr int NWS = kWL ? (27 * 16 * G8 + NTH - 1) / NTH : 1;  // weight slots per thread
   uint4 wst[NWS];
   auto halo_src = [&](int i, int c, const uint4** src) -> bool {
     const int c8 = i % G8, hv = i / G8;
@@ -271,15 +274,15 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   auto stage_load = [&](int c) {
 #pragma unroll
     for (int j = 0; j < NST; ++j) {
-      const int i = tid + 256 * j;
+      const int i = tid + NTH * j;
       const uint4* src;
       st[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (i < kHalo * G8 && halo_src(i, c, &src)) st[j] = *src;
+      if (i < HALO * G8 && halo_src(i, c, &src)) st[j] = *src;
     }
     if constexpr (kWL) {
 #pragma clang loop unroll(full)
       for (int j = 0; j < NWS; ++j) {
-        const int i = tid + 256 * j;  // (tap, row, 8-channel group)
+        const int i = tid + NTH * j;  // (tap, row, 8-channel group)
         wst[j] = make_uint4(0u, 0u, 0u, 0u);
         if (i < 27 * 16 * G8) {
           const int c8 = i % G8, row = (i / G8) % 16, tap = i / (16 * G8);
@@ -296,20 +299,20 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
     if constexpr (kPipe) {
 #pragma unroll
       for (int j = 0; j < NST; ++j) {
-        const int i = tid + 256 * j;
-        if (i < kHalo * G8)
+        const int i = tid + NTH * j;
+        if (i < HALO * G8)
           *reinterpret_cast<uint4*>(sx + (i / G8) * PITCH + 8 * (i % G8)) = st[j];
       }
       if constexpr (kWL) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < NWS; ++j) {
-          const int i = tid + 256 * j;
+          const int i = tid + NTH * j;
           if (i < 27 * 16 * G8)
             *reinterpret_cast<uint4*>(sw + (i / G8) * WP + 8 * (i % G8)) = wst[j];
         }
       }
     } else {
-      for (int i = tid; i < kHalo * G8; i += 256) {
+      for (int i = tid; i < HALO * G8; i += NTH) {
         const uint4* src;
         uint4 val = make_uint4(0u, 0u, 0u, 0u);
         if (halo_src(i, c, &src)) val = *src;
@@ -1135,12 +1138,24 @@ static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
       }
   }
   const dim3 grid((unsigned)tiles, (unsigned)(groups / mt)), block(256);
+  if constexpr (CC == 16) {
+    if (mt == 1 && tiles >= 2 * kSplitBelow) {
+      // the one-group 16-channel-chunk form on large grids: 8 planes (8
+      // wavefronts) per workgroup, so that the halo and the weights are
+      // staged once for twice the outputs
+      const int tz8 = (a.n3 + 7) / 8;
+      const long long tiles8 = (long long)tx * ty * tz8;
+      hipLaunchKernelGGL((conv3_tile_kernel<1, CC, 8>), dim3((unsigned)tiles8, (unsigned)groups),
+                         dim3(512), 0, s, a, tx, ty, tz8);
+      return hipGetLastError();
+    }
+  }
   switch (mt) {
-    case 1: hipLaunchKernelGGL((conv3_tile_kernel<1, CC>), grid, block, 0, s, a, tx, ty, tz); break;
-    case 2: hipLaunchKernelGGL((conv3_tile_kernel<2, CC>), grid, block, 0, s, a, tx, ty, tz); break;
-    case 3: hipLaunchKernelGGL((conv3_tile_kernel<3, CC>), grid, block, 0, s, a, tx, ty, tz); break;
-    case 4: hipLaunchKernelGGL((conv3_tile_kernel<4, CC>), grid, block, 0, s, a, tx, ty, tz); break;
-    case 6: hipLaunchKernelGGL((conv3_tile_kernel<6, CC>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 1: hipLaunchKernelGGL((conv3_tile_kernel<1, CC, kTZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 2: hipLaunchKernelGGL((conv3_tile_kernel<2, CC, kTZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 3: hipLaunchKernelGGL((conv3_tile_kernel<3, CC, kTZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 4: hipLaunchKernelGGL((conv3_tile_kernel<4, CC, kTZ>), grid, block, 0, s, a, tx, ty, tz); break;
+    case 6: hipLaunchKernelGGL((conv3_tile_kernel<6, CC, kTZ>), grid, block, 0, s, a, tx, ty, tz); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
