@@ -384,13 +384,15 @@ void pf_unet_destroy(pf_unet* net);
 const char* pf_unet_last_error(const pf_unet* net);
 int pf_unet_set_stream(pf_unet* net, uintptr_t stream);
 /* Forward (and data-gradient) convolution kernel of this network:
- * 2 (default): register-blocked where it is faster (16 input channels,
- * cout <= 32, grids of at least 2^16 voxels), else as 1 -- per group of 8
- * input channels the input block and the weights are copied into LDS
+ * 2 (default): register-blocked where it is faster (16 -> 32 channels on
+ * grids of at least 2^16 voxels), else as 1 -- per group of 8 input
+ * channels the input block and the weights are copied into LDS
  * asynchronously (double buffered) and every staged input row feeds all the
  * output rows and planes it reaches;
- * 1: LDS-tiled -- a 16 x 4 x 4 block of output voxels per workgroup with
- * its input halo staged in LDS per chunk of input channels;
+ * 1: LDS-tiled -- a 16 x 4 x 4 block of output voxels per workgroup (16 x 4
+ * x 8 for 16 output channels on large grids) with its input halo (and, for
+ * 16 output channels, the weights) staged in LDS per chunk of input
+ * channels;
  * 0: direct -- every B fragment gathered from memory.  Same products; the
  * FP32 partial sums are taken in another order. */
 int pf_unet_set_conv_kernel(pf_unet* net, int32_t variant);

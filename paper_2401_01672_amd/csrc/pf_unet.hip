@@ -1187,15 +1187,14 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const long long nvox = (long long)a.n1 * a.n2 * a.n3;
   if (nvox == 0) return hipSuccess;
-  if (a.variant == 2 && a.cin == 16) {
-    // register-blocked where it was measured faster: 16 input channels on
-    // grids with enough blocks to fill the chip (at 96^3: 16 -> 16 in 40 us
-    // against 53 us, 16 -> 32 at 48^3 in 15 us against 18 us); with 8 or 48
-    // and more input channels the per-group copy latency of the
-    // register-blocked form costs more than its LDS savings, and the
-    // LDS-tiled form runs
-    if (a.cout == 16 && nvox >= (1LL << 19)) return launch_reg_mt<1, 4, 2>(a, s);
-    if (a.cout <= 32 && nvox >= (1LL << 16)) return launch_reg<2, 2>(a, s);
+  if (a.variant == 2 && a.cin == 16 && a.cout == 32 && nvox >= (1LL << 16)) {
+    // register-blocked where it is measured faster: 16 -> 32 channels on
+    // grids with enough blocks to fill the chip (48^3: 15 us against 18 us).
+    // 16 -> 16 runs faster on the LDS-tiled form since its weights are staged
+    // in LDS and its workgroups own 8 planes (96^3: 36 against 40 us), and
+    // with 8 or 48 and more input channels the per-group copy latency of the
+    // register-blocked form costs more than its LDS savings.
+    return launch_reg<2, 2>(a, s);
   }
   if (a.variant >= 1) {
     if (a.cin % 32 == 0) return launch_tile_cc<32>(a, s);

@@ -22,7 +22,7 @@ struct ConvArgs {
   int out_stride, out_off, cout;
   int relu;
   int n1, n2, n3;
-  int variant;         // 2: register-blocked kernel for 16 input channels on
+  int variant;         // 2: register-blocked kernel for 16 -> 32 channels on
                        // large grids, else as 1; 1: LDS-tiled kernel; 0: direct
                        // kernel (same products, FP32 sums in another order)
 };

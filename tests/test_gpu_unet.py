@@ -170,9 +170,10 @@ def test_forward_exact_routing_network_every_voxel(shape, variant):
 
 
 def test_forward_exact_routing_network_large_grid():
-    """The same on a grid large enough for the 16 x 8 x 8 register blocks of
-    the full-resolution layers (four readouts: the FP64 reference takes
-    seconds per forward pass here)."""
+    """The same on a grid large enough for the full-resolution layers' large
+    forms (16 x 4 x 8 LDS tiles for 16 output channels, the register blocks
+    for 16 -> 32; four readouts: the FP64 reference takes seconds per forward
+    pass here)."""
     _routing_check((84, 80, 80), "reg", (0, 5, 10, 15))
 
 
@@ -326,8 +327,9 @@ def test_errors():
 @pytest.mark.parametrize("cin,cout", [(48, 16), (16, 16), (8, 16), (16, 32)])
 def test_full_size_convolution_sampled(edge, cin, cout):
     """The full-resolution convolutions at the benchmark grids (the largest,
-    48 -> 16 channels, and the other shapes of the register-blocked form);
-    sampled voxels against the direct sum."""
+    48 -> 16 channels, and the other shapes of the large forms: 16 x 4 x 8
+    LDS tiles for 16 output channels, register blocks for 16 -> 32); sampled
+    voxels against the direct sum."""
     rng = np.random.default_rng(edge + cin)
     shape = (edge, edge, edge)
     xb = torch.randint(-16000, 16000, shape + (cin,), dtype=torch.int16, device=DEV)
