@@ -196,10 +196,11 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   // on inside the k-block loop (48 -> 16 at 96^3: 75 instead of 83 us; with
   // 8-channel chunks the extra LDS costs more occupancy than the loads: 8 ->
   // 16 took 32 instead of 26 us).
-  constexpr bool kWL = MT == 1 && CC == 16;
+  constexpr bool kWL = MT <= 2 && CC == 16;
+  constexpr int WR = 16 * MT;  // weight rows staged (the workgroup's output channels)
   static_assert(!kWL || TPB > 1, "weights in LDS assume tabulated offsets");
   constexpr int WP = 16;
-  __shared__ __align__(16) uint16_t sw[kWL ? 27 * 16 * WP : 8];
+  __shared__ __align__(16) uint16_t sw[kWL ? 27 * WR * WP : 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, g = lane >> 4, r = lane & 15, w = tid >> 6;
   // XCD-aware order: consecutive tiles of a row stay on one XCD
@@ -234,7 +235,7 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
       const int tap = kb * TPB + tg, tc = tap < 27 ? tap : 26;
       lofs[kb] = lbase + (((tc / 9) * kHY + (tc / 3) % 3) * kHX + tc % 3) * PITCH;
       // the weights in LDS: row r of tap tc; else the column in memory
-      wcol[kb] = kWL ? (tc * 16 + r) * WP + cig : tc * a.cin + cig;
+      wcol[kb] = kWL ? (tc * WR + r) * WP + cig : tc * a.cin + cig;
     }
   }
   auto lds_off = [&](int kb) -> int {
@@ -260,7 +261,7 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   constexpr bool kPipe = CC <= 16;
   constexpr int NST = kPipe ? (HALO * G8 + NTH - 1) / NTH : 1;  // 16-byte slots per thread
   uint4 st[NST];
-  constexpr int NWS = kWL ? (27 * 16 * G8 + NTH - 1) / NTH : 1;  // weight slots per thread
+  constexpr int NWS = kWL ? (27 * WR * G8 + NTH - 1) / NTH : 1;  // weight slots per thread
   uint4 wst[NWS];
   auto halo_src = [&](int i, int c, const uint4** src) -> bool {
     const int c8 = i % G8, hv = i / G8;
@@ -284,8 +285,8 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
       for (int j = 0; j < NWS; ++j) {
         const int i = tid + NTH * j;  // (tap, row, 8-channel group)
         wst[j] = make_uint4(0u, 0u, 0u, 0u);
-        if (i < 27 * 16 * G8) {
-          const int c8 = i % G8, row = (i / G8) % 16, tap = i / (16 * G8);
+        if (i < 27 * WR * G8) {
+          const int c8 = i % G8, row = (i / G8) % WR, tap = i / (WR * G8);
           wst[j] = *reinterpret_cast<const uint4*>(a.w + (long long)(mb * 16 + row) * a.kpad +
                                                    tap * a.cin + c * CC + 8 * c8);
         }
@@ -307,7 +308,7 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < NWS; ++j) {
           const int i = tid + NTH * j;
-          if (i < 27 * 16 * G8)
+          if (i < 27 * WR * G8)
             *reinterpret_cast<uint4*>(sw + (i / G8) * WP + 8 * (i % G8)) = wst[j];
         }
       }
@@ -335,7 +336,7 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         bf16x8 afrag;
-        if constexpr (kWL) afrag = *reinterpret_cast<const bf16x8*>(sw + w_col(kb));
+        if constexpr (kWL) afrag = *reinterpret_cast<const bf16x8*>(sw + w_col(kb) + m * 16 * WP);
         else afrag = ld8(wrow[m] + c * CC + w_col(kb));
         if (kb == KB - 1 && pad_lane) afrag = zero8();
 #pragma unroll
@@ -1197,7 +1198,7 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
     return launch_reg<2, 2>(a, s);
   }
   if (a.variant >= 1) {
-    if (a.cin % 32 == 0) return launch_tile_cc<32>(a, s);
+    if (a.cin % 32 == 0 && a.cout != 32) return launch_tile_cc<32>(a, s);
     if (a.cin % 16 == 0) return launch_tile_cc<16>(a, s);
     return launch_tile_cc<8>(a, s);
   }
