@@ -1198,7 +1198,10 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
     return launch_reg<2, 2>(a, s);
   }
   if (a.variant >= 1) {
-    if (a.cin % 32 == 0 && a.cout != 32) return launch_tile_cc<32>(a, s);
+    // 16-channel chunks up to 64 output channels: their weights fit in LDS
+    // beside the halo (one or two output groups per workgroup; 64 outputs on
+    // small grids are split into one group per workgroup)
+    if (a.cin % 32 == 0 && a.cout > 64) return launch_tile_cc<32>(a, s);
     if (a.cin % 16 == 0) return launch_tile_cc<16>(a, s);
     return launch_tile_cc<8>(a, s);
   }
