@@ -168,17 +168,18 @@ constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHalo = kHX * kHY * kHZ;
 
-// Row pitch (channels) of a halo voxel in LDS.  16-channel chunks use the
-// unpadded 32-byte row: measured faster than the 48-byte padded one (48 -> 16
-// at 96^3: 69 against 77 us), and the smaller block lets four workgroups
-// share a CU.
+// Row pitch (channels) of a halo voxel in LDS.  8- and 16-channel chunks use
+// the unpadded row: measured faster than the 48-byte padded one (48 -> 16 at
+// 96^3: 69 against 77 us), and the smaller block lets four workgroups share
+// a CU.
 template <int CC>
-__host__ __device__ constexpr int tile_pitch() { return CC == 8 ? 24 : CC == 16 ? 16 : CC + 8; }
+__host__ __device__ constexpr int tile_pitch() { return CC <= 16 ? CC : CC + 8; }
 
-// The one-group 16-channel-chunk form is held to 128 registers (four waves
-// per SIMD; 48 -> 16 at 96^3: 64.5 instead of 68.5 us), no spills.
+// The one-group form with 8- or 16-channel chunks is held to 128 registers
+// (four waves per SIMD; 48 -> 16 at 96^3: 64.5 instead of 68.5 us), no
+// spills.
 template <int MT, int CC>
-constexpr int tile_waves() { return MT == 1 && CC == 16 ? 4 : 1; }
+constexpr int tile_waves() { return MT == 1 && CC <= 16 ? 4 : 1; }
 
 // TZ: output planes per workgroup, one wavefront each (64 TZ threads).
 template <int MT, int CC, int TZ>
@@ -190,16 +191,15 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   constexpr int TPB = 32 / CC;  // taps per k-block
   constexpr int KB = (27 + TPB - 1) / TPB;
   __shared__ __align__(16) uint16_t sx[HALO * PITCH];
-  // One output group and chunks of 16 channels (the 48 -> 16 layer): the
-  // chunk's weights are staged in LDS with the halo (27 taps x 16 rows, pitch
-  // 24 channels), so the A fragments are LDS reads instead of L2 loads waited
-  // on inside the k-block loop (48 -> 16 at 96^3: 75 instead of 83 us; with
-  // 8-channel chunks the extra LDS costs more occupancy than the loads: 8 ->
-  // 16 took 32 instead of 26 us).
-  constexpr bool kWL = MT <= 2 && CC == 16;
+  // One or two output groups and chunks of 8 or 16 channels: the chunk's
+  // weights (27 taps x 16 MT rows, unpadded) are staged in LDS with the halo,
+  // so the A fragments are LDS reads instead of L2 loads waited on inside the
+  // k-block loop (48 -> 16 at 96^3: 75 instead of 83 us; 96 -> 32 at 48^3:
+  // 32 instead of 46.5 us).
+  constexpr bool kWL = MT <= 2 && CC <= 16;
   constexpr int WR = 16 * MT;  // weight rows staged (the workgroup's output channels)
   static_assert(!kWL || TPB > 1, "weights in LDS assume tabulated offsets");
-  constexpr int WP = 16;
+  constexpr int WP = CC;
   __shared__ __align__(16) uint16_t sw[kWL ? 27 * WR * WP : 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, g = lane >> 4, r = lane & 15, w = tid >> 6;
@@ -1139,11 +1139,12 @@ static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
       }
   }
   const dim3 grid((unsigned)tiles, (unsigned)(groups / mt)), block(256);
-  if constexpr (CC == 16) {
+  if constexpr (CC <= 16) {
     if (mt == 1 && tiles >= 2 * kSplitBelow) {
-      // the one-group 16-channel-chunk form on large grids: 8 planes (8
-      // wavefronts) per workgroup, so that the halo and the weights are
-      // staged once for twice the outputs
+      // the one-group form on large grids: 8 planes (8 wavefronts) per
+      // workgroup, so that the halo and the weights are staged once for
+      // twice the outputs (48 -> 16 at 96^3: 58 instead of 64.5 us; 8 -> 16:
+      // 23 instead of 26 us)
       const int tz8 = (a.n3 + 7) / 8;
       const long long tiles8 = (long long)tx * ty * tz8;
       hipLaunchKernelGGL((conv3_tile_kernel<1, CC, 8>), dim3((unsigned)tiles8, (unsigned)groups),
