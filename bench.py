@@ -196,7 +196,8 @@ def run_warmstart(args, probs):
     achieved = fl_dom / (ms[dom] * 1e-3) / 1e12
     roof = dict(bound="mfma", achieved=round(achieved, 1), peak=MFMA_BF16_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), traffic=None,
-                kernel=f"conv3_tile_kernel, convolution {dom} ({layers[dom]['cin']} -> "
+                kernel=f"{'conv3_xfold_kernel' if layers[dom]['cout'] == 16 else 'conv3_tile_kernel'}, "
+                       f"convolution {dom} ({layers[dom]['cin']} -> "
                        f"{layers[dom]['cout']} channels at {edge}^3), BF16 in, FP32 accumulate",
                 algorithmic_flops_per_launch=fl_dom)
     res = W.evaluate(net, probs, args.ws_budget, log=lambda m: print(m, file=sys.stderr))

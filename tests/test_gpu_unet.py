@@ -73,6 +73,28 @@ def test_conv_forward(cin, cout, shape):
         assert np.all(np.abs(got - ex) <= bound), float(np.max(np.abs(got - ex) - bound))
 
 
+@pytest.mark.parametrize("cin,cout", [(48, 16), (16, 16), (8, 16), (16, 32)])
+def test_conv_forward_large_forms_ragged(cin, cout):
+    """A grid large enough for the forms taken on full-resolution grids (the
+    x-folded form for 16 output channels, with 14 outputs per row of 16
+    positions; 8-plane tiles; register blocks for 16 -> 32), ragged in every
+    direction for each of them: every voxel against the exact sum."""
+    shape = (45, 62, 71)
+    rng = np.random.default_rng(cin * 31 + cout)
+    x = U.round_bf16(rng.normal(size=shape + (cin,)))
+    w = rng.normal(0, np.sqrt(2.0 / (27 * cin)), size=(cout, 27, cin)).astype(np.float32)
+    b = rng.normal(0, 0.1, size=cout).astype(np.float32)
+    wb = U.round_bf16(w)
+    ex = U.conv3_cl(x, wb, b.astype(np.float64))
+    bound = conv_bound(x, wb, b.astype(np.float64), ex)
+    for relu in (False, True):
+        y = pf.conv3_bf16(bits_to_dev(x), torch.from_numpy(w).to(DEV),
+                          torch.from_numpy(b).to(DEV), relu, cout)
+        got = dev_to_f64(y)
+        ref = np.maximum(ex, 0.0) if relu else ex
+        assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) - bound))
+
+
 @pytest.mark.parametrize("cin,cout", [(8, 16), (16, 16), (16, 32), (32, 64), (64, 64),
                                       (96, 32), (48, 16), (32, 32)])
 @pytest.mark.parametrize("shape", [(7, 10, 13), (16, 8, 24)])
