@@ -382,7 +382,7 @@ class Solver:
 
 class PFBatchOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("z_chunk", C.c_int32), ("steps_per_poll", C.c_int32),
-                ("pad", C.c_int32)]
+                ("branches", C.c_int32)]
 
 
 BATCH_MODES = {"persistent": 1, "graph": 2}
@@ -390,14 +390,15 @@ BATCH_MODES = {"persistent": 1, "graph": 2}
 
 def batch_integrate(solvers, t_end: float = float("inf"), max_steps: int = 2**62,
                     eq_tol: float = 0.0, raise_on_error: bool = True, mode: str = "graph",
-                    z_chunk: int = 0, steps_per_poll: int = 0):
+                    z_chunk: int = 0, steps_per_poll: int = 0, branches: int = 0):
     """pf_batch_integrate over Solver objects: 'persistent' (one cooperative
     kernel per poll interval) or 'graph' (per-stage launches replayed as a
-    HIP graph).  Returns one stats dict per solver."""
+    HIP graph, in `branches` parallel chains over instance groups; 0 = the
+    library's default).  Returns one stats dict per solver."""
     n = len(solvers)
     hs = (C.c_void_p * n)(*[s.h for s in solvers])
     out = (PFRunStats * n)()
-    opts = PFBatchOptions(BATCH_MODES[mode], int(z_chunk), int(steps_per_poll), 0)
+    opts = PFBatchOptions(BATCH_MODES[mode], int(z_chunk), int(steps_per_poll), int(branches))
     rc = lib().pf_batch_integrate(hs, n, float(t_end), int(max_steps), float(eq_tol), out, 0,
                                   C.byref(opts))
     if rc < 0 and raise_on_error:

@@ -17,6 +17,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "pf_internal.h"
@@ -77,6 +78,10 @@ struct pf_handle {
     DevCtl* hgath = nullptr;  // pinned
     long long cap_items = 0;
     int cap_inst = 0;
+    // side streams and fork/join events of a graph with parallel chains
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
   } bw;
 };
 
@@ -618,6 +623,11 @@ void free_batch_work(pf_handle* h) {
   (void)hipFree(b.bar);
   (void)hipFree(b.gath);
   if (b.hgath) (void)hipHostFree(b.hgath);
+  for (int i = 0; i < 3; ++i) {
+    if (b.side[i]) (void)hipStreamDestroy(b.side[i]);
+    if (b.join[i]) (void)hipEventDestroy(b.join[i]);
+  }
+  if (b.fork) (void)hipEventDestroy(b.fork);
   b = pf_handle::BatchWork();
 }
 
@@ -635,10 +645,17 @@ int batch_work(pf_handle* h, int n, long long nitems) {
       hipMalloc(&b.act, sizeof(int) * ni) != hipSuccess ||
       hipMalloc(&b.bar, 4 * sizeof(unsigned)) != hipSuccess ||
       hipMalloc(&b.gath, sizeof(DevCtl) * ni) != hipSuccess ||
-      hipHostMalloc((void**)&b.hgath, sizeof(DevCtl) * ni, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&b.hgath, sizeof(DevCtl) * ni, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess) {
     free_batch_work(h);
     return PF_ENOMEM;
   }
+  for (int i = 0; i < 3; ++i)
+    if (hipStreamCreateWithFlags(&b.side[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming) != hipSuccess) {
+      free_batch_work(h);
+      return PF_ENOMEM;
+    }
   b.cap_inst = ni;
   b.cap_items = nit;
   return PF_OK;
@@ -1166,8 +1183,9 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   if (!inst || n < 1 || !out) return fail(nullptr, PF_EINVAL, "batch: inst, n >= 1 and out required");
   const int mode = (opts && opts->mode) ? opts->mode : 2;
   if (mode != 1 && mode != 2) return fail(nullptr, PF_EINVAL, "batch: mode must be 1 or 2");
-  if (opts && (opts->z_chunk < 0 || opts->steps_per_poll < 0))
-    return fail(nullptr, PF_EINVAL, "batch: negative option");
+  if (opts && (opts->z_chunk < 0 || opts->steps_per_poll < 0 || opts->branches < 0 ||
+               opts->branches > 4))
+    return fail(nullptr, PF_EINVAL, "batch: negative option or more than 4 branches");
   auto w0 = std::chrono::steady_clock::now();
   for (int i = 0; i < n; ++i) {
     if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
@@ -1196,6 +1214,13 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   const int kBatchZ = 4;
   const long long kMinItems = 1024;
   const int kStepsPerLaunch = (opts && opts->steps_per_poll) ? opts->steps_per_poll : 32;
+  // Parallel chains of the multi-launch form: the running instances are
+  // split into groups of about equal work, and each group's stage launches
+  // form their own chain in the graph (one on the stream, the others on side
+  // streams forked from it and joined back).  A launch of one chain then runs
+  // while another chain is between two of its launches.
+  const bool kBranchesGiven = opts && opts->branches;
+  const int kBranches = kBranchesGiven ? opts->branches : 2;
   std::vector<int> act;
   for (int i = 0; i < n; ++i) {
     pf_handle* h = inst[i];
@@ -1253,7 +1278,6 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     int z = z_fixed ? z_fixed : kBatchZ;
     if (!z_fixed)
       while (z > 1 && batch_items_at(inst, act, z) < kMinItems) z >>= 1;
-    tab = act;
     items.clear();
     for (int i : act) {
       pf_handle* h = inst[i];
@@ -1265,7 +1289,42 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       d.p5 = h->part5;
       d.ntiles = h->nparts;
       d.h3 = h->mc.h3;
-      for (int k = 0; k < h->nparts; ++k) items.push_back(make_int2(i, k));
+    }
+    // groups of about equal work: instances by decreasing tile count, each to
+    // the lightest group so far; the table lists the groups one after another.
+    // By default only while every chain keeps at least kMinChainItems items:
+    // with fewer (the tail of a sweep, a few instances on thinned tiles) one
+    // chain measured faster (48-instance sweep to equilibrium: 6.9 s with two
+    // chains throughout against 6.6 s with one, 6.4 s with this rule).  A
+    // count given in the options is used as given (at most one chain per
+    // instance).
+    long long nitems_all = 0;
+    for (int i : act) nitems_all += inst[i]->nparts;
+    const long long kMinChainItems = 2048;
+    int nb = mode == 2 ? std::min<int>(kBranches, (int)act.size()) : 1;
+    if (!kBranchesGiven)
+      while (nb > 1 && nitems_all < (long long)nb * kMinChainItems) --nb;
+    std::vector<int> order(act);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return inst[a]->nparts > inst[b]->nparts; });
+    std::vector<std::vector<int>> grp(nb);
+    std::vector<long long> load(nb, 0);
+    for (int i : order) {
+      int best = 0;
+      for (int k = 1; k < nb; ++k)
+        if (load[k] < load[best]) best = k;
+      grp[best].push_back(i);
+      load[best] += inst[i]->nparts;
+    }
+    tab.clear();
+    std::vector<int> item_off(nb + 1, 0), inst_off(nb + 1, 0);
+    for (int k = 0; k < nb; ++k) {
+      for (int i : grp[k]) {
+        tab.push_back(i);
+        for (int t = 0; t < inst[i]->nparts; ++t) items.push_back(make_int2(i, t));
+      }
+      item_off[k + 1] = (int)items.size();
+      inst_off[k + 1] = (int)tab.size();
     }
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
@@ -1273,16 +1332,29 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
             hipSuccess ||
         hipMemcpyAsync(ditems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice,
                        s) != hipSuccess ||
-        hipMemcpyAsync(dact, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s) !=
+        hipMemcpyAsync(dact, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return fail(h0, PF_EHIP, "batch: descriptor upload failed");
     if (mode != 2) return PF_OK;
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
-      e = pf::launch_batch_step(h0->P.precision, h0->P.model, h0->smooth, ddesc, ditems,
-                                (int)items.size(), dact, (int)act.size(), lds, s);
+    if (e == hipSuccess && nb > 1) {
+      e = hipEventRecord(h0->bw.fork, s);
+      for (int k = 1; k < nb && e == hipSuccess; ++k)
+        e = hipStreamWaitEvent(h0->bw.side[k - 1], h0->bw.fork, 0);
+    }
+    for (int b = 0; b < nb && e == hipSuccess; ++b) {
+      hipStream_t sb = b == 0 ? s : h0->bw.side[b - 1];
+      for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
+        e = pf::launch_batch_step(h0->P.precision, h0->P.model, h0->smooth, ddesc,
+                                  ditems + item_off[b], item_off[b + 1] - item_off[b],
+                                  dact + inst_off[b], inst_off[b + 1] - inst_off[b], lds, sb);
+    }
+    for (int k = 1; k < nb && e == hipSuccess; ++k) {
+      e = hipEventRecord(h0->bw.join[k - 1], h0->bw.side[k - 1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, h0->bw.join[k - 1], 0);
+    }
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e == hipSuccess && e2 == hipSuccess) {
       e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);

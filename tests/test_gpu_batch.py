@@ -110,6 +110,46 @@ def test_batch_staggered_finish_equals_individual_runs(mode):
         s.close()
 
 
+@pytest.mark.parametrize("branches", [1, 2, 3, 4])
+def test_batch_parallel_chains_equal_individual_runs(branches):
+    """The graph form with its instances split over 1 to 4 parallel chains of
+    stage launches (a count given explicitly is used even on small tables;
+    with 4 chains and 3 instances every chain holds one instance): each
+    instance ends bitwise equal to its own single run, also as the running
+    set shrinks."""
+    insts = small_instances(3 if branches == 4 else 6, "fp32", seed0=3100 + branches)
+    t_end = 0.1
+    n = len(insts)
+    starts = [t_end * i / (n + 1) for i in range(n)]
+    batch = make_solvers(insts, "fp32", 1e-3)
+    single = make_solvers(insts, "fp32", 1e-3)
+    for s, b, t0 in zip(single, batch, starts):
+        s.set_time(t0, 1e-3)
+        b.set_time(t0, 1e-3)
+    stats_b = pf.batch_integrate(batch, t_end=t_end, max_steps=5000, steps_per_poll=6,
+                                 branches=branches)
+    for i, s in enumerate(single):
+        st = s.integrate(t_end=t_end, max_steps=5000)
+        sb = stats_b[i]
+        assert st["status"] == sb["status"] == pf.PF_OK
+        assert (st["steps_accepted"], st["steps_rejected"]) == \
+            (sb["steps_accepted"], sb["steps_rejected"])
+        a, _ = s.get_state()
+        b, _ = batch[i].get_state()
+        assert np.array_equal(a, b), i
+    for s in batch + single:
+        s.close()
+
+
+def test_batch_rejects_too_many_branches():
+    insts = small_instances(2, "fp32", seed0=3200)
+    batch = make_solvers(insts, "fp32", 1e-3)
+    with pytest.raises(pf.PFError):
+        pf.batch_integrate(batch, max_steps=10, branches=5)
+    for s in batch:
+        s.close()
+
+
 def test_batch_fp64_fixed_step_matches_oracle():
     insts = small_instances(5, "fp64", fixed_dt=True, seed0=900)
     # a common fixed step inside Merson's stability interval for every
