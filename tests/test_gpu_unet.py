@@ -345,6 +345,40 @@ def test_errors():
     assert rc == pf.PF_EINVAL
 
 
+def test_convolution_beyond_32bit_offsets_sampled():
+    """A 512^3 grid of 16 channels: the input and the output each span 4 GiB,
+    past the 32-bit byte offsets of the tiled forms, so the launcher takes the
+    direct kernel (64-bit indexing); sampled voxels (the corners among them)
+    against the direct sum."""
+    edge, cin, cout = 512, 16, 16
+    rng = np.random.default_rng(512)
+    shape = (edge, edge, edge)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(512)
+    xb = torch.randint(-16000, 16000, shape + (cin,), dtype=torch.int16, device=DEV, generator=g)
+    xb &= -32641  # sign and low mantissa bits; exponent set below
+    xb |= 123 << 7
+    w = rng.normal(0, 0.05, size=(cout, 27, cin)).astype(np.float32)
+    b = rng.normal(0, 0.1, size=cout).astype(np.float32)
+    y = pf.conv3_bf16(xb, torch.from_numpy(w).to(DEV), torch.from_numpy(b).to(DEV), False, cout)
+    wb = U.round_bf16(w)
+    pts = [(0, 0, 0), (edge - 1, edge - 1, edge - 1), (0, edge - 1, 0), (edge - 1, 0, edge - 1),
+           (edge // 2, edge - 1, 3)] + [tuple(int(v) for v in rng.integers(0, edge, 3))
+                                         for _ in range(60)]
+    for z, yy, x in pts:
+        z0, z1 = max(z - 1, 0), min(z + 2, edge)
+        y0, y1 = max(yy - 1, 0), min(yy + 2, edge)
+        x0, x1 = max(x - 1, 0), min(x + 2, edge)
+        patch = dev_to_f64(xb[z0:z1, y0:y1, x0:x1].contiguous())
+        ref = U.conv3_brute(patch, wb, b.astype(np.float64))[z - z0, yy - y0, x - x0]
+        S = U.conv3_brute(np.abs(patch), np.abs(wb), np.abs(b).astype(np.float64))[
+            z - z0, yy - y0, x - x0]
+        got = dev_to_f64(y[z, yy, x].contiguous())
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 27 * cin * 2.0 ** -24 * S)
+    del xb, y
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("edge", [96, 192])
 @pytest.mark.parametrize("cin,cout", [(48, 16), (16, 16), (8, 16), (16, 32)])
 def test_full_size_convolution_sampled(edge, cin, cout):
