@@ -337,6 +337,68 @@ def test_full_size_coupled_256_fp32_rhs_and_step():
     s.close()
 
 
+def test_max_size_1024_fp32_step_sampled():
+    """1024^3 FP32 coupled (each field 4 GiB, cell byte offsets past 2^32):
+    one fixed step on the vector passes, sampled cells against the FP64
+    oracle run on 13^3 crops around them (a step reaches five cells, so a
+    crop's own faces, outside the domain's, do not reach its centre)."""
+    n = 1024
+    c = pi.case_coupled_256()
+    p = dict(c.params, n1=n, n2=n, n3=n)
+    dev = torch.device("cuda")
+    i = torch.arange(n, device=dev, dtype=torch.int32)
+    z, y, x = i.view(n, 1, 1), i.view(1, n, 1), i.view(1, 1, n)
+    # glass: a lattice of 6^3 blocks (every 7th block along each diagonal)
+    mask_d = (((x // 6 + y // 6 + z // 6) % 7) == 0).to(torch.uint8)
+    # an ice front whose height varies with x1 and x2, about two cells wide
+    def front(xx, yy):
+        return 300.0 + 40.0 * torch.sin(xx * 0.02) + 30.0 * torch.cos(yy * 0.013)
+
+    zf = front(x.float(), y.float())
+    ph = (0.5 * (1.0 - torch.tanh((z.float() - zf) / 2))).to(torch.float32)
+    ph = torch.where(mask_d == 1, torch.zeros((), device=dev), ph).contiguous()
+    th = (-3.0 + 4.0 * z.float() / n).expand(n, n, n).to(torch.float32).contiguous()
+    mask = mask_d.cpu().numpy()
+    s = pf.Solver(p, mask, "fp32", dict(c.run, tol=0.0))
+    s.set_vector(True)
+    s.set_tile(8)
+    s.set_state(ph, th)
+    s.set_time(0.0, 1e-3)
+    s.integrate(max_steps=1)
+    g, gth = s.get_state(device=True)
+    rng = np.random.default_rng(1024)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n - 1, 0, n - 1), (3, n - 1, 5), (n - 1, 512, 0)]
+    fronts = []
+    for _ in range(16):  # on the front
+        xc, yc = (int(v) for v in rng.integers(0, n, 2))
+        zc = int(round(float(zf[0, yc, xc]))) + int(rng.integers(-1, 2))
+        fronts.append((zc, yc, xc))
+    pts += fronts + [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(12)]
+    moved = []
+    for zc, yc, xc in pts:
+        lo = [max(v - 6, 0) for v in (zc, yc, xc)]
+        hi = [min(v + 7, n) for v in (zc, yc, xc)]
+        sl = tuple(slice(a, b) for a, b in zip(lo, hi))
+        pc = dict(p, n1=hi[2] - lo[2], n2=hi[1] - lo[1], n3=hi[0] - lo[0])
+        P = oracle.make_params(pc)
+        phi_c = ph[sl].cpu().numpy().astype(np.float64)
+        T_c = th[sl].cpu().numpy().astype(np.float64) + T_STAR
+        ph_o, T_o, _ = oracle.integrate(P, np.ascontiguousarray(mask[sl]),
+                                        oracle.make_ctl(tol=0.0), 0.0, 1e-3,
+                                        np.ascontiguousarray(phi_c), np.ascontiguousarray(T_c),
+                                        max_steps=1)
+        k = (zc - lo[0], yc - lo[1], xc - lo[2])
+        assert abs(float(g[zc, yc, xc]) - ph_o[k]) <= 1e-5, (zc, yc, xc)
+        assert abs(float(gth[zc, yc, xc]) - (T_o[k] - T_STAR)) <= 1e-5, (zc, yc, xc)
+        if (zc, yc, xc) in fronts:
+            moved.append(abs(ph_o[k] - phi_c[k]))
+    # the step moves the front cells far beyond the bound
+    assert max(moved) > 1e-4, moved
+    s.close()
+    del ph, th, g, gth, mask_d, zf
+    torch.cuda.empty_cache()
+
+
 def test_error_paths_on_gpu():
     c = pi.case_micro_32()
     s = pf.Solver(c.params, c.mask, "fp64", c.run)
