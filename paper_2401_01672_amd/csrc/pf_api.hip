@@ -1339,10 +1339,13 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     if (mode != 2) return PF_OK;
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    int forked = 0;  // side streams that joined the capture
     if (e == hipSuccess && nb > 1) {
       e = hipEventRecord(h0->bw.fork, s);
-      for (int k = 1; k < nb && e == hipSuccess; ++k)
+      for (int k = 1; k < nb && e == hipSuccess; ++k) {
         e = hipStreamWaitEvent(h0->bw.side[k - 1], h0->bw.fork, 0);
+        if (e == hipSuccess) forked = k;
+      }
     }
     for (int b = 0; b < nb && e == hipSuccess; ++b) {
       hipStream_t sb = b == 0 ? s : h0->bw.side[b - 1];
@@ -1351,15 +1354,18 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
                                   ditems + item_off[b], item_off[b + 1] - item_off[b],
                                   dact + inst_off[b], inst_off[b + 1] - inst_off[b], lds, sb);
     }
-    for (int k = 1; k < nb && e == hipSuccess; ++k) {
-      e = hipEventRecord(h0->bw.join[k - 1], h0->bw.side[k - 1]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s, h0->bw.join[k - 1], 0);
+    // every side stream that joined is joined back, also after a failed
+    // launch, so that the capture ends cleanly
+    for (int k = 1; k <= forked; ++k) {
+      hipError_t ej = hipEventRecord(h0->bw.join[k - 1], h0->bw.side[k - 1]);
+      if (ej == hipSuccess) ej = hipStreamWaitEvent(s, h0->bw.join[k - 1], 0);
+      if (e == hipSuccess) e = ej;
     }
-    hipError_t e2 = hipStreamEndCapture(s, &g);
-    if (e == hipSuccess && e2 == hipSuccess) {
-      e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-    }
+    hipGraph_t g_ = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g_);
+    g = g_;
+    if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    if (e2 == hipSuccess && g) (void)hipGraphDestroy(g);
     if (e != hipSuccess || e2 != hipSuccess) {
       gexec = nullptr;
       return fail(h0, PF_EHIP, "batch: graph capture failed");
