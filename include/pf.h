@@ -338,9 +338,11 @@ int pf_get_config(const pf_handle* h, int32_t* out);
  * passes of an attempt run in order with a HIP event between each two (so
  * each pass reads what the previous one has just written, as in a run),
  * reps times after one warm-up; ms[i] receives the mean duration of pass i
- * (S1..S5, or the three passes of the paired schedule) and ms[5] that of the
- * controller (reps back-to-back launches on a scratch control block).  The
- * state, t and dt are left unchanged.  Synchronous. */
+ * (S1..S5, or the three passes of the paired schedule; the last pass
+ * includes the step controller, which runs in its last workgroup, on a
+ * scratch control block) and ms[5] that of the controller alone (reps
+ * back-to-back standalone launches on a scratch control block; runs issue no
+ * such launch).  The state, t and dt are left unchanged.  Synchronous. */
 int pf_time_kernels(pf_handle* h, int32_t reps, double* ms);
 
 /* Block the host until all work issued on the handle's stream is done. */

@@ -47,6 +47,8 @@ struct pf_handle {
   double* part1 = nullptr;
   double* part5 = nullptr;
   double* diag_out = nullptr;
+  unsigned* fold_ctr = nullptr;  // device: S5 partials written (controller folded into S5)
+  unsigned long long* fold_acc = nullptr;  // device: their running maximum
   DevCtl* ctl = nullptr;   // device
   DevCtl* hctl = nullptr;  // pinned host mirror
   int sched = pf::kSchedFive;
@@ -295,12 +297,46 @@ StageArgs s5_paired_args(const pf_handle* h) {
   return a;
 }
 
+int num_passes(const pf_handle* h) { return h->sched == pf::kSchedFive ? 5 : 3; }
+
+// S1 partials the controller reduces: one per S1 workgroup (five passes) or
+// per first-pair workgroup (paired schedule)
+int s1_parts(const pf_handle* h) { return h->sched == pf::kSchedFive ? h->st_np[1] : h->npair; }
+
+// The step controller of a single-instance run runs in S5's last workgroup
+// (no controller launch) on grids of at most kFoldMaxCells cells, whose
+// passes are short enough for the launch to matter.  On large grids the
+// atomic count of the workgroups' maxima, all on one word, and the
+// controller's memory round trips in S5's tail cost more than the launch
+// they save (256^3 FP32: S5 99 -> 110 us for a 4.6 us controller launch
+// saved); on small ones the launch dominates (warm start at 96^3: 80x ->
+// 94x median speed-up).  The batched sweep keeps its controller launch:
+// folded per instance it measured slower over the whole sweep (6.6-6.64 s
+// against 6.4 s).
+constexpr long long kFoldMaxCells = 1LL << 22;
+
+bool fold_ok(const pf_handle* h) { return h->ncell <= kFoldMaxCells; }
+
+// The step controller folded into S5's arguments: the workgroup that writes
+// the last partial runs it on `ctl`.
+void set_fold(const pf_handle* h, StageArgs& a, DevCtl* ctl) {
+  a.fold = 1;
+  a.fold_np1 = s1_parts(h);
+  a.fold_np5 = h->st_np[5];
+  a.fold_p1 = h->part1;
+  a.fold_ctr = h->fold_ctr;
+  a.fold_acc = h->fold_acc;
+  a.fold_ctl = ctl;
+}
+
 // Launch pass i (0-based) of one attempt under the handle's schedule;
-// returns hipErrorInvalidValue past the last pass.
-hipError_t issue_pass(const pf_handle* h, int i, hipStream_t s) {
+// returns hipErrorInvalidValue past the last pass.  fold_ctl: if not null,
+// the last pass (S5) also runs the step controller on it.
+hipError_t issue_pass(const pf_handle* h, int i, hipStream_t s, DevCtl* fold_ctl = nullptr) {
   if (h->sched == pf::kSchedFive) {
     if (i >= 5) return hipErrorInvalidValue;
     StageArgs a = stage_args(h, i + 1);
+    if (i == 4 && fold_ctl) set_fold(h, a, fold_ctl);
     return pf::launch_stage(h->P.precision, h->P.model, i + 1, a, s);
   }
   if (i == 0 || i == 1) {
@@ -309,24 +345,25 @@ hipError_t issue_pass(const pf_handle* h, int i, hipStream_t s) {
   }
   if (i == 2) {
     StageArgs a = s5_paired_args(h);
+    if (fold_ctl) set_fold(h, a, fold_ctl);
     return pf::launch_stage(h->P.precision, h->P.model, 5, a, s);
   }
   return hipErrorInvalidValue;
 }
 
-int num_passes(const pf_handle* h) { return h->sched == pf::kSchedFive ? 5 : 3; }
-
 hipError_t launch_ctl(const pf_handle* h, DevCtl* ctl, hipStream_t s) {
-  const int np1 = h->sched == pf::kSchedFive ? h->st_np[1] : h->npair;
-  return pf::launch_controller(ctl, h->part1, np1, h->part5, h->st_np[5], h->mc.h3, s);
+  return pf::launch_controller(ctl, h->part1, s1_parts(h), h->part5, h->st_np[5], h->mc.h3, s);
 }
 
+// One attempt: the passes and the step controller (in the last pass, or
+// launched after it).
 hipError_t issue_step(const pf_handle* h, hipStream_t s) {
+  const bool fold = fold_ok(h);
   for (int i = 0; i < num_passes(h); ++i) {
-    hipError_t e = issue_pass(h, i, s);
+    hipError_t e = issue_pass(h, i, s, (fold && i == num_passes(h) - 1) ? h->ctl : nullptr);
     if (e != hipSuccess) return e;
   }
-  return launch_ctl(h, h->ctl, s);
+  return fold ? hipSuccess : launch_ctl(h, h->ctl, s);
 }
 
 void drop_graph(pf_handle* h) {
@@ -743,6 +780,7 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
   const size_t part_bytes = (((size_t)h->max_parts * (pf::kPartS1 + pf::kPartS5) + 64) *
                              sizeof(double) + 255) & ~(size_t)255;
   const size_t total = field * 6 * h->nvar + code_bytes + part_bytes + 2 * 256 +  // control block + timing copy
+                       256 +  // counter of the folded controller
                        (h->smooth ? field : 0);
   if (hipMalloc(&h->slab, total) != hipSuccess) return bail(PF_ENOMEM, "hipMalloc of work buffers failed");
   char* p = static_cast<char*>(h->slab);
@@ -761,6 +799,9 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
   p += part_bytes;
   h->ctl = reinterpret_cast<DevCtl*>(p);
   p += 2 * 256;
+  h->fold_ctr = reinterpret_cast<unsigned*>(p);
+  h->fold_acc = reinterpret_cast<unsigned long long*>(p + 128);
+  p += 256;
   if (h->smooth) h->G = p;
   if (hipHostMalloc((void**)&h->hctl, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess)
     return bail(PF_ENOMEM, "hipHostMalloc failed");
@@ -783,6 +824,7 @@ int create_impl(const pf_params* params, const uint8_t* mask, const double* G,
   if (e == hipSuccess)
     e = pf::launch_build_code(dmask, h->code, params->n1, params->n2, params->n3, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->slab, 0, field * 6 * h->nvar, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->fold_ctr, 0, 256, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   (void)hipFree(dmask);
   if (e != hipSuccess) return bail(PF_EHIP, std::string("setup: ") + hipGetErrorString(e));
@@ -1123,9 +1165,9 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
   // The passes of one attempt run in schedule order, an event between each
   // two, repeated reps times (after one warm-up attempt), so every pass reads
   // what its predecessor has just written, as in a run.  The control block is
-  // set to a live attempt but the controller does not run: y[cur] is never
-  // written by a stage kernel, so the state, t and dt are unchanged (the stage
-  // buffers are scratch until the next S1).
+  // set to a live attempt, and the controller that the last pass runs works on
+  // a scratch copy: y[cur] is never written by a stage kernel, so the state, t
+  // and dt are unchanged (the stage buffers are scratch until the next S1).
   DevCtl& c = *h->hctl;
   init_ctl(h, c, INFINITY, 1LL << 62, 0.0);
   int rc = push_ctl(h);
@@ -1136,10 +1178,16 @@ int pf_time_kernels(pf_handle* h, int32_t reps, double* ms) {
   hipEvent_t& e0 = ev[0];
   hipEvent_t& e1 = ev[1];
   for (int i = 0; i < 6; ++i) ms[i] = 0.0;
+  // the last pass runs the folded controller, as in a run, on a scratch copy
+  // of the control block
+  DevCtl cs = c;
+  cs.done = 0;
+  PF_HIP(h, hipMemcpyAsync(h->ctl + 1, &cs, sizeof(DevCtl), hipMemcpyHostToDevice, h->stream));
   for (int r = 0; r <= reps; ++r) {
     PF_HIP(h, hipEventRecord(ev[0], h->stream));
     for (int i = 0; i < np; ++i) {
-      PF_HIP(h, issue_pass(h, i, h->stream));
+      PF_HIP(h, issue_pass(h, i, h->stream,
+                           (i == np - 1 && fold_ok(h)) ? h->ctl + 1 : nullptr));
       PF_HIP(h, hipEventRecord(ev[i + 1], h->stream));
     }
     PF_HIP(h, hipEventSynchronize(ev[np]));
@@ -1318,10 +1366,12 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
     }
     tab.clear();
     std::vector<int> item_off(nb + 1, 0), inst_off(nb + 1, 0);
+    std::vector<int> ctl_launch(nb, 0);  // a chain with instances whose controller is not folded
     for (int k = 0; k < nb; ++k) {
       for (int i : grp[k]) {
         tab.push_back(i);
         for (int t = 0; t < inst[i]->nparts; ++t) items.push_back(make_int2(i, t));
+        if (!desc[i].st[4].fold) ctl_launch[k] = 1;
       }
       item_off[k + 1] = (int)items.size();
       inst_off[k + 1] = (int)tab.size();
@@ -1352,7 +1402,8 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
       for (int k = 0; k < kStepsPerLaunch && e == hipSuccess; ++k)
         e = pf::launch_batch_step(h0->P.precision, h0->P.model, h0->smooth, ddesc,
                                   ditems + item_off[b], item_off[b + 1] - item_off[b],
-                                  dact + inst_off[b], inst_off[b + 1] - inst_off[b], lds, sb);
+                                  dact + inst_off[b], inst_off[b + 1] - inst_off[b],
+                                  ctl_launch[b] != 0, lds, sb);
     }
     // every side stream that joined is joined back, also after a failed
     // launch, so that the capture ends cleanly

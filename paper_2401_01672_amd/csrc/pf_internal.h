@@ -113,6 +113,17 @@ struct StageArgs {
   int vec;               // 1: four x1-cells per thread (needs n1 % 4 == 0)
   int stream_nt;         // 1: non-temporal loads/stores of the streamed fields
   double t_fixed;        // standalone RHS time
+  // S5 only: the step controller folded into the pass (fold = 1): the
+  // fold_np5 workgroup maxima are combined atomically in fold_acc and
+  // counted in fold_ctr (both zero between passes), and the workgroup that
+  // completes the count runs the controller on fold_ctl, with the S1
+  // partials fold_p1 [fold_np1].
+  int fold;
+  int fold_np1, fold_np5;
+  const double* fold_p1;
+  unsigned* fold_ctr;
+  unsigned long long* fold_acc;
+  DevCtl* fold_ctl;
 };
 
 // Arguments of a paired-stage kernel (S1+S2 or S3+S4 in one pass; see
@@ -178,11 +189,12 @@ hipError_t launch_batch(int precision, int model, const BatchDesc* desc, const i
                         unsigned* err, size_t lds, hipStream_t s);
 int batch_max_blocks(int precision, int model, size_t lds);
 // batched sweep, multi-launch form: one attempt = 5 stage launches over the
-// nitems items + 1 controller launch over the ninst instances of inst_list;
+// nitems items (S5 runs the controllers folded into it) + with ctl, one
+// controller launch over the ninst instances of inst_list for the others;
 // smooth: the instances carry the smooth glass field (paper mode)
 hipError_t launch_batch_step(int precision, int model, int smooth, const BatchDesc* desc,
                              const int2* items, int nitems, const int* inst_list, int ninst,
-                             size_t lds, hipStream_t s);
+                             bool ctl, size_t lds, hipStream_t s);
 // control blocks of the instances in inst_list, gathered into out[ninst]
 // (one device-to-host copy per poll instead of one per instance)
 hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ninst,

@@ -403,6 +403,9 @@ struct CellRHSSmooth {
 // ---------------------------------------------------------------------------
 // Stage kernel.  STAGE 0 = standalone RHS (in -> out as k).
 
+// the S5 partial of a workgroup, and the folded step controller (below)
+__device__ void s5_partial(const StageArgs& a, int slot, double v, double* smem);
+
 template <typename R, int MODEL, int STAGE, int REACT = PF_REACT_SIGMA, int SMOOTH = 0>
 __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
   __shared__ double smem[8 * kWaves];
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
     double v[1] = {red0};
     const int ops[1] = {1};
     block_reduce<1>(v, ops, smem);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = v[0];
+    s5_partial(a, blockIdx.x, v[0], smem);
   }
 }
 
@@ -618,8 +621,11 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs a) {
 
 // One block (256 threads) runs the controller of one control block; smem
 // holds 8 * kWaves doubles.  Safe to call repeatedly from a persistent block.
+// With FOLDED the maximum of the S5 partials is eps_in (thread 0's value) and
+// p5 is not read.
+template <bool FOLDED = false>
 __device__ void controller_body(DevCtl* ctl, const double* p1, int np1, const double* p5,
-                                int np5, double h3, double* smem) {
+                                int np5, double h3, double* smem, double eps_in = 0.0) {
   __syncthreads();  // smem reuse across consecutive calls
   if (ctl->done) return;
   // Only the maxima are reduced per attempt: the stage kernels leave the
@@ -628,7 +634,8 @@ __device__ void controller_body(DevCtl* ctl, const double* p1, int np1, const do
   double v[2] = {0.0, 0.0};
   for (int i = threadIdx.x; i < np1; i += blockDim.x)
     v[0] = dmax_nf(v[0], p1[(size_t)i * kPartS1 + 0]);
-  for (int i = threadIdx.x; i < np5; i += blockDim.x) v[1] = dmax_nf(v[1], p5[i]);
+  if constexpr (!FOLDED)
+    for (int i = threadIdx.x; i < np5; i += blockDim.x) v[1] = dmax_nf(v[1], p5[i]);
   const int ops[2] = {1, 1};
   block_reduce<2>(v, ops, smem);
   if (threadIdx.x != 0) return;
@@ -639,7 +646,7 @@ __device__ void controller_body(DevCtl* ctl, const double* p1, int np1, const do
   c.sum_phi = 0.0;
   c.enthalpy = 0.0;
   c.ice = 0.0;
-  const double eps = v[1];
+  const double eps = FOLDED ? eps_in : v[1];
   c.eps = eps;
   c.dt_used = c.dt_att;
   c.accepted = 0;
@@ -704,6 +711,43 @@ __global__ __launch_bounds__(256) void controller_kernel(DevCtl* ctl, const doub
                                                          double h3) {
   __shared__ double smem[8 * kWaves];
   controller_body(ctl, p1, np1, p5, np5, h3, smem);
+}
+
+// The S5 partial of slot `slot` (the workgroup's maximum of the error
+// estimate), written by thread 0; called by every thread of the workgroup.
+// With the controller folded into the pass (a.fold) the partials are instead
+// combined by an agent-scope atomic maximum into one word (as unsigned
+// integers: the partials are non-negative or +Inf, whose bit patterns order
+// like their values), a counter counts them, and the workgroup whose partial
+// completes the count reads and clears the word, clears the counter and runs
+// the controller: the attempt needs no controller launch.  The S1 partials
+// come from an earlier launch and are read plainly.
+__device__ void s5_partial(const StageArgs& a, int slot, double v, double* smem) {
+  if (!a.fold) {
+    if (threadIdx.x == 0) a.part[slot] = v;
+    return;
+  }
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    const unsigned long long old = __hip_atomic_fetch_max(
+        a.fold_acc, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT);
+    // the count moves only once the maximum has been taken
+    asm volatile("" ::"v"(old) : "memory");
+    const unsigned prev =
+        __hip_atomic_fetch_add(a.fold_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev + 1u == (unsigned)a.fold_np5;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  double eps = 0.0;
+  if (threadIdx.x == 0) {
+    eps = __longlong_as_double(
+        (long long)__hip_atomic_load(a.fold_acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    __hip_atomic_store(a.fold_acc, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.fold_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  controller_body<true>(a.fold_ctl, a.fold_p1, a.fold_np1, nullptr, 0, 0.0, smem, eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -810,10 +854,13 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchDesc* de
                                                               it.y, smem, pf_stage_lds);
 }
 
+// The controllers of the listed instances whose controller is not folded
+// into their S5 work items (one workgroup each).
 __global__ __launch_bounds__(256) void batch_ctl_kernel(const BatchDesc* desc,
                                                         const int* inst_list) {
   __shared__ double smem[8 * kWaves];
   const BatchDesc& d = desc[inst_list[blockIdx.x]];
+  if (d.st[4].fold) return;
   controller_body(d.st[0].ctl, d.p1, d.ntiles, d.p5, d.ntiles, d.h3, smem);
 }
 
@@ -838,41 +885,44 @@ hipError_t launch_gather_ctl(const BatchDesc* desc, const int* inst_list, int ni
 
 template <typename R, int MODEL, int SMOOTH>
 static hipError_t launch_batch_step_t(const BatchDesc* desc, const int2* items, int nitems,
-                                      const int* inst_list, int ninst, size_t lds,
+                                      const int* inst_list, int ninst, bool ctl, size_t lds,
                                       hipStream_t s) {
   const dim3 g((unsigned)nitems), b(kBlock);
   hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 1, SMOOTH>), g, b, lds, s, desc, items);
   hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 2, SMOOTH>), g, b, lds, s, desc, items);
   hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 3, SMOOTH>), g, b, lds, s, desc, items);
   hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 4, SMOOTH>), g, b, lds, s, desc, items);
+  // S5 runs the step controller of the instances with few work items in the
+  // last of their items; the others' run in a controller launch
   hipLaunchKernelGGL((batch_stage_kernel<R, MODEL, 5, SMOOTH>), g, b, lds, s, desc, items);
-  hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc, inst_list);
+  if (ctl)
+    hipLaunchKernelGGL(batch_ctl_kernel, dim3((unsigned)ninst), dim3(256), 0, s, desc, inst_list);
   return hipGetLastError();
 }
 
 template <typename R, int SMOOTH>
 static hipError_t launch_batch_step_r(int model, const BatchDesc* desc, const int2* items,
-                                      int nitems, const int* inst_list, int ninst, size_t lds,
-                                      hipStream_t s) {
+                                      int nitems, const int* inst_list, int ninst, bool ctl,
+                                      size_t lds, hipStream_t s) {
   return model == PF_MODEL_AC
              ? launch_batch_step_t<R, PF_MODEL_AC, SMOOTH>(desc, items, nitems, inst_list, ninst,
-                                                          lds, s)
+                                                          ctl, lds, s)
              : launch_batch_step_t<R, PF_MODEL_COUPLED, SMOOTH>(desc, items, nitems, inst_list,
-                                                               ninst, lds, s);
+                                                               ninst, ctl, lds, s);
 }
 
 hipError_t launch_batch_step(int precision, int model, int smooth, const BatchDesc* desc,
                              const int2* items, int nitems, const int* inst_list, int ninst,
-                             size_t lds, hipStream_t s) {
+                             bool ctl, size_t lds, hipStream_t s) {
   if (precision == PF_FP64)
     return smooth ? launch_batch_step_r<double, 1>(model, desc, items, nitems, inst_list, ninst,
-                                                   lds, s)
+                                                   ctl, lds, s)
                   : launch_batch_step_r<double, 0>(model, desc, items, nitems, inst_list, ninst,
-                                                   lds, s);
-  return smooth ? launch_batch_step_r<float, 1>(model, desc, items, nitems, inst_list, ninst, lds,
-                                                s)
-                : launch_batch_step_r<float, 0>(model, desc, items, nitems, inst_list, ninst, lds,
-                                                s);
+                                                   ctl, lds, s);
+  return smooth ? launch_batch_step_r<float, 1>(model, desc, items, nitems, inst_list, ninst, ctl,
+                                                lds, s)
+                : launch_batch_step_r<float, 0>(model, desc, items, nitems, inst_list, ninst, ctl,
+                                                lds, s);
 }
 
 template <typename R, int MODEL>
@@ -1497,7 +1547,7 @@ __device__ __forceinline__ void stage4_tile(const StageArgs& a, const int tile,
     double v[1] = {red0};
     const int ops[1] = {1};
     block_reduce<1>(v, ops, smem);
-    if (threadIdx.x == 0) a.part[slot] = v[0];
+    s5_partial(a, slot, v[0], smem);
     __syncthreads();
   }
 }
