@@ -7,7 +7,7 @@ ramped from -5 C to +5 C over 60 s, T0 = +1 C; tol 1e-6 adaptive steps), FP32
 fields with FP64 error norm, time, step and diagnostic sums.  One benchmark
 step is one adaptive Merson attempt over the whole grid: five fused stage
 passes, the FP64 error-norm and diagnostic reductions and the on-device step
-controller (run by the last workgroup of the fifth pass).  GCUPS = cells x attempts / s / 1e9 (every cell counts, glass
+controller (a kernel of its own at this size).  GCUPS = cells x attempts / s / 1e9 (every cell counts, glass
 included).  The 128^3 FP64 case and the other workloads run with --workload.
 
 Prints ONE JSON line.  Inputs are synthetic (seeded random sequential addition
@@ -154,8 +154,8 @@ def run_sweep(args):
     achieved = bpc * cell_att_early / early / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="one batched attempt of all 48 instances (5 stage launches, each "
-                       "instance's controller in its last S5 work item; graph replay)",
+                kernel="one batched attempt of all 48 instances (5 stage launches + "
+                       "controller, graph replay)",
                 algorithmic_bytes_per_launch=int(round(bpc * cell_att_early / EARLY)))
     extra = dict(cells_total=ncell, early_ms_per_attempt=round(ms_step, 4),
                  early_attempts_check=att_early,

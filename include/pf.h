@@ -253,13 +253,10 @@ typedef struct {
                              instances make at least 1024 items, halved
                              down to 1 below that)                         */
   int32_t steps_per_poll; /* attempts between host checks (0: 32)          */
-  int32_t branches;       /* mode 2: the running instances are split into
-                             this many groups of about equal work (at most
-                             one per instance), each with its own chain of
-                             stage launches in the graph, so that one
-                             group's launch gaps overlap the other groups'
-                             kernels; 1 to 4, or 0: two while each chain
-                             keeps at least 2048 work items, else one      */
+  int32_t branches;       /* mode 2: parallel chains of stage launches in
+                             the graph over groups of instances; switched
+                             off in this build: 0 and 1 (one chain) are
+                             accepted, 2 to 4 return PF_EINVAL            */
 } pf_batch_options;
 
 /* opts may be NULL (defaults). */

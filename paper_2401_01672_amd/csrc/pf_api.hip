@@ -1234,6 +1234,13 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   if (opts && (opts->z_chunk < 0 || opts->steps_per_poll < 0 || opts->branches < 0 ||
                opts->branches > 4))
     return fail(nullptr, PF_EINVAL, "batch: negative option or more than 4 branches");
+  // Parallel chains are switched off: one run with three chains (three
+  // instances, staggered finishing times) ended in a host segmentation fault
+  // inside this call whose cause is not found; the same case had passed five
+  // times before.  Until it is, the graph holds one chain.
+  if (opts && opts->branches > 1)
+    return fail(nullptr, PF_EINVAL,
+                "batch: parallel chains (branches > 1) are switched off in this build");
   auto w0 = std::chrono::steady_clock::now();
   for (int i = 0; i < n; ++i) {
     if (!inst[i]) return fail(nullptr, PF_EINVAL, "batch: NULL handle");
@@ -1268,7 +1275,7 @@ int pf_batch_integrate(pf_handle* const* inst, int32_t n, double t_end, int64_t 
   // streams forked from it and joined back).  A launch of one chain then runs
   // while another chain is between two of its launches.
   const bool kBranchesGiven = opts && opts->branches;
-  const int kBranches = kBranchesGiven ? opts->branches : 2;
+  const int kBranches = 1;
   std::vector<int> act;
   for (int i = 0; i < n; ++i) {
     pf_handle* h = inst[i];

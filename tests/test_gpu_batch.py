@@ -110,7 +110,16 @@ def test_batch_staggered_finish_equals_individual_runs(mode):
         s.close()
 
 
-@pytest.mark.parametrize("branches", [1, 2, 3, 4])
+CHAINS_OFF = ("parallel chains are switched off in the library: one run with three chains "
+              "ended in a host segmentation fault inside pf_batch_integrate whose cause is "
+              "not found")
+
+
+@pytest.mark.parametrize("branches", [
+    1,
+    pytest.param(2, marks=pytest.mark.skip(reason=CHAINS_OFF)),
+    pytest.param(3, marks=pytest.mark.skip(reason=CHAINS_OFF)),
+    pytest.param(4, marks=pytest.mark.skip(reason=CHAINS_OFF))])
 def test_batch_parallel_chains_equal_individual_runs(branches):
     """The graph form with its instances split over 1 to 4 parallel chains of
     stage launches (a count given explicitly is used even on small tables;
@@ -142,10 +151,13 @@ def test_batch_parallel_chains_equal_individual_runs(branches):
 
 
 def test_batch_rejects_too_many_branches():
+    """More than 4 chains is an error; 2 to 4 are refused while parallel
+    chains are switched off (the call returns before any GPU work)."""
     insts = small_instances(2, "fp32", seed0=3200)
     batch = make_solvers(insts, "fp32", 1e-3)
-    with pytest.raises(pf.PFError):
-        pf.batch_integrate(batch, max_steps=10, branches=5)
+    for br in (5, 2, 4):
+        with pytest.raises(pf.PFError):
+            pf.batch_integrate(batch, max_steps=10, branches=br)
     for s in batch:
         s.close()
 
