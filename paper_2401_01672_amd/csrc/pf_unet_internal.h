@@ -55,7 +55,6 @@ struct HeadArgs {
 };
 
 constexpr int kConvMaxTiles = 16;   // (cout / 16) * ceil(cin / 16) for the weight gradient
-constexpr int kWgChunk = 64;        // voxels staged per weight-gradient iteration
 constexpr int kHeadParts = 18;
 
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s);

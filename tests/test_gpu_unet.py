@@ -97,8 +97,10 @@ def test_conv_forward_large_forms_ragged(cin, cout):
 
 @pytest.mark.parametrize("cin,cout", [(8, 16), (16, 16), (16, 32), (32, 64), (64, 64),
                                       (96, 32), (48, 16), (32, 32)])
-@pytest.mark.parametrize("shape", [(7, 10, 13), (16, 8, 24)])
+@pytest.mark.parametrize("shape", [(7, 10, 13), (16, 8, 24), (21, 17, 70)])
 def test_conv_backward(cin, cout, shape):
+    """(21, 17, 70): twelve voxel ranges of the weight gradient, its 32 x 2 x 2
+    blocks ragged in every direction."""
     rng = np.random.default_rng(7 * cin + cout + shape[0])
     x = U.round_bf16(rng.normal(size=shape + (cin,)))
     w = rng.normal(0, np.sqrt(2.0 / (27 * cin)), size=(cout, 27, cin)).astype(np.float32)
