@@ -24,6 +24,7 @@ namespace pfu {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -282,9 +283,9 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   constexpr int G8 = CC / 8;
   constexpr bool kPipe = CC <= 16;
   constexpr int NST = kPipe ? (HALO * G8 + NTH - 1) / NTH : 1;  // 16-byte slots per thread
-  uint4 st[NST];
+  u32x4 st[NST];
   constexpr int NWS = kWL ? (27 * WR * G8 + NTH - 1) / NTH : 1;  // weight slots per thread
-  uint4 wst[NWS];
+  u32x4 wst[NWS];
   auto halo_src = [&](int i, int c, const uint4** src) -> bool {
     const int c8 = i % G8, hv = i / G8;
     const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
@@ -299,8 +300,16 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   // their byte offsets from the input and weight bases (32-bit, checked by
   // the launcher; kNoSlot outside the grid) are computed once here instead
   // of once per chunk, which was most of the kernel's VALU work.  Their LDS
-  // slots are 16 i bytes (unpadded rows: PITCH = WP = CC).
-  constexpr uint32_t kNoSlot = 0xffffffffu;
+  // slots are 16 i bytes (unpadded rows: PITCH = WP = CC).  The loads go
+  // through raw buffer resources, which return zeros at a byte offset at or
+  // beyond the resource's size: kNoSlot is 2^31 (the launcher keeps both
+  // sizes below it), so a slot outside the grid needs no branch or zero fill.
+  constexpr uint32_t kNoSlot = 0x80000000u;
+  const auto rin = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)a.in, 0, (int)(2u * (uint32_t)(a.n1 * a.n2 * a.n3) * (uint32_t)a.in_stride),
+      0x00020000);
+  const auto rwt =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, 2 * a.cout * a.kpad, 0x00020000);
   uint32_t hb[NST], wb[NWS];
   if constexpr (kPipe) {
 #pragma unroll
@@ -330,18 +339,11 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
   auto stage_load = [&](int c) {
     const uint32_t cb = (uint32_t)(2 * CC * c);
 #pragma unroll
-    for (int j = 0; j < NST; ++j) {
-      st[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (hb[j] != kNoSlot)
-        st[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.in) + (hb[j] + cb));
-    }
+    for (int j = 0; j < NST; ++j) st[j] = __builtin_amdgcn_raw_buffer_load_b128(rin, hb[j] + cb, 0, 0);
     if constexpr (kWL) {
 #pragma clang loop unroll(full)
-      for (int j = 0; j < NWS; ++j) {
-        wst[j] = make_uint4(0u, 0u, 0u, 0u);
-        if (wb[j] != kNoSlot)
-          wst[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.w) + (wb[j] + cb));
-      }
+      for (int j = 0; j < NWS; ++j)
+        wst[j] = __builtin_amdgcn_raw_buffer_load_b128(rwt, wb[j] + cb, 0, 0);
     }
   };
   const int nchunks = a.cin / CC;
@@ -353,13 +355,13 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
 #pragma unroll
       for (int j = 0; j < NST; ++j) {
         const int i = tid + NTH * j;
-        if (i < HALO * G8) *reinterpret_cast<uint4*>(sx + 8 * i) = st[j];
+        if (i < HALO * G8) *reinterpret_cast<u32x4*>(sx + 8 * i) = st[j];
       }
       if constexpr (kWL) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < NWS; ++j) {
           const int i = tid + NTH * j;
-          if (i < 27 * WR * G8) *reinterpret_cast<uint4*>(sw + 8 * i) = wst[j];
+          if (i < 27 * WR * G8) *reinterpret_cast<u32x4*>(sw + 8 * i) = wst[j];
         }
       }
     } else {
@@ -441,11 +443,13 @@ void conv3_tile_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z) {
 constexpr int kFX = 16;           // positions per row
 constexpr int kFOut = kFX - 2;    // outputs per row
 
+// (every lane writes and a lane without a source reads zero, so no old value
+// is needed)
 __device__ __forceinline__ float dpp_row_shr1(float v) {  // lane r takes lane r - 1 (row start: 0)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float dpp_row_shl1(float v) {  // lane r takes lane r + 1 (row end: 0)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x101, 0xf, 0xf, true));
 }
 
 template <int TZ>
@@ -455,7 +459,9 @@ void conv3_xfold_kernel(ConvArgs a, int tiles_x, int tiles_y) {
   constexpr int HY = kTY + 2, HZ = TZ + 2;
   constexpr int HALO = kFX * HY * HZ;  // voxels of the staged block
   constexpr int KB = 5;                // k-blocks: 9 (dz, dy) taps x 16 channels, padded to 10
-  constexpr int WSZ = 27 * 16 * CC;    // the chunk's weights, [dx][dz, dy][co][ci]
+  // the chunk's weights, [dx][dz, dy][co][ci], with a tenth (dz, dy) slot of
+  // zeros per dx for the padding tap
+  constexpr int WSZ = 3 * 10 * 16 * CC;
   __shared__ __align__(16) uint16_t sx[HALO * CC];
   __shared__ __align__(16) uint16_t sw[WSZ];
   const int tid = threadIdx.x;
@@ -474,7 +480,7 @@ void conv3_xfold_kernel(ConvArgs a, int tiles_x, int tiles_y) {
     for (int t = 0; t < 4; ++t) acc[d][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   // lane group g: channels 8 (g & 1) .. + 7 of the (dz, dy) tap 2 kb + (g >> 1);
-  // tap 9 (the padding) reads tap 8 and takes zero weights
+  // tap 9 (the padding) reads tap 8 of the input and the zero weight slot
   const int cig = 8 * (g & 1), tg = g >> 1;
   const int lbase = ((w * HY) * kFX + r) * CC + cig;
   const int wbase = r * CC + cig;
@@ -484,13 +490,25 @@ void conv3_xfold_kernel(ConvArgs a, int tiles_x, int tiles_y) {
     const int t0 = 2 * kb < 9 ? 2 * kb : 8, t1 = 2 * kb + 1 < 9 ? 2 * kb + 1 : 8;
     const int h0 = ((t0 / 3) * HY + t0 % 3) * kFX * CC, h1 = ((t1 / 3) * HY + t1 % 3) * kFX * CC;
     lofs[kb] = lbase + (tg ? h1 : h0);
-    wofs[kb] = wbase + (tg ? t1 : t0) * 16 * CC;
+    wofs[kb] = wbase + (tg ? 2 * kb + 1 : t0) * 16 * CC;
   }
-  const bool pad_lane = tg == 1;  // in the last k-block
+  // the zero slots (never overwritten by the staging; visible after the
+  // first chunk's barrier)
+  if (tid < 3 * 16 * CC / 8)
+    *reinterpret_cast<u32x4*>(sw + ((tid / (16 * CC / 8)) * 10 + 9) * 16 * CC +
+                              8 * (tid % (16 * CC / 8))) = u32x4{0u, 0u, 0u, 0u};
 
   // staging slots (the same voxels and weight rows for every chunk; 32-bit
-  // byte offsets, checked by the launcher)
-  constexpr uint32_t kNoSlot = 0xffffffffu;
+  // byte offsets, checked by the launcher).  The loads go through raw buffer
+  // resources over the input and the weights: a load at a byte offset at or
+  // beyond the resource's size returns zeros, so a slot outside the grid is
+  // an offset of 2^31 (the launcher keeps both sizes below it) and needs
+  // neither a branch nor a zero fill.
+  constexpr uint32_t kNoSlot = 0x80000000u;
+  const auto rin = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)a.in, 0, (int)(2u * (uint32_t)(a.n1 * a.n2 * a.n3) * (uint32_t)a.in_stride),
+      0x00020000);
+  const auto rwt = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, 2 * 16 * a.kpad, 0x00020000);
   constexpr int NST = (HALO * G8 + NTH - 1) / NTH;
   constexpr int NWS = (27 * 16 * G8 + NTH - 1) / NTH;
   uint32_t hb[NST], wb[NWS];
@@ -511,23 +529,15 @@ void conv3_xfold_kernel(ConvArgs a, int tiles_x, int tiles_y) {
     const int i = tid + NTH * j;  // (tap, row, 8-channel group), tap = 3 (dz, dy) + dx
     const int c8 = i % G8, row = (i / G8) % 16, tap = i / (16 * G8);
     wb[j] = i < 27 * 16 * G8 ? (uint32_t)(2 * (row * a.kpad + tap * a.cin + 8 * c8)) : kNoSlot;
-    wdst[j] = (((tap % 3) * 9 + tap / 3) * 16 + row) * CC + 8 * c8;
+    wdst[j] = (((tap % 3) * 10 + tap / 3) * 16 + row) * CC + 8 * c8;
   }
-  uint4 st[NST], wst[NWS];
+  u32x4 st[NST], wst[NWS];
   auto stage_load = [&](int c) {
     const uint32_t cb = (uint32_t)(2 * CC * c);
 #pragma unroll
-    for (int j = 0; j < NST; ++j) {
-      st[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (hb[j] != kNoSlot)
-        st[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.in) + (hb[j] + cb));
-    }
+    for (int j = 0; j < NST; ++j) st[j] = __builtin_amdgcn_raw_buffer_load_b128(rin, hb[j] + cb, 0, 0);
 #pragma unroll
-    for (int j = 0; j < NWS; ++j) {
-      wst[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (wb[j] != kNoSlot)
-        wst[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.w) + (wb[j] + cb));
-    }
+    for (int j = 0; j < NWS; ++j) wst[j] = __builtin_amdgcn_raw_buffer_load_b128(rwt, wb[j] + cb, 0, 0);
   };
   const int nchunks = a.cin / CC;
   stage_load(0);
@@ -536,12 +546,12 @@ void conv3_xfold_kernel(ConvArgs a, int tiles_x, int tiles_y) {
 #pragma unroll
     for (int j = 0; j < NST; ++j) {
       const int i = tid + NTH * j;
-      if (i < HALO * G8) *reinterpret_cast<uint4*>(sx + 8 * i) = st[j];
+      if (i < HALO * G8) *reinterpret_cast<u32x4*>(sx + 8 * i) = st[j];
     }
 #pragma unroll
     for (int j = 0; j < NWS; ++j) {
       const int i = tid + NTH * j;
-      if (i < 27 * 16 * G8) *reinterpret_cast<uint4*>(sw + wdst[j]) = wst[j];
+      if (i < 27 * 16 * G8) *reinterpret_cast<u32x4*>(sw + wdst[j]) = wst[j];
     }
     __syncthreads();
     if (c + 1 < nchunks) stage_load(c + 1);
@@ -553,8 +563,7 @@ void conv3_xfold_kernel(ConvArgs a, int tiles_x, int tiles_y) {
         bfrag[t] = *reinterpret_cast<const bf16x8*>(sx + lofs[kb] + t * kFX * CC);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        bf16x8 afrag = *reinterpret_cast<const bf16x8*>(sw + d * 9 * 16 * CC + wofs[kb]);
-        if (kb == KB - 1 && pad_lane) afrag = zero8();
+        const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(sw + d * 10 * 16 * CC + wofs[kb]);
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[d][t] = mfma16(afrag, bfrag[t], acc[d][t]);
       }
@@ -1539,7 +1548,9 @@ static hipError_t launch_tile_cc(const ConvArgs& a, hipStream_t s) {
       const long long ftiles = (long long)fx * ty * fz;
       const long long nv = (long long)a.n1 * a.n2 * a.n3;
       const bool out32 = 2 * (nv * a.out_stride + a.out_off) < 0xffffffffLL;
-      if (ftiles >= 2 * kSplitBelow && ftiles < (1LL << 31) && out32) {
+      // its staging loads mark slots outside the grid with offset 2^31
+      const bool in31 = 2 * nv * a.in_stride < (1LL << 31) && 2LL * 16 * a.kpad < (1LL << 31);
+      if (ftiles >= 2 * kSplitBelow && ftiles < (1LL << 31) && out32 && in31) {
         hipLaunchKernelGGL((conv3_xfold_kernel<8>), dim3((unsigned)ftiles), dim3(512), 0, s, a,
                            fx, ty);
         return hipGetLastError();
@@ -1605,9 +1616,10 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t s) {
     // register-blocked form costs more than its LDS savings.
     return launch_reg<2, 2>(a, s);
   }
-  // the tiled form addresses its staging slots by 32-bit byte offsets
+  // the tiled form addresses its staging slots by 32-bit byte offsets and
+  // marks slots outside the grid with offset 2^31
   const bool off32 = 2 * (nvox * a.in_stride + a.in_off) < 0xffffffffLL &&
-                     2LL * a.cout * a.kpad < 0xffffffffLL;
+                     2 * nvox * a.in_stride < (1LL << 31) && 2LL * a.cout * a.kpad < (1LL << 31);
   if (a.variant >= 1 && off32) {
     // 16-channel chunks up to 64 output channels: their weights fit in LDS
     // beside the halo (one or two output groups per workgroup; 64 outputs on
