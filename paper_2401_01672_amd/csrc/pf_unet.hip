@@ -1157,6 +1157,33 @@ __global__ void up_fwd8_kernel(const uint16_t* in, int in_stride, int in_off, ui
       ld16(in + (size_t)p * in_stride + in_off + 8 * g);
 }
 
+// The decoder's input at one level: nearest 2x upsampling of the coarser
+// path (cu channels) and the skip tensor of this level (cs channels),
+// concatenated per voxel into out (stride cu + cs).  One thread per 8
+// channels of a voxel, so consecutive threads write each voxel's whole row:
+// the skip half is not written on its own as a strided partial row (on grids
+// past the last-level cache those partial lines cost a read-modify-write
+// each).
+__global__ void up_cat8_kernel(const uint16_t* up, int up_stride, const uint16_t* skip,
+                               int skip_stride, uint16_t* out, int cu8, int cs8, int n1, int n2,
+                               unsigned total) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const unsigned c8 = (unsigned)(cu8 + cs8);
+  const unsigned v = i / c8, g = i - v * c8;
+  uint4 q;
+  if (g < (unsigned)cu8) {
+    const unsigned x = v % (unsigned)n1, t = v / (unsigned)n1;
+    const unsigned y = t % (unsigned)n2, z = t / (unsigned)n2;
+    const unsigned p =
+        ((z >> 1) * ((unsigned)n2 >> 1) + (y >> 1)) * ((unsigned)n1 >> 1) + (x >> 1);
+    q = ld16(up + (size_t)p * up_stride + 8 * g);
+  } else {
+    q = ld16(skip + (size_t)v * skip_stride + 8 * (g - (unsigned)cu8));
+  }
+  *reinterpret_cast<uint4*>(out + (size_t)v * (8 * c8) + 8 * g) = q;
+}
+
 // nearest 2x upsampling (output grid n = 2 m)
 __global__ void up_fwd_kernel(const uint16_t* in, int in_stride, int in_off, uint16_t* out,
                               int out_stride, int out_off, int c, int n1, int n2, int n3) {
@@ -1727,6 +1754,21 @@ hipError_t launch_pool_bwd(const View& dout, const View& din, int c, int n1, int
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(pool_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dout.p,
                      dout.stride, dout.off, din.p, din.stride, din.off, c, n1, n2, n3, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_up_cat(const View& up, const View& skip, const View& out, int cu, int cs,
+                         int n1, int n2, int n3, hipStream_t s) {
+  const long long nv = (long long)n1 * n2 * n3;
+  if (nv == 0) return hipSuccess;
+  const long long total = nv * ((cu + cs) / 8);
+  if (cu % 8 || cs % 8 || up.off || skip.off || out.off || up.stride % 8 ||
+      skip.stride % 8 || out.stride != cu + cs || n1 % 2 || n2 % 2 || n3 % 2 ||
+      total >= (1LL << 32))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(up_cat8_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, up.p,
+                     up.stride, skip.p, skip.stride, out.p, cu / 8, cs / 8, n1, n2,
+                     (unsigned)total);
   return hipGetLastError();
 }
 

@@ -101,6 +101,7 @@ struct pf_unet {
   int n1 = 0, n2 = 0, n3 = 0, train = 0;
   void* slab = nullptr;
   uint16_t *X0, *A1, *C1, *E1, *F1, *P1, *A2, *C2, *E2, *F2, *P2, *A3, *B3;
+  uint16_t *S1, *S2;  // skip tensors (layers 1 and 3), copied into C1 / C2 with the upsampling
   uint16_t *gN16a, *gN16b, *gC1, *gP1, *gM32a, *gM32b, *gC2, *gQ32, *gQ64a, *gQ64b;
   float* wpart = nullptr;   // weight-gradient partials
   float* bpart = nullptr;   // bias-gradient partials
@@ -161,11 +162,13 @@ int ensure_grid(pf_unet* n, int n1, int n2, int n3, int train) {
     n->X0 = c.take<uint16_t>(N * kInChannels);
     n->A1 = c.take<uint16_t>(N * 16);
     n->C1 = c.take<uint16_t>(N * 48);
+    n->S1 = c.take<uint16_t>(N * 16);
     n->E1 = c.take<uint16_t>(N * 16);
     n->F1 = c.take<uint16_t>(N * 16);
     n->P1 = c.take<uint16_t>(M * 16);
     n->A2 = c.take<uint16_t>(M * 32);
     n->C2 = c.take<uint16_t>(M * 96);
+    n->S2 = c.take<uint16_t>(M * 32);
     n->E2 = c.take<uint16_t>(M * 32);
     n->F2 = c.take<uint16_t>(M * 32);
     n->P2 = c.take<uint16_t>(Q * 32);
@@ -317,18 +320,20 @@ int run_net(pf_unet* n, const uint8_t* glass, int from_code, double dT, double l
                                s));
   // encoder
   PFU_TRY(conv(n, 0, V(n->X0, 8, 0), V(n->A1, 16, 0), N1, N2, N3));
-  PFU_TRY(conv(n, 1, V(n->A1, 16, 0), V(n->C1, 48, 32), N1, N2, N3));
-  PFU_HIP(n, pfu::launch_pool_fwd(V(n->C1, 48, 32), V(n->P1, 16, 0), 16, M1, M2, M3, s));
+  PFU_TRY(conv(n, 1, V(n->A1, 16, 0), V(n->S1, 16, 0), N1, N2, N3));
+  PFU_HIP(n, pfu::launch_pool_fwd(V(n->S1, 16, 0), V(n->P1, 16, 0), 16, M1, M2, M3, s));
   PFU_TRY(conv(n, 2, V(n->P1, 16, 0), V(n->A2, 32, 0), M1, M2, M3));
-  PFU_TRY(conv(n, 3, V(n->A2, 32, 0), V(n->C2, 96, 64), M1, M2, M3));
-  PFU_HIP(n, pfu::launch_pool_fwd(V(n->C2, 96, 64), V(n->P2, 32, 0), 32, Q1, Q2, Q3, s));
+  PFU_TRY(conv(n, 3, V(n->A2, 32, 0), V(n->S2, 32, 0), M1, M2, M3));
+  PFU_HIP(n, pfu::launch_pool_fwd(V(n->S2, 32, 0), V(n->P2, 32, 0), 32, Q1, Q2, Q3, s));
   PFU_TRY(conv(n, 4, V(n->P2, 32, 0), V(n->A3, 64, 0), Q1, Q2, Q3));
   PFU_TRY(conv(n, 5, V(n->A3, 64, 0), V(n->B3, 64, 0), Q1, Q2, Q3));
   // decoder
-  PFU_HIP(n, pfu::launch_up_fwd(V(n->B3, 64, 0), V(n->C2, 96, 0), 64, M1, M2, M3, s));
+  PFU_HIP(n, pfu::launch_up_cat(V(n->B3, 64, 0), V(n->S2, 32, 0), V(n->C2, 96, 0), 64, 32, M1, M2,
+                                M3, s));
   PFU_TRY(conv(n, 6, V(n->C2, 96, 0), V(n->E2, 32, 0), M1, M2, M3));
   PFU_TRY(conv(n, 7, V(n->E2, 32, 0), V(n->F2, 32, 0), M1, M2, M3));
-  PFU_HIP(n, pfu::launch_up_fwd(V(n->F2, 32, 0), V(n->C1, 48, 0), 32, N1, N2, N3, s));
+  PFU_HIP(n, pfu::launch_up_cat(V(n->F2, 32, 0), V(n->S1, 16, 0), V(n->C1, 48, 0), 32, 16, N1, N2,
+                                N3, s));
   PFU_TRY(conv(n, 8, V(n->C1, 48, 0), V(n->E1, 16, 0), N1, N2, N3));
   PFU_TRY(conv(n, 9, V(n->E1, 16, 0), V(n->F1, 16, 0), N1, N2, N3));
   HeadArgs h;
@@ -377,12 +382,12 @@ int run_net(pf_unet* n, const uint8_t* glass, int from_code, double dT, double l
   // pooling adds into the skip gradient of level 2
   PFU_HIP(n, pfu::launch_pool_bwd(V(n->gQ32, 32, 0), V(n->gC2, 96, 64), 32, M1, M2, M3, 1, s));
   const View dx3 = V(n->gM32a, 32, 0);
-  PFU_TRY(conv_bwd(n, 3, V(n->gC2, 96, 64), V(n->C2, 96, 64), V(n->A2, 32, 0), &dx3, M1, M2, M3));
+  PFU_TRY(conv_bwd(n, 3, V(n->gC2, 96, 64), V(n->S2, 32, 0), V(n->A2, 32, 0), &dx3, M1, M2, M3));
   const View dx2 = V(n->gP1, 16, 0);
   PFU_TRY(conv_bwd(n, 2, V(n->gM32a, 32, 0), V(n->A2, 32, 0), V(n->P1, 16, 0), &dx2, M1, M2, M3));
   PFU_HIP(n, pfu::launch_pool_bwd(V(n->gP1, 16, 0), V(n->gC1, 48, 32), 16, N1, N2, N3, 1, s));
   const View dx1 = V(n->gN16a, 16, 0);
-  PFU_TRY(conv_bwd(n, 1, V(n->gC1, 48, 32), V(n->C1, 48, 32), V(n->A1, 16, 0), &dx1, N1, N2, N3));
+  PFU_TRY(conv_bwd(n, 1, V(n->gC1, 48, 32), V(n->S1, 16, 0), V(n->A1, 16, 0), &dx1, N1, N2, N3));
   PFU_TRY(conv_bwd(n, 0, V(n->gN16a, 16, 0), V(n->A1, 16, 0), V(n->X0, 8, 0), nullptr, N1, N2,
                    N3));
   return PF_OK;
@@ -659,9 +664,9 @@ int pf_unet_time_layers(pf_unet* n, int32_t n1, int32_t n2, int32_t n3, int32_t 
   };
   const Item items[kNumLayers] = {
       {0, V(n->X0, 8, 0), V(n->A1, 16, 0), N1, N2, N3},
-      {1, V(n->A1, 16, 0), V(n->C1, 48, 32), N1, N2, N3},
+      {1, V(n->A1, 16, 0), V(n->S1, 16, 0), N1, N2, N3},
       {2, V(n->P1, 16, 0), V(n->A2, 32, 0), N1 / 2, N2 / 2, N3 / 2},
-      {3, V(n->A2, 32, 0), V(n->C2, 96, 64), N1 / 2, N2 / 2, N3 / 2},
+      {3, V(n->A2, 32, 0), V(n->S2, 32, 0), N1 / 2, N2 / 2, N3 / 2},
       {4, V(n->P2, 32, 0), V(n->A3, 64, 0), N1 / 4, N2 / 4, N3 / 4},
       {5, V(n->A3, 64, 0), V(n->B3, 64, 0), N1 / 4, N2 / 4, N3 / 4},
       {6, V(n->C2, 96, 0), V(n->E2, 32, 0), N1 / 2, N2 / 2, N3 / 2},

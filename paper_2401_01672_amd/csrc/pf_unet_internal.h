@@ -67,6 +67,10 @@ hipError_t launch_pool_fwd(const View& in, const View& out, int c, int m1, int m
                            hipStream_t s);
 hipError_t launch_pool_bwd(const View& dout, const View& din, int c, int n1, int n2, int n3,
                            int accumulate, hipStream_t s);
+// [nearest 2x upsampling of up (cu channels) | skip (cs channels)] per voxel
+// into out (stride cu + cs); views without offsets, cu and cs multiples of 8
+hipError_t launch_up_cat(const View& up, const View& skip, const View& out, int cu, int cs,
+                         int n1, int n2, int n3, hipStream_t s);
 hipError_t launch_up_fwd(const View& in, const View& out, int c, int n1, int n2, int n3,
                          hipStream_t s);
 hipError_t launch_up_bwd(const View& dout, const View& din, int c, int m1, int m2, int m3,
